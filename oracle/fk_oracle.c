@@ -1,0 +1,465 @@
+/*
+ * fk_oracle.c -- plain CPU oracle for the fused preprocessing chain.
+ *
+ * TEST INFRASTRUCTURE ONLY.  The test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark load this library; the GPU library never
+ * includes, links or calls anything here, and this file includes nothing of
+ * the GPU library.
+ *
+ * What it computes.  Fusion changes where intermediates live, not what is
+ * computed (Section II: the fused kernel performs exactly the operations of
+ * the separate kernels, keeping intermediates in registers instead of
+ * DRAM).  So the oracle is the plain definition: each operation of the chain
+ * runs UNFUSED, as one full pass over the whole image, and every
+ * intermediate is stored as fp32 -- the separate-kernel pipeline of the
+ * kernel-call algorithm and of the vertical-fusion figure (part A), whose
+ * intermediate images are float buffers (Section VI-L names crop_32F and the
+ * resized buffer).
+ *
+ * Next to the fp32 result it carries, per element, an fp64 shadow of the
+ * same operation sequence (no intermediate rounding) and the largest
+ * magnitude the element took along the chain; tests use both to bound
+ * rounding error.
+ *
+ * Readings where the paper is silent (each is listed in the design notes):
+ *  - Resize (Sections VI-F, VI-J name "Resize" only): bilinear, half-pixel
+ *    centres, no antialiasing, taps clamped to the crop; source coordinate
+ *    sx = max(fma(ox + 0.5, w / OW, -0.5), 0) in fp32, x0 = floor(sx),
+ *    x1 = min(x0 + 1, w - 1), ax = sx - x0; two horizontal lerps and one
+ *    vertical lerp, each written as fma(a, p1 - p0, p0); the result stays
+ *    fp32 (not re-quantised).
+ *  - Values: u8 and fp16 sources convert to fp32 exactly, and every
+ *    arithmetic op runs in fp32, so the running value is held as fp32 from
+ *    the read onwards; "cvt" is then numerically the identity.
+ *  - Swap (ColorConvert BGR->RGB): exchanges channels 0 and 2; channel 3 is
+ *    kept; a no-op for one channel.  Per-channel constants index channels by
+ *    their position after earlier swaps.
+ *  - Mul/Add/Sub/Div: one IEEE fp32 operation each (round to nearest even),
+ *    no contraction; Div is a true division.
+ *  - Write: packed out[(y*W + x)*C + c] or planar out[(c*H + y)*W + x];
+ *    fp16 outputs round to nearest even.
+ *
+ * Build: gcc -O2 -std=c11 -fno-fast-math -ffp-contract=off -shared -fPIC.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { ORC_U8 = 0, ORC_F16 = 1, ORC_F32 = 2 };
+enum { ORC_READ_PLAIN = 0, ORC_READ_CROP_RESIZE = 1 };
+enum { ORC_SWAP = 0, ORC_CVT = 1, ORC_MUL = 2, ORC_ADD = 3, ORC_SUB = 4, ORC_DIV = 5 };
+enum { ORC_PACKED = 0, ORC_PLANAR = 1 };
+
+enum {
+    ORC_OK = 0,
+    ORC_EINVAL = -1,
+    ORC_ENOMEM = -3,
+};
+
+typedef struct {
+    int32_t kind;
+    int32_t nconst; /* 0, 1 (scalar) or C (one per channel) */
+    float k[4];
+} orc_op;
+
+typedef struct {
+    int32_t read_kind;
+    int32_t in_dtype;
+    int32_t channels;
+    const orc_op *ops;
+    int32_t n_ops;
+    int32_t out_dtype; /* ORC_F32 or ORC_F16 */
+    int32_t layout;    /* ORC_PACKED or ORC_PLANAR */
+} orc_chain;
+
+typedef struct {
+    const void *src;     /* packed HWC frame, host memory */
+    int32_t W, H;        /* frame size in pixels */
+    int64_t pitch;       /* bytes between frame rows */
+    int32_t x, y, w, h;  /* region of interest */
+    int32_t ow, oh;      /* output size (crop+resize); plain read uses w, h */
+    void *dst;           /* output image in the chain's output dtype/layout */
+    double *v64;         /* optional: fp64 shadow, same layout as dst */
+    float *smax;         /* optional: largest |value| along the chain */
+} orc_item;
+
+/* ---------------------------------------------------------------- fp16 -- */
+
+/* IEEE binary16 -> binary32; exact for every input. */
+float orc_half_to_float(uint16_t h)
+{
+    uint32_t sign = (uint32_t)(h >> 15) & 1u;
+    int32_t exp = (h >> 10) & 0x1f;
+    uint32_t man = h & 0x3ffu;
+    float mag;
+    if (exp == 0) {
+        mag = ldexpf((float)man, -24); /* subnormal (or zero) */
+    } else if (exp == 31) {
+        mag = man ? NAN : INFINITY;
+    } else {
+        mag = ldexpf((float)(man | 0x400u), exp - 25);
+    }
+    return sign ? -mag : mag;
+}
+
+/* binary32 -> binary16, round to nearest, ties to even. */
+uint16_t orc_float_to_half(float f)
+{
+    uint32_t bits;
+    memcpy(&bits, &f, sizeof bits);
+    uint16_t sign = (uint16_t)((bits >> 16) & 0x8000u);
+    if (isnan(f))
+        return (uint16_t)(sign | 0x7e00u);
+    double a = fabs((double)f);
+    if (a >= 65520.0) /* halfway between 65504 and 2^16 rounds to inf */
+        return (uint16_t)(sign | 0x7c00u);
+    /* Scale so the binary16 unit in the last place becomes 1, then round to
+     * an integer with ties to even (nearbyint in the default mode). */
+    int e;
+    frexp(a, &e); /* a = m * 2^e, m in [0.5, 1) */
+    int ulp_exp = e - 11;  /* normal numbers: 11 significant bits */
+    if (ulp_exp < -24)
+        ulp_exp = -24;     /* subnormal spacing */
+    double q = nearbyint(ldexp(a, -ulp_exp)); /* exact scaling, RNE */
+    double r = ldexp(q, ulp_exp);
+    if (r >= 65520.0)
+        return (uint16_t)(sign | 0x7c00u);
+    if (r == 0.0)
+        return sign;
+    /* Re-encode r, which is exactly representable in binary16. */
+    int re;
+    double rm = frexp(r, &re); /* r = rm * 2^re */
+    int biased = re - 1 + 15;
+    uint16_t out;
+    if (biased <= 0) {
+        out = (uint16_t)ldexp(r, 24); /* subnormal: multiple of 2^-24 */
+    } else {
+        uint16_t mant = (uint16_t)(ldexp(rm, 11) - 1024.0);
+        out = (uint16_t)((biased << 10) | mant);
+    }
+    return (uint16_t)(sign | out);
+}
+
+/* ----------------------------------------------------------- elements -- */
+
+static size_t dtype_size(int32_t dt)
+{
+    return dt == ORC_U8 ? 1u : dt == ORC_F16 ? 2u : 4u;
+}
+
+/* Element (x, y, c) of a packed HWC frame, converted to fp32 (exact). */
+static float frame_elem(const orc_item *it, int32_t dt, int32_t C, int32_t x, int32_t y,
+                        int32_t c)
+{
+    const uint8_t *row = (const uint8_t *)it->src + (int64_t)y * it->pitch;
+    size_t idx = (size_t)x * (size_t)C + (size_t)c;
+    if (dt == ORC_U8)
+        return (float)row[idx];
+    if (dt == ORC_F16) {
+        uint16_t h;
+        memcpy(&h, row + idx * 2, 2);
+        return orc_half_to_float(h);
+    }
+    float v;
+    memcpy(&v, row + idx * 4, 4);
+    return v;
+}
+
+/* One intermediate image: packed HWC, fp32 value, fp64 shadow, running max. */
+typedef struct {
+    int32_t w, h, C;
+    float *v;
+    double *d;
+    float *s;
+} img;
+
+static int img_alloc(img *m, int32_t w, int32_t h, int32_t C)
+{
+    size_t n = (size_t)w * (size_t)h * (size_t)C;
+    m->w = w;
+    m->h = h;
+    m->C = C;
+    m->v = (float *)malloc(n * sizeof(float));
+    m->d = (double *)malloc(n * sizeof(double));
+    m->s = (float *)malloc(n * sizeof(float));
+    if (!m->v || !m->d || !m->s)
+        return ORC_ENOMEM;
+    return ORC_OK;
+}
+
+static void img_free(img *m)
+{
+    free(m->v);
+    free(m->d);
+    free(m->s);
+    m->v = NULL;
+    m->d = NULL;
+    m->s = NULL;
+}
+
+/* ------------------------------------------------------------- steps -- */
+
+/* Crop: the region of interest becomes its own image (values to fp32). */
+static int step_crop(const orc_chain *ch, const orc_item *it, img *out)
+{
+    int32_t C = ch->channels;
+    int rc = img_alloc(out, it->w, it->h, C);
+    if (rc)
+        return rc;
+    for (int32_t j = 0; j < it->h; ++j)
+        for (int32_t i = 0; i < it->w; ++i)
+            for (int32_t c = 0; c < C; ++c) {
+                size_t o = ((size_t)j * (size_t)it->w + (size_t)i) * (size_t)C + (size_t)c;
+                float v = frame_elem(it, ch->in_dtype, C, it->x + i, it->y + j, c);
+                out->v[o] = v;
+                out->d[o] = (double)v;
+                out->s[o] = fabsf(v);
+            }
+    return ORC_OK;
+}
+
+/* Source coordinate of output index o for a scale of in/out (half-pixel
+ * centres), clamped below at 0; returns the two tap indices and weight. */
+static void bilinear_coord(int32_t o, float scale, int32_t in_size, int32_t *i0, int32_t *i1,
+                           float *a)
+{
+    float s = fmaf((float)o + 0.5f, scale, -0.5f);
+    if (s < 0.0f)
+        s = 0.0f;
+    int32_t lo = (int32_t)floorf(s);
+    if (lo > in_size - 1) /* cannot happen for in/out scales; kept as a guard */
+        lo = in_size - 1;
+    *i0 = lo;
+    *i1 = lo + 1 < in_size ? lo + 1 : in_size - 1;
+    *a = s - (float)lo;
+}
+
+/* Bilinear resize of a whole image to ow x oh. */
+static int step_resize(const img *in, int32_t ow, int32_t oh, img *out)
+{
+    int32_t C = in->C;
+    int rc = img_alloc(out, ow, oh, C);
+    if (rc)
+        return rc;
+    float sx_scale = (float)in->w / (float)ow;
+    float sy_scale = (float)in->h / (float)oh;
+    for (int32_t oy = 0; oy < oh; ++oy) {
+        int32_t y0, y1;
+        float ay;
+        bilinear_coord(oy, sy_scale, in->h, &y0, &y1, &ay);
+        for (int32_t ox = 0; ox < ow; ++ox) {
+            int32_t x0, x1;
+            float ax;
+            bilinear_coord(ox, sx_scale, in->w, &x0, &x1, &ax);
+            for (int32_t c = 0; c < C; ++c) {
+                size_t i00 = ((size_t)y0 * (size_t)in->w + (size_t)x0) * (size_t)C + (size_t)c;
+                size_t i01 = ((size_t)y0 * (size_t)in->w + (size_t)x1) * (size_t)C + (size_t)c;
+                size_t i10 = ((size_t)y1 * (size_t)in->w + (size_t)x0) * (size_t)C + (size_t)c;
+                size_t i11 = ((size_t)y1 * (size_t)in->w + (size_t)x1) * (size_t)C + (size_t)c;
+                float p00 = in->v[i00], p01 = in->v[i01], p10 = in->v[i10], p11 = in->v[i11];
+                float top = fmaf(ax, p01 - p00, p00);
+                float bot = fmaf(ax, p11 - p10, p10);
+                float v = fmaf(ay, bot - top, top);
+                double d00 = in->d[i00], d01 = in->d[i01], d10 = in->d[i10], d11 = in->d[i11];
+                double dtop = d00 + (double)ax * (d01 - d00);
+                double dbot = d10 + (double)ax * (d11 - d10);
+                double dv = dtop + (double)ay * (dbot - dtop);
+                float sm = in->s[i00];
+                if (in->s[i01] > sm) sm = in->s[i01];
+                if (in->s[i10] > sm) sm = in->s[i10];
+                if (in->s[i11] > sm) sm = in->s[i11];
+                if (fabsf(v) > sm) sm = fabsf(v);
+                size_t o = ((size_t)oy * (size_t)ow + (size_t)ox) * (size_t)C + (size_t)c;
+                out->v[o] = v;
+                out->d[o] = dv;
+                out->s[o] = sm;
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* Swap channels 0 and 2 of every pixel (BGR <-> RGB); alpha untouched. */
+static void step_swap(img *m)
+{
+    if (m->C < 3)
+        return;
+    size_t npix = (size_t)m->w * (size_t)m->h;
+    for (size_t p = 0; p < npix; ++p) {
+        size_t a = p * (size_t)m->C, b = a + 2;
+        float tv = m->v[a];
+        m->v[a] = m->v[b];
+        m->v[b] = tv;
+        double td = m->d[a];
+        m->d[a] = m->d[b];
+        m->d[b] = td;
+        float ts = m->s[a];
+        m->s[a] = m->s[b];
+        m->s[b] = ts;
+    }
+}
+
+/* One binary arithmetic op with a scalar or per-channel constant. */
+static void step_arith(img *m, const orc_op *op)
+{
+    size_t npix = (size_t)m->w * (size_t)m->h;
+    for (size_t p = 0; p < npix; ++p)
+        for (int32_t c = 0; c < m->C; ++c) {
+            size_t i = p * (size_t)m->C + (size_t)c;
+            float k = op->nconst == 1 ? op->k[0] : op->k[c];
+            float v = m->v[i];
+            double d = m->d[i];
+            float r;
+            double rd;
+            switch (op->kind) {
+            case ORC_MUL: r = v * k; rd = d * (double)k; break;
+            case ORC_ADD: r = v + k; rd = d + (double)k; break;
+            case ORC_SUB: r = v - k; rd = d - (double)k; break;
+            default:      r = v / k; rd = d / (double)k; break; /* ORC_DIV */
+            }
+            m->v[i] = r;
+            m->d[i] = rd;
+            if (fabsf(r) > m->s[i])
+                m->s[i] = fabsf(r);
+        }
+}
+
+/* Write the final image to the item's output in the chain's layout/dtype. */
+static void step_write(const orc_chain *ch, const img *m, const orc_item *it)
+{
+    int32_t C = m->C;
+    for (int32_t y = 0; y < m->h; ++y)
+        for (int32_t x = 0; x < m->w; ++x)
+            for (int32_t c = 0; c < C; ++c) {
+                size_t i = ((size_t)y * (size_t)m->w + (size_t)x) * (size_t)C + (size_t)c;
+                size_t o = ch->layout == ORC_PLANAR
+                               ? ((size_t)c * (size_t)m->h + (size_t)y) * (size_t)m->w + (size_t)x
+                               : i;
+                if (ch->out_dtype == ORC_F16)
+                    ((uint16_t *)it->dst)[o] = orc_float_to_half(m->v[i]);
+                else
+                    ((float *)it->dst)[o] = m->v[i];
+                if (it->v64)
+                    it->v64[o] = m->d[i];
+                if (it->smax)
+                    it->smax[o] = m->s[i];
+            }
+}
+
+/* ---------------------------------------------------------- validate -- */
+
+static int chain_ok(const orc_chain *ch)
+{
+    if (!ch || (ch->n_ops > 0 && !ch->ops) || ch->n_ops < 0)
+        return 0;
+    if (ch->read_kind != ORC_READ_PLAIN && ch->read_kind != ORC_READ_CROP_RESIZE)
+        return 0;
+    if (ch->in_dtype < ORC_U8 || ch->in_dtype > ORC_F32)
+        return 0;
+    if (ch->channels != 1 && ch->channels != 3 && ch->channels != 4)
+        return 0;
+    if (ch->out_dtype != ORC_F32 && ch->out_dtype != ORC_F16)
+        return 0;
+    if (ch->layout != ORC_PACKED && ch->layout != ORC_PLANAR)
+        return 0;
+    for (int32_t i = 0; i < ch->n_ops; ++i) {
+        const orc_op *op = &ch->ops[i];
+        if (op->kind < ORC_SWAP || op->kind > ORC_DIV)
+            return 0;
+        if (op->kind == ORC_SWAP || op->kind == ORC_CVT) {
+            if (op->nconst != 0)
+                return 0;
+        } else if (op->nconst != 1 && op->nconst != ch->channels) {
+            return 0;
+        }
+    }
+    return 1;
+}
+
+static int item_ok(const orc_chain *ch, const orc_item *it)
+{
+    if (!it->src || !it->dst || it->W < 1 || it->H < 1)
+        return 0;
+    if (it->pitch < (int64_t)it->W * ch->channels * (int64_t)dtype_size(ch->in_dtype))
+        return 0;
+    if (it->w < 1 || it->h < 1 || it->x < 0 || it->y < 0)
+        return 0;
+    if ((int64_t)it->x + it->w > it->W || (int64_t)it->y + it->h > it->H)
+        return 0;
+    if (ch->read_kind == ORC_READ_CROP_RESIZE && (it->ow < 1 || it->oh < 1))
+        return 0;
+    return 1;
+}
+
+/* --------------------------------------------------------------- API -- */
+
+int orc_validate(const orc_chain *ch, const orc_item *items, int32_t n)
+{
+    if (!chain_ok(ch) || n < 0 || (n > 0 && !items))
+        return ORC_EINVAL;
+    for (int32_t b = 0; b < n; ++b)
+        if (!item_ok(ch, &items[b]))
+            return ORC_EINVAL;
+    return ORC_OK;
+}
+
+/* Run the chain, unfused, on each item in turn. */
+int orc_run(const orc_chain *ch, const orc_item *items, int32_t n)
+{
+    int rc = orc_validate(ch, items, n);
+    if (rc)
+        return rc;
+    for (int32_t b = 0; b < n; ++b) {
+        const orc_item *it = &items[b];
+        img cur = {0}, nxt = {0};
+        rc = step_crop(ch, it, &cur);
+        if (!rc && ch->read_kind == ORC_READ_CROP_RESIZE) {
+            rc = step_resize(&cur, it->ow, it->oh, &nxt);
+            img_free(&cur);
+            cur = nxt;
+        }
+        for (int32_t i = 0; !rc && i < ch->n_ops; ++i) {
+            const orc_op *op = &ch->ops[i];
+            if (op->kind == ORC_SWAP)
+                step_swap(&cur);
+            else if (op->kind == ORC_CVT)
+                ; /* fp32 conversion already exact at the read */
+            else
+                step_arith(&cur, op);
+        }
+        if (!rc)
+            step_write(ch, &cur, it);
+        img_free(&cur);
+        if (rc)
+            return rc;
+    }
+    return ORC_OK;
+}
+
+/* Resize of one plane of fp32 values (used by the pins to test the resize
+ * step in isolation, without the u8 read). */
+int orc_resize_f32(const float *src, int32_t w, int32_t h, int32_t C, float *dst, int32_t ow,
+                   int32_t oh)
+{
+    if (!src || !dst || w < 1 || h < 1 || ow < 1 || oh < 1 || C < 1)
+        return ORC_EINVAL;
+    img in = {0}, out = {0};
+    int rc = img_alloc(&in, w, h, C);
+    if (rc) {
+        img_free(&in);
+        return rc;
+    }
+    size_t n = (size_t)w * (size_t)h * (size_t)C;
+    for (size_t i = 0; i < n; ++i) {
+        in.v[i] = src[i];
+        in.d[i] = (double)src[i];
+        in.s[i] = fabsf(src[i]);
+    }
+    rc = step_resize(&in, ow, oh, &out);
+    if (!rc)
+        memcpy(dst, out.v, (size_t)ow * (size_t)oh * (size_t)C * sizeof(float));
+    img_free(&in);
+    img_free(&out);
+    return rc;
+}
