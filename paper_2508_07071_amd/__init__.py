@@ -1,0 +1,303 @@
+"""Python binding of libfkmi.so, the MI355X fused preprocessing-chain library.
+
+Argument marshalling only: every step of a chain runs in the library's HIP
+kernels.  The functions keep the C ABI's names (``fk_plan_create``,
+``fk_run``, ...) and take ctypes structures or plain Python values; the
+helpers ``chain_desc`` and ``make_items`` build those structures from the
+chain/item dicts used throughout the project, with torch tensors as device
+buffers.  PyTorch provides device memory and streams only.
+
+The library is loaded after ``import torch`` so that both share torch's HIP
+runtime; loading fails loudly if the library is missing or if two HIP
+runtimes end up in the process.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch  # noqa: F401  (must own the process's HIP runtime before the library loads)
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libfkmi.so")
+
+FK_OK = 0
+FK_ERR_INVALID_ARG = -1
+FK_ERR_UNSUPPORTED = -2
+FK_ERR_OUT_OF_MEMORY = -3
+FK_ERR_HIP = -4
+FK_ERR_BAD_STATE = -5
+FK_ERR_BUDGET = -6
+
+FK_U8, FK_F16, FK_F32 = 0, 1, 2
+FK_PACKED, FK_PLANAR = 0, 1
+FK_READ_PLAIN, FK_READ_CROP_RESIZE = 0, 1
+FK_OP_SWAP_RB, FK_OP_CVT_F32, FK_OP_MUL, FK_OP_ADD, FK_OP_SUB, FK_OP_DIV = range(6)
+FK_CONFIG_DEFAULT, FK_CONFIG_MANUAL, FK_CONFIG_AUTOTUNE, FK_CONFIG_MODEL = range(4)
+FK_TIER_AUTO, FK_TIER_RUNTIME = 0, 1
+
+DTYPE = {"u8": FK_U8, "f16": FK_F16, "f32": FK_F32}
+LAYOUT = {"packed": FK_PACKED, "planar": FK_PLANAR}
+READ = {"plain": FK_READ_PLAIN, "crop_resize": FK_READ_CROP_RESIZE}
+OP = {"swap": FK_OP_SWAP_RB, "cvt": FK_OP_CVT_F32, "mul": FK_OP_MUL, "add": FK_OP_ADD,
+      "sub": FK_OP_SUB, "div": FK_OP_DIV}
+TORCH_DTYPE = {"u8": torch.uint8, "f16": torch.float16, "f32": torch.float32}
+
+
+class fk_read_desc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("in_dtype", C.c_int32), ("channels", C.c_int32)]
+
+
+class fk_op_desc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_consts", C.c_int32), ("consts", C.c_float * 4)]
+
+
+class fk_write_desc(C.Structure):
+    _fields_ = [("out_dtype", C.c_int32), ("layout", C.c_int32)]
+
+
+class fk_chain_desc(C.Structure):
+    _fields_ = [("read", fk_read_desc), ("ops", C.POINTER(fk_op_desc)), ("n_ops", C.c_int32),
+                ("write", fk_write_desc)]
+
+
+class fk_image(C.Structure):
+    _fields_ = [("ptr", C.c_void_p), ("width", C.c_int32), ("height", C.c_int32),
+                ("pitch_bytes", C.c_int64)]
+
+
+class fk_item(C.Structure):
+    _fields_ = [("src", fk_image), ("x", C.c_int32), ("y", C.c_int32), ("w", C.c_int32),
+                ("h", C.c_int32), ("dst", C.c_void_p), ("out_w", C.c_int32), ("out_h", C.c_int32)]
+
+
+class fk_launch_config(C.Structure):
+    _fields_ = [("block_threads", C.c_int32), ("coarsen", C.c_int32)]
+
+    def __repr__(self):
+        return f"fk_launch_config({self.block_threads}, {self.coarsen})"
+
+
+class fk_plan_opts(C.Structure):
+    _fields_ = [("config_source", C.c_int32), ("manual", fk_launch_config), ("use_graph", C.c_int32),
+                ("strict_fp", C.c_int32), ("tier", C.c_int32)]
+
+
+class FKError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def _hip_runtimes() -> set:
+    with open("/proc/self/maps") as f:
+        return {ln.split()[-1] for ln in f if "libamdhip64" in ln}
+
+
+def lib():
+    """Load libfkmi.so (built by ``__graft_entry__.build()``).  Raises if it
+    is missing: there is no fallback path."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    runtimes = _hip_runtimes()
+    if len(runtimes) > 1:
+        raise ImportError(f"more than one HIP runtime loaded: {sorted(runtimes)}")
+    P = C.c_void_p
+    sig = {
+        "fk_status_string": ([C.c_int32], C.c_char_p),
+        "fk_last_error": ([], C.c_char_p),
+        "fk_version": ([], C.c_char_p),
+        "fk_chain_validate": ([C.POINTER(fk_chain_desc)], C.c_int32),
+        "fk_items_validate": ([C.POINTER(fk_chain_desc), C.POINTER(fk_item), C.c_int32], C.c_int32),
+        "fk_plan_create": ([C.POINTER(fk_chain_desc), C.c_int32, C.POINTER(fk_plan_opts),
+                            C.POINTER(P)], C.c_int32),
+        "fk_plan_destroy": ([P], C.c_int32),
+        "fk_plan_get_config": ([P, C.POINTER(fk_launch_config)], C.c_int32),
+        "fk_plan_set_config": ([P, C.POINTER(fk_launch_config)], C.c_int32),
+        "fk_plan_get_tier": ([P, C.POINTER(C.c_int32)], C.c_int32),
+        "fk_run": ([P, C.POINTER(fk_item), C.c_int32, P], C.c_int32),
+        "fk_unfused_scratch_bytes": ([P, C.POINTER(fk_item), C.c_int32, C.POINTER(C.c_int64)],
+                                     C.c_int32),
+        "fk_run_unfused": ([P, C.POINTER(fk_item), C.c_int32, P, C.c_int64, P], C.c_int32),
+        "fk_autotune_space": ([C.POINTER(fk_launch_config), C.c_int32], C.c_int32),
+        "fk_autotune": ([P, C.POINTER(fk_item), C.c_int32, C.c_int32, C.POINTER(C.c_float),
+                         C.POINTER(fk_launch_config)], C.c_int32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+# Symbols the header declares; tests check the library exports each one.
+EXPORTS = [
+    "fk_status_string", "fk_last_error", "fk_version", "fk_chain_validate", "fk_items_validate",
+    "fk_plan_create", "fk_plan_destroy", "fk_plan_get_config", "fk_plan_set_config",
+    "fk_plan_get_tier", "fk_run", "fk_unfused_scratch_bytes", "fk_run_unfused",
+    "fk_autotune_space", "fk_autotune",
+]
+
+
+def check(status: int) -> int:
+    if status != FK_OK:
+        L = lib()
+        raise FKError(status, f"{L.fk_status_string(status).decode()}: {L.fk_last_error().decode()}")
+    return status
+
+
+# ------------------------------------------------------------ marshalling --
+
+def chain_desc(chain: dict):
+    """fk_chain_desc for a chain dict; the returned object keeps its op array
+    alive (attribute ``_ops``)."""
+    ops = chain["ops"]
+    arr = (fk_op_desc * max(1, len(ops)))()
+    for i, op in enumerate(ops):
+        arr[i].kind = OP[op["kind"]]
+        ks = list(op.get("k", []))
+        arr[i].n_consts = len(ks)
+        for j, v in enumerate(ks[:4]):
+            arr[i].consts[j] = v
+    d = fk_chain_desc()
+    d.read.kind = READ[chain["read"]["kind"]]
+    d.read.in_dtype = DTYPE[chain["read"]["dtype"]]
+    d.read.channels = chain["read"]["channels"]
+    d.ops = arr
+    d.n_ops = len(ops)
+    d.write.out_dtype = DTYPE[chain["write"]["dtype"]]
+    d.write.layout = LAYOUT[chain["write"]["layout"]]
+    d._ops = arr
+    return d
+
+
+def make_items(chain: dict, frames: list, items: list, outs: list):
+    """fk_item array: `frames` are device tensors (H, W, C) (any row pitch in
+    their stride), `outs` device tensors receiving each item's output."""
+    arr = (fk_item * max(1, len(items)))()
+    for b, it in enumerate(items):
+        fr = frames[it["frame"]]
+        a = arr[b]
+        a.src.ptr = fr.data_ptr()
+        a.src.height, a.src.width = int(fr.shape[0]), int(fr.shape[1])
+        a.src.pitch_bytes = int(fr.stride(0)) * fr.element_size()
+        a.x, a.y, a.w, a.h = it["x"], it["y"], it["w"], it["h"]
+        a.dst = outs[b].data_ptr()
+        if chain["read"]["kind"] == "crop_resize":
+            a.out_w, a.out_h = it["out_w"], it["out_h"]
+        else:
+            a.out_w, a.out_h = 0, 0
+    return arr
+
+
+def out_shape(chain: dict, item: dict) -> tuple:
+    c = chain["read"]["channels"]
+    if chain["read"]["kind"] == "crop_resize":
+        oh, ow = item["out_h"], item["out_w"]
+    else:
+        oh, ow = item["h"], item["w"]
+    return (c, oh, ow) if chain["write"]["layout"] == "planar" else (oh, ow, c)
+
+
+def stream_handle(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+# ------------------------------------------------------------- C ABI calls --
+
+def fk_status_string(s: int) -> str:
+    return lib().fk_status_string(s).decode()
+
+
+def fk_last_error() -> str:
+    return lib().fk_last_error().decode()
+
+
+def fk_version() -> str:
+    return lib().fk_version().decode()
+
+
+def fk_chain_validate(desc) -> int:
+    return lib().fk_chain_validate(C.byref(desc))
+
+
+def fk_items_validate(desc, items, n: int) -> int:
+    return lib().fk_items_validate(C.byref(desc), items, n)
+
+
+def fk_plan_create(desc, max_batch: int, opts=None) -> int:
+    """Returns the plan handle (an int); raises FKError on failure."""
+    h = C.c_void_p()
+    check(lib().fk_plan_create(C.byref(desc), max_batch, C.byref(opts) if opts is not None else None,
+                               C.byref(h)))
+    return h.value
+
+
+def fk_plan_destroy(plan: int) -> None:
+    check(lib().fk_plan_destroy(plan))
+
+
+def fk_plan_get_config(plan: int) -> fk_launch_config:
+    c = fk_launch_config()
+    check(lib().fk_plan_get_config(plan, C.byref(c)))
+    return c
+
+
+def fk_plan_set_config(plan: int, cfg: fk_launch_config) -> None:
+    check(lib().fk_plan_set_config(plan, C.byref(cfg)))
+
+
+def fk_plan_get_tier(plan: int) -> int:
+    v = C.c_int32()
+    check(lib().fk_plan_get_tier(plan, C.byref(v)))
+    return v.value
+
+
+def fk_run(plan: int, items, n: int, stream: int) -> None:
+    check(lib().fk_run(plan, items, n, stream))
+
+
+def fk_unfused_scratch_bytes(plan: int, items, n: int) -> int:
+    v = C.c_int64()
+    check(lib().fk_unfused_scratch_bytes(plan, items, n, C.byref(v)))
+    return v.value
+
+
+def fk_run_unfused(plan: int, items, n: int, scratch_ptr: int, scratch_bytes: int, stream: int) -> None:
+    check(lib().fk_run_unfused(plan, items, n, scratch_ptr, scratch_bytes, stream))
+
+
+def fk_autotune_space() -> list:
+    n = lib().fk_autotune_space(None, 0)
+    arr = (fk_launch_config * n)()
+    lib().fk_autotune_space(arr, n)
+    return [fk_launch_config(a.block_threads, a.coarsen) for a in arr]
+
+
+def fk_autotune(plan: int, items, n: int, reps: int):
+    """Returns (best config, list of 20 median times in ms)."""
+    space = lib().fk_autotune_space(None, 0)
+    times = (C.c_float * space)()
+    best = fk_launch_config()
+    check(lib().fk_autotune(plan, items, n, reps, times, C.byref(best)))
+    return best, list(times)
+
+
+def plan_opts(config_source=FK_CONFIG_DEFAULT, manual=(256, 1), use_graph=False, strict=False,
+              tier=FK_TIER_AUTO) -> fk_plan_opts:
+    o = fk_plan_opts()
+    o.config_source = config_source
+    o.manual.block_threads, o.manual.coarsen = manual
+    o.use_graph = int(bool(use_graph))
+    o.strict_fp = int(bool(strict))
+    o.tier = tier
+    return o

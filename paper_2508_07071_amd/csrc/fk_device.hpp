@@ -1,0 +1,633 @@
+// fk_device.hpp -- device operations and the fused transform kernel.
+//
+// Structure (Section IV of the paper, re-designed for CDNA4):
+//  - Read ops produce a register tile of fp32 pixels from device memory
+//    using the thread's coordinates (Section IV-B, read operations).
+//  - Compute ops transform the tile in registers (Section IV-A).  Two tiers:
+//      * compile-time ops composed by C++17 templates (StaticChain below),
+//        with a compile-time contraction rule fusing Mul+Add/Sub into one
+//        FMA;
+//      * a run-time op list (uniform, read with scalar loads) for chains
+//        only known when a plan is created.
+//  - Write ops store the tile (Section IV-B, write operations; Split is the
+//    planar write).
+//  - k_transform is the transform data-parallel pattern (Section IV-C): it
+//    owns the thread behaviour -- batch-slot lookup (BatchRead), work
+//    decomposition, thread coarsening -- and connects read -> compute ->
+//    write without touching memory in between.
+//
+// Work decomposition: an item's output is cut into units of kUnitPx = 4
+// consecutive pixels of one row.  A tile is blockDim.x * K units of one
+// item; thread t handles units tile_base + j * blockDim.x + t (j < K), so
+// every load/store instruction of a wave touches consecutive units.  The
+// grid strides over the tiles of all items (persistent horizontal fusion).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include <utility>
+
+#include "fk_internal.hpp"
+
+namespace fk {
+
+// Read-only tables live in the constant address space so that uniform
+// accesses become scalar loads through the scalar cache.
+#define FK_CONST __attribute__((address_space(4)))
+
+template <typename T>
+__device__ __forceinline__ const FK_CONST T *cptr(const T *p)
+{
+    return (const FK_CONST T *)p;
+}
+
+// Frames and outputs are global memory: explicit global pointers give
+// global_load/global_store instead of flat accesses.
+#define FK_GLOBAL __attribute__((address_space(1)))
+typedef const FK_GLOBAL uint8_t *gsrc_t;
+typedef FK_GLOBAL uint8_t *gdst_t;
+
+// Native vector types (usable through address-space qualified pointers).
+typedef float fx4 __attribute__((ext_vector_type(4)));
+typedef uint32_t ux4 __attribute__((ext_vector_type(4)));
+typedef uint32_t ux2 __attribute__((ext_vector_type(2)));
+
+template <int DT>
+struct DSize;
+template <>
+struct DSize<DT_U8> { static constexpr int v = 1; };
+template <>
+struct DSize<DT_F16> { static constexpr int v = 2; };
+template <>
+struct DSize<DT_F32> { static constexpr int v = 4; };
+
+// ------------------------------------------------------------ elements --
+
+template <int DT>
+__device__ __forceinline__ float load_elem(gsrc_t p);
+template <>
+__device__ __forceinline__ float load_elem<DT_U8>(gsrc_t p)
+{
+    return (float)(*p);
+}
+template <>
+__device__ __forceinline__ float load_elem<DT_F16>(gsrc_t p)
+{
+    return (float)(*(const FK_GLOBAL _Float16 *)p);
+}
+template <>
+__device__ __forceinline__ float load_elem<DT_F32>(gsrc_t p)
+{
+    return *(const FK_GLOBAL float *)p;
+}
+
+// Element i of a dword array holding packed elements of type DT.
+template <int DT, int NW>
+__device__ __forceinline__ float unpack_elem(const uint32_t (&w)[NW], int i)
+{
+    if constexpr (DT == DT_U8) {
+        return (float)((w[i >> 2] >> (8 * (i & 3))) & 0xffu);
+    } else if constexpr (DT == DT_F16) {
+        uint16_t h = (uint16_t)(w[i >> 1] >> (16 * (i & 1)));
+        return (float)__builtin_bit_cast(_Float16, h);
+    } else {
+        return __builtin_bit_cast(float, w[i]);
+    }
+}
+
+template <int DT>
+__device__ __forceinline__ void store_elem(gdst_t p, float v);
+template <>
+__device__ __forceinline__ void store_elem<DT_F32>(gdst_t p, float v)
+{
+    *(FK_GLOBAL float *)p = v;
+}
+template <>
+__device__ __forceinline__ void store_elem<DT_F16>(gdst_t p, float v)
+{
+    *(FK_GLOBAL _Float16 *)p = (_Float16)v;  // round to nearest even
+}
+
+// ---------------------------------------------------------- read ops --
+
+// Plain read: the ROI 1:1.  Loads one unit (4 pixels) of output row oy
+// starting at column ox0; returns the number of valid pixels.
+template <int DT, int C>
+struct ReadPlain {
+    static constexpr int kind = RD_PLAIN;
+    __device__ __forceinline__ static void load(const ItemRec &it, int oy, int ox0, int n,
+                                                float (&r)[kUnitPx][C])
+    {
+        constexpr int ES = DSize<DT>::v;
+        gsrc_t row = (gsrc_t)it.src + (int64_t)(it.y + oy) * it.pitch +
+                     (int64_t)(it.x + ox0) * (C * ES);
+        if (n == kUnitPx && (it.flags & IF_SRC_VEC)) {
+            constexpr int NW = kUnitPx * C * ES / 4;
+            uint32_t w[NW];
+            const FK_GLOBAL uint32_t *p = (const FK_GLOBAL uint32_t *)row;
+#pragma unroll
+            for (int i = 0; i < NW; ++i)
+                w[i] = p[i];
+#pragma unroll
+            for (int i = 0; i < kUnitPx; ++i)
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    r[i][c] = unpack_elem<DT, NW>(w, i * C + c);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kUnitPx; ++i)
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    r[i][c] = i < n ? load_elem<DT>(row + (i * C + c) * ES) : 0.0f;
+        }
+    }
+};
+
+// Half-pixel source coordinate of output index o, clamped below at 0, with
+// its two taps (clamped to the ROI) and the fractional weight.
+__device__ __forceinline__ void bilinear_coord(int o, float scale, int in_size, int &i0, int &i1,
+                                               float &a)
+{
+    float s = fmaf((float)o + 0.5f, scale, -0.5f);
+    s = s < 0.0f ? 0.0f : s;
+    int lo = (int)floorf(s);
+    lo = lo > in_size - 1 ? in_size - 1 : lo;
+    i0 = lo;
+    i1 = lo + 1 < in_size ? lo + 1 : in_size - 1;
+    a = s - (float)lo;
+}
+
+// Crop + bilinear resize: the ROI resized to (ow, oh).
+template <int DT, int C>
+struct ReadCropResize {
+    static constexpr int kind = RD_CROP_RESIZE;
+    __device__ __forceinline__ static void load(const ItemRec &it, int oy, int ox0, int n,
+                                                float (&r)[kUnitPx][C])
+    {
+        constexpr int ES = DSize<DT>::v;
+        int y0, y1;
+        float ay;
+        bilinear_coord(oy, it.sy, it.h, y0, y1, ay);
+        gsrc_t base = (gsrc_t)it.src + (int64_t)it.x * (C * ES);
+        gsrc_t r0 = base + (int64_t)(it.y + y0) * it.pitch;
+        gsrc_t r1 = base + (int64_t)(it.y + y1) * it.pitch;
+#pragma unroll
+        for (int i = 0; i < kUnitPx; ++i) {
+            if (i < n) {
+                int x0, x1;
+                float ax;
+                bilinear_coord(ox0 + i, it.sx, it.w, x0, x1, ax);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const float p00 = load_elem<DT>(r0 + (x0 * C + c) * ES);
+                    const float p01 = load_elem<DT>(r0 + (x1 * C + c) * ES);
+                    const float p10 = load_elem<DT>(r1 + (x0 * C + c) * ES);
+                    const float p11 = load_elem<DT>(r1 + (x1 * C + c) * ES);
+                    const float top = fmaf(ax, p01 - p00, p00);
+                    const float bot = fmaf(ax, p11 - p10, p10);
+                    r[i][c] = fmaf(ay, bot - top, top);
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    r[i][c] = 0.0f;
+            }
+        }
+    }
+};
+
+// ------------------------------------------------- compile-time ops --
+// Storage-less op types with a static exec on one pixel (a C-vector in
+// registers); binary ops take their constants from the plan's constant
+// table at a compile-time slot (Section IV-A: unary and binary operation
+// types; instantiable ops carry the parameters).
+
+struct OpSwapRB {
+    template <int C>
+    __device__ __forceinline__ static void exec(float (&px)[C], const FK_CONST float *)
+    {
+        if constexpr (C >= 3) {
+            float t = px[0];
+            px[0] = px[2];
+            px[2] = t;
+        }
+    }
+};
+
+struct OpCvtF32 {  // values are fp32 from the read on: nothing to do
+    template <int C>
+    __device__ __forceinline__ static void exec(float (&)[C], const FK_CONST float *) {}
+};
+
+// Per-channel constants at slot S (S .. S+C-1); PerCh = false: one scalar.
+template <int S, bool PerCh>
+struct OpMul {
+    template <int C>
+    __device__ __forceinline__ static void exec(float (&px)[C], const FK_CONST float *k)
+    {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            px[c] = px[c] * k[PerCh ? S + c : S];
+    }
+};
+template <int S, bool PerCh>
+struct OpAdd {
+    template <int C>
+    __device__ __forceinline__ static void exec(float (&px)[C], const FK_CONST float *k)
+    {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            px[c] = px[c] + k[PerCh ? S + c : S];
+    }
+};
+template <int S, bool PerCh>
+struct OpSub {
+    template <int C>
+    __device__ __forceinline__ static void exec(float (&px)[C], const FK_CONST float *k)
+    {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            px[c] = px[c] - k[PerCh ? S + c : S];
+    }
+};
+template <int S, bool PerCh>
+struct OpDiv {
+    template <int C>
+    __device__ __forceinline__ static void exec(float (&px)[C], const FK_CONST float *k)
+    {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            px[c] = px[c] / k[PerCh ? S + c : S];
+    }
+};
+// Contracted Mul followed by Add (Neg = false) or Sub (Neg = true).
+template <int S1, bool P1, int S2, bool P2, bool Neg>
+struct OpMulAddFused {
+    template <int C>
+    __device__ __forceinline__ static void exec(float (&px)[C], const FK_CONST float *k)
+    {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const float m = k[P1 ? S1 + c : S1];
+            const float a = k[P2 ? S2 + c : S2];
+            px[c] = fmaf(px[c], m, Neg ? -a : a);
+        }
+    }
+};
+
+template <class... Ops>
+struct StaticChain {
+    template <int C>
+    __device__ __forceinline__ static void exec(float (&px)[C], const FK_CONST float *k)
+    {
+        (Ops::exec(px, k), ...);
+    }
+};
+
+// Compile-time contraction: rewrite the op list so that every Mul directly
+// followed by an Add or Sub becomes one fused multiply-add.
+template <class... T>
+struct TypeList {};
+
+template <class Done, class Rest>
+struct Contract;
+template <class... D>
+struct Contract<TypeList<D...>, TypeList<>> {
+    using type = StaticChain<D...>;
+};
+template <class... D, class H, class... R>
+struct Contract<TypeList<D...>, TypeList<H, R...>> {
+    using type = typename Contract<TypeList<D..., H>, TypeList<R...>>::type;
+};
+template <class... D, int S1, bool P1, int S2, bool P2, class... R>
+struct Contract<TypeList<D...>, TypeList<OpMul<S1, P1>, OpAdd<S2, P2>, R...>> {
+    using type = typename Contract<TypeList<D..., OpMulAddFused<S1, P1, S2, P2, false>>,
+                                   TypeList<R...>>::type;
+};
+template <class... D, int S1, bool P1, int S2, bool P2, class... R>
+struct Contract<TypeList<D...>, TypeList<OpMul<S1, P1>, OpSub<S2, P2>, R...>> {
+    using type = typename Contract<TypeList<D..., OpMulAddFused<S1, P1, S2, P2, true>>,
+                                   TypeList<R...>>::type;
+};
+
+template <bool Strict, class... Ops>
+struct Compose {
+    using type = typename std::conditional<
+        Strict, StaticChain<Ops...>,
+        typename Contract<TypeList<>, TypeList<Ops...>>::type>::type;
+};
+
+// The hot normalise chain: swap, cvt, *k, -mean, /std.  Constant table:
+// [k, mean0..2, std0..2].
+template <bool Strict>
+using NormalizeChain = typename Compose<Strict, OpSwapRB, OpCvtF32, OpMul<0, false>,
+                                        OpSub<1, true>, OpDiv<4, true>>::type;
+
+// cvt then N alternating Mul (even op) / Add (odd op), scalar constants in
+// op order at slots 0..N-1.
+template <size_t I>
+using MulOrAdd = typename std::conditional<(I % 2 == 0), OpMul<(int)I, false>,
+                                           OpAdd<(int)I, false>>::type;
+template <bool Strict, class Seq>
+struct MulAddSeq;
+template <bool Strict, size_t... I>
+struct MulAddSeq<Strict, std::index_sequence<I...>> {
+    using type = typename Compose<Strict, OpCvtF32, MulOrAdd<I>...>::type;
+};
+template <int N, bool Strict>
+using MulAddChain = typename MulAddSeq<Strict, std::make_index_sequence<N>>::type;
+
+// Compute stage over a thread's whole register tile.
+template <class Chain>
+struct StaticCompute {
+    template <int K, int C>
+    __device__ __forceinline__ static void apply(const KArgs &a, float (&v)[K][kUnitPx][C])
+    {
+        const FK_CONST float *k = cptr(a.consts);
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+#pragma unroll
+            for (int i = 0; i < kUnitPx; ++i)
+                Chain::exec(v[j][i], k);
+    }
+};
+
+// ------------------------------------------------------ run-time ops --
+// The op list is uniform across the grid: each op is one scalar branch and
+// its constants come through the scalar cache, then applied to all
+// K * 4 * C values of the thread's tile.
+struct RuntimeCompute {
+    template <int K, int C>
+    __device__ __forceinline__ static void apply(const KArgs &a, float (&v)[K][kUnitPx][C])
+    {
+        const FK_CONST OpRec *ops = cptr(a.ops);
+        for (int o = 0; o < a.n_ops; ++o) {
+            const int code = ops[o].code;
+            float ka[C], kb[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                ka[c] = ops[o].a[c];
+                kb[c] = ops[o].b[c];
+            }
+            if (code == OPC_FMA) {
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+#pragma unroll
+                    for (int i = 0; i < kUnitPx; ++i)
+#pragma unroll
+                        for (int c = 0; c < C; ++c)
+                            v[j][i][c] = fmaf(v[j][i][c], ka[c], kb[c]);
+            } else if (code == OPC_MUL) {
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+#pragma unroll
+                    for (int i = 0; i < kUnitPx; ++i)
+#pragma unroll
+                        for (int c = 0; c < C; ++c)
+                            v[j][i][c] = v[j][i][c] * ka[c];
+            } else if (code == OPC_ADD) {
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+#pragma unroll
+                    for (int i = 0; i < kUnitPx; ++i)
+#pragma unroll
+                        for (int c = 0; c < C; ++c)
+                            v[j][i][c] = v[j][i][c] + ka[c];
+            } else {
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+#pragma unroll
+                    for (int i = 0; i < kUnitPx; ++i)
+#pragma unroll
+                        for (int c = 0; c < C; ++c)
+                            v[j][i][c] = v[j][i][c] / ka[c];
+            }
+        }
+    }
+};
+
+// --------------------------------------------------------- write ops --
+
+// Planar write (Split): channel c of pixel p goes to plane c.
+template <int DT, int C>
+struct WritePlanar {
+    static constexpr int layout = LY_PLANAR;
+    static constexpr int lds_bytes_per_thread = 0;
+    __device__ __forceinline__ static void store(const ItemRec &it, int oy, int ox0, int n,
+                                                 const float (&r)[kUnitPx][C], uint8_t *, bool)
+    {
+        constexpr int ES = DSize<DT>::v;
+        const int64_t plane = (int64_t)it.ow * it.oh;
+        const int64_t p0 = (int64_t)oy * it.ow + ox0;
+        gdst_t dst = (gdst_t)it.dst;
+        if (n == kUnitPx && (it.flags & IF_DST_VEC)) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                gdst_t q = dst + (c * plane + p0) * ES;
+                if constexpr (DT == DT_F32) {
+                    *(FK_GLOBAL fx4 *)q = fx4{r[0][c], r[1][c], r[2][c], r[3][c]};
+                } else {
+                    uint32_t lo = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)r[0][c]) |
+                                  ((uint32_t)__builtin_bit_cast(uint16_t, (_Float16)r[1][c]) << 16);
+                    uint32_t hi = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)r[2][c]) |
+                                  ((uint32_t)__builtin_bit_cast(uint16_t, (_Float16)r[3][c]) << 16);
+                    *(FK_GLOBAL ux2 *)q = ux2{lo, hi};
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < kUnitPx; ++i)
+                if (i < n)
+#pragma unroll
+                    for (int c = 0; c < C; ++c)
+                        store_elem<DT>(dst + (c * plane + p0 + i) * ES, r[i][c]);
+        }
+    }
+};
+
+// Packed write.  A wave whose 64 units are all whole and contiguous stages
+// its output through LDS so that each global store instruction writes one
+// contiguous run (16 bytes per lane); otherwise per-element stores.
+template <int DT, int C>
+struct WritePacked {
+    static constexpr int layout = LY_PACKED;
+    static constexpr int ES = DSize<DT>::v;
+    static constexpr int UB = kUnitPx * C * ES;                 // bytes per unit
+    static constexpr bool kStage = (UB != 16 && UB != 8);       // else already lane-contiguous
+    static constexpr int lds_bytes_per_thread = kStage ? UB : 0;
+    static constexpr int CH = (UB % 16 == 0) ? 16 : 8;          // chunk per store
+
+    __device__ __forceinline__ static void pack(const float (&r)[kUnitPx][C],
+                                                uint32_t (&w)[UB / 4])
+    {
+        if constexpr (DT == DT_F32) {
+#pragma unroll
+            for (int i = 0; i < kUnitPx; ++i)
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    w[i * C + c] = __builtin_bit_cast(uint32_t, r[i][c]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < kUnitPx * C; e += 2) {
+                const float a = r[e / C][e % C];
+                const float b = r[(e + 1) / C][(e + 1) % C];
+                w[e / 2] = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)a) |
+                           ((uint32_t)__builtin_bit_cast(uint16_t, (_Float16)b) << 16);
+            }
+        }
+    }
+
+    // wave_lds: this wave's LDS region (64 * UB bytes); all_whole: the
+    // whole wave holds whole, contiguous units (wave-uniform).
+    __device__ __forceinline__ static void store(const ItemRec &it, int oy, int ox0, int n,
+                                                 const float (&r)[kUnitPx][C], uint8_t *wave_lds,
+                                                 bool all_whole)
+    {
+        const int64_t p0 = (int64_t)oy * it.ow + ox0;
+        gdst_t dst = (gdst_t)it.dst + p0 * (C * ES);
+        if (all_whole) {
+            uint32_t w[UB / 4];
+            pack(r, w);
+            if constexpr (!kStage) {
+                if constexpr (UB == 16)
+                    *(FK_GLOBAL ux4 *)dst = ux4{w[0], w[1], w[2], w[3]};
+                else
+                    *(FK_GLOBAL ux2 *)dst = ux2{w[0], w[1]};
+            } else {
+                const int lane = threadIdx.x & (kWave - 1);
+                // lane's unit -> LDS, then 64 * UB bytes out in contiguous chunks
+                uint32_t *mine = (uint32_t *)(wave_lds + lane * UB);
+#pragma unroll
+                for (int i = 0; i < UB / 4; ++i)
+                    mine[i] = w[i];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                gdst_t wdst = dst - (int64_t)lane * UB;  // the wave's first unit
+                constexpr int NCH = kWave * UB / CH;
+#pragma unroll
+                for (int k = 0; k < (NCH + kWave - 1) / kWave; ++k) {
+                    const int ch = k * kWave + lane;
+                    if (NCH % kWave == 0 || ch < NCH) {
+                        if constexpr (CH == 16)
+                            *(FK_GLOBAL ux4 *)(wdst + ch * 16) = *(const ux4 *)(wave_lds + ch * 16);
+                        else
+                            *(FK_GLOBAL ux2 *)(wdst + ch * 8) = *(const ux2 *)(wave_lds + ch * 8);
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < kUnitPx; ++i)
+                if (i < n)
+#pragma unroll
+                    for (int c = 0; c < C; ++c)
+                        store_elem<DT>(dst + (i * C + c) * ES, r[i][c]);
+        }
+    }
+};
+
+// ------------------------------------------------ transform pattern --
+
+// Copy one item record out of the constant table (scalar loads).
+__device__ __forceinline__ ItemRec load_item(const FK_CONST ItemRec *p)
+{
+    const FK_CONST uint32_t *q = (const FK_CONST uint32_t *)p;
+    uint32_t w[sizeof(ItemRec) / 4];
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(ItemRec) / 4); ++i)
+        w[i] = q[i];
+    ItemRec it;
+    __builtin_memcpy(&it, w, sizeof(ItemRec));
+    return it;
+}
+
+// Batch slot owning a tile: the last item whose first tile is <= tile.
+__device__ __forceinline__ int find_item(const FK_CONST uint32_t *tb, int n_items, uint32_t tile)
+{
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tb[mid] <= tile)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+template <class Read, class Compute, class Write, int C, int K>
+__global__ __launch_bounds__(kMaxBlock) void k_transform(const KArgs a)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    const FK_CONST RunHeader *hdr = cptr(a.hdr);
+    const FK_CONST uint32_t *tb = cptr(a.tile_begin);
+    const FK_CONST ItemRec *items = cptr(a.items);
+    const int n_items = hdr->n_items;
+    const uint32_t total = hdr->total_tiles;
+    const int T = blockDim.x;
+    const int tid = threadIdx.x;
+    const uint32_t tile_units = (uint32_t)T * K;
+    uint8_t *wave_lds = lds + (tid / kWave) * (kWave * Write::lds_bytes_per_thread);
+    const bool swap = a.swap != 0;
+
+    for (uint32_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        const int b = find_item(tb, n_items, tile);
+        const ItemRec it = load_item(items + b);
+        const uint32_t units = (uint32_t)it.upr * (uint32_t)it.oh;
+        const uint32_t ubase = (tile - tb[b]) * tile_units;
+
+        float v[K][kUnitPx][C];
+        int oy[K], ox0[K], nv[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const uint32_t u = ubase + (uint32_t)(j * T + tid);
+            if (u < units) {
+                const uint32_t row = u / (uint32_t)it.upr;
+                oy[j] = (int)row;
+                ox0[j] = (int)(u - row * (uint32_t)it.upr) * kUnitPx;
+                const int left = it.ow - ox0[j];
+                nv[j] = left < kUnitPx ? left : kUnitPx;
+                Read::load(it, oy[j], ox0[j], nv[j], v[j]);
+            } else {
+                oy[j] = 0;
+                ox0[j] = 0;
+                nv[j] = 0;
+#pragma unroll
+                for (int i = 0; i < kUnitPx; ++i)
+#pragma unroll
+                    for (int c = 0; c < C; ++c)
+                        v[j][i][c] = 0.0f;
+            }
+        }
+        if constexpr (C >= 3) {
+            // run-time tier: the chain's net channel swap, applied at the read
+            if (swap) {
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+#pragma unroll
+                    for (int i = 0; i < kUnitPx; ++i) {
+                        const float t = v[j][i][0];
+                        v[j][i][0] = v[j][i][2];
+                        v[j][i][2] = t;
+                    }
+            }
+        }
+
+        Compute::template apply<K, C>(a, v);
+
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const bool whole = nv[j] == kUnitPx && (it.flags & IF_DST_VEC);
+            const bool wave_whole = __all(whole ? 1 : 0);
+            if (nv[j] > 0)
+                Write::store(it, oy[j], ox0[j], nv[j], v[j], wave_lds, wave_whole);
+        }
+    }
+}
+
+}  // namespace fk

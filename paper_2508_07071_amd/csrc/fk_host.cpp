@@ -1,0 +1,716 @@
+// fk_host.cpp -- host runtime of the fused chain library: validation, chain
+// normalisation, plans (the executor of Section IV-D: parameters are
+// computed on the host once per plan and per run, then the fused kernel is
+// launched), batch tables (BatchRead parameter arrays, Section IV-B), the
+// hipGraph replay path and the launch-configuration autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fk.h"
+#include "fk_host.hpp"
+#include "fk_internal.hpp"
+
+using namespace fk;
+
+// ---------------------------------------------------------------- errors --
+
+static thread_local std::string g_last_error;
+
+fk_status fk::set_error(fk_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+fk_status fk::hip_error(hipError_t e, const char *what)
+{
+    return set_error(FK_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+extern "C" const char *fk_status_string(fk_status s)
+{
+    switch (s) {
+    case FK_OK: return "ok";
+    case FK_ERR_INVALID_ARG: return "invalid argument";
+    case FK_ERR_UNSUPPORTED: return "unsupported";
+    case FK_ERR_OUT_OF_MEMORY: return "out of memory";
+    case FK_ERR_HIP: return "HIP error";
+    case FK_ERR_BAD_STATE: return "bad state";
+    case FK_ERR_BUDGET: return "over budget";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *fk_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char *fk_version(void) { return "fk-mi355x 0.1 (gfx950)"; }
+
+// ------------------------------------------------------------ validation --
+
+int fk::dtype_size(int32_t dt) { return dt == FK_U8 ? 1 : dt == FK_F16 ? 2 : 4; }
+
+fk_status fk::validate_chain(const fk_chain_desc *ch)
+{
+    if (!ch)
+        return set_error(FK_ERR_INVALID_ARG, "chain is null");
+    const fk_read_desc &r = ch->read;
+    if (r.kind != FK_READ_PLAIN && r.kind != FK_READ_CROP_RESIZE)
+        return set_error(FK_ERR_INVALID_ARG, "unknown read kind %d", r.kind);
+    if (r.in_dtype != FK_U8 && r.in_dtype != FK_F16 && r.in_dtype != FK_F32)
+        return set_error(FK_ERR_INVALID_ARG, "unknown input dtype %d", r.in_dtype);
+    if (r.channels != 1 && r.channels != 3 && r.channels != 4)
+        return set_error(FK_ERR_UNSUPPORTED, "channels must be 1, 3 or 4 (got %d)", r.channels);
+    if (ch->write.out_dtype != FK_F32 && ch->write.out_dtype != FK_F16)
+        return set_error(FK_ERR_UNSUPPORTED, "output dtype must be FK_F32 or FK_F16");
+    if (ch->write.layout != FK_PACKED && ch->write.layout != FK_PLANAR)
+        return set_error(FK_ERR_INVALID_ARG, "unknown layout %d", ch->write.layout);
+    if (ch->n_ops < 0 || ch->n_ops > FK_MAX_OPS)
+        return set_error(FK_ERR_INVALID_ARG, "n_ops %d outside 0..%d", ch->n_ops, FK_MAX_OPS);
+    if (ch->n_ops > 0 && !ch->ops)
+        return set_error(FK_ERR_INVALID_ARG, "ops is null");
+    for (int32_t i = 0; i < ch->n_ops; ++i) {
+        const fk_op_desc &op = ch->ops[i];
+        if (op.kind < FK_OP_SWAP_RB || op.kind > FK_OP_DIV)
+            return set_error(FK_ERR_INVALID_ARG, "op %d: unknown kind %d", i, op.kind);
+        if (op.kind == FK_OP_SWAP_RB || op.kind == FK_OP_CVT_F32) {
+            if (op.n_consts != 0)
+                return set_error(FK_ERR_INVALID_ARG, "op %d: takes no constants", i);
+        } else if (op.n_consts != 1 && op.n_consts != r.channels) {
+            return set_error(FK_ERR_INVALID_ARG, "op %d: n_consts must be 1 or %d", i, r.channels);
+        }
+    }
+    return FK_OK;
+}
+
+fk_status fk::validate_items(const fk_chain_desc *ch, const fk_item *items, int32_t n)
+{
+    if (n < 0)
+        return set_error(FK_ERR_INVALID_ARG, "n_items < 0");
+    if (n > 0 && !items)
+        return set_error(FK_ERR_INVALID_ARG, "items is null");
+    const int64_t es = dtype_size(ch->read.in_dtype);
+    const int64_t C = ch->read.channels;
+    for (int32_t b = 0; b < n; ++b) {
+        const fk_item &it = items[b];
+        if (!it.src.ptr || !it.dst)
+            return set_error(FK_ERR_INVALID_ARG, "item %d: null src or dst", b);
+        if (it.src.width < 1 || it.src.height < 1)
+            return set_error(FK_ERR_INVALID_ARG, "item %d: empty frame", b);
+        if (it.src.pitch_bytes < it.src.width * C * es || it.src.pitch_bytes % es != 0)
+            return set_error(FK_ERR_INVALID_ARG, "item %d: bad pitch %lld", b,
+                             (long long)it.src.pitch_bytes);
+        if ((uintptr_t)it.src.ptr % es != 0)
+            return set_error(FK_ERR_INVALID_ARG, "item %d: src not element aligned", b);
+        if ((uintptr_t)it.dst % dtype_size(ch->write.out_dtype) != 0)
+            return set_error(FK_ERR_INVALID_ARG, "item %d: dst not element aligned", b);
+        if (it.w < 1 || it.h < 1 || it.x < 0 || it.y < 0 ||
+            (int64_t)it.x + it.w > it.src.width || (int64_t)it.y + it.h > it.src.height)
+            return set_error(FK_ERR_INVALID_ARG,
+                             "item %d: ROI (%d,%d,%d,%d) not inside the %dx%d frame", b, it.x,
+                             it.y, it.w, it.h, it.src.width, it.src.height);
+        if (ch->read.kind == FK_READ_CROP_RESIZE) {
+            if (it.out_w < 1 || it.out_h < 1)
+                return set_error(FK_ERR_INVALID_ARG, "item %d: output size must be positive", b);
+            if ((int64_t)it.out_w * it.out_h > (1LL << 28))
+                return set_error(FK_ERR_UNSUPPORTED, "item %d: output too large", b);
+        } else {
+            if (!((it.out_w == 0 && it.out_h == 0) || (it.out_w == it.w && it.out_h == it.h)))
+                return set_error(FK_ERR_INVALID_ARG,
+                                 "item %d: plain read output must be 0x0 or the ROI size", b);
+            if ((int64_t)it.w * it.h > (1LL << 28))
+                return set_error(FK_ERR_UNSUPPORTED, "item %d: ROI too large", b);
+        }
+    }
+    return FK_OK;
+}
+
+extern "C" fk_status fk_chain_validate(const fk_chain_desc *chain)
+{
+    try {
+        return validate_chain(chain);
+    } catch (...) {
+        return set_error(FK_ERR_INVALID_ARG, "exception");
+    }
+}
+
+extern "C" fk_status fk_items_validate(const fk_chain_desc *chain, const fk_item *items,
+                                       int32_t n_items)
+{
+    try {
+        fk_status s = validate_chain(chain);
+        if (s)
+            return s;
+        return validate_items(chain, items, n_items);
+    } catch (...) {
+        return set_error(FK_ERR_INVALID_ARG, "exception");
+    }
+}
+
+// --------------------------------------------------------- normalisation --
+
+// Run-time op list: swaps moved to the read (each later-crossed op's
+// per-channel constants permuted), CVT dropped, SUB -> ADD(-k), and unless
+// strict, MUL immediately followed by ADD -> FMA.  Every rewrite preserves
+// the per-element fp32 arithmetic exactly except the contraction.
+void fk::normalise_chain(const fk_chain_desc *ch, bool strict, std::vector<OpRec> &ops,
+                         int32_t &swap)
+{
+    const int C = ch->read.channels;
+    // swaps after op i (parity)
+    std::vector<int> after(ch->n_ops + 1, 0);
+    for (int i = ch->n_ops - 1; i >= 0; --i)
+        after[i] = after[i + 1] ^ (ch->ops[i].kind == FK_OP_SWAP_RB ? 1 : 0);
+    swap = (C >= 3) ? after[0] : 0;
+    std::vector<OpRec> lin;
+    for (int i = 0; i < ch->n_ops; ++i) {
+        const fk_op_desc &d = ch->ops[i];
+        if (d.kind == FK_OP_SWAP_RB || d.kind == FK_OP_CVT_F32)
+            continue;
+        OpRec r;
+        std::memset(&r, 0, sizeof r);
+        float k[4];
+        for (int c = 0; c < 4; ++c)
+            k[c] = d.n_consts == 1 ? d.consts[0] : (c < C ? d.consts[c] : 0.0f);
+        if (C >= 3 && after[i + 1] && d.n_consts != 1)
+            std::swap(k[0], k[2]);
+        switch (d.kind) {
+        case FK_OP_MUL: r.code = OPC_MUL; break;
+        case FK_OP_ADD: r.code = OPC_ADD; break;
+        case FK_OP_SUB:
+            r.code = OPC_ADD;
+            for (int c = 0; c < 4; ++c)
+                k[c] = -k[c];
+            break;
+        default: r.code = OPC_DIV; break;
+        }
+        for (int c = 0; c < 4; ++c)
+            r.a[c] = k[c];
+        lin.push_back(r);
+    }
+    ops.clear();
+    for (size_t i = 0; i < lin.size(); ++i) {
+        if (!strict && lin[i].code == OPC_MUL && i + 1 < lin.size() && lin[i + 1].code == OPC_ADD) {
+            OpRec f = lin[i];
+            f.code = OPC_FMA;
+            for (int c = 0; c < 4; ++c)
+                f.b[c] = lin[i + 1].a[c];
+            ops.push_back(f);
+            ++i;
+        } else {
+            ops.push_back(lin[i]);
+        }
+    }
+}
+
+// Compile-time chains built into the library.
+int fk::match_static(const fk_chain_desc *ch, std::vector<float> &consts, int &n_ops)
+{
+    const fk_op_desc *o = ch->ops;
+    // crop+resize u8x3 -> swap, cvt, mul(1), sub, div -> planar f32
+    if (ch->read.kind == FK_READ_CROP_RESIZE && ch->read.in_dtype == FK_U8 &&
+        ch->read.channels == 3 && ch->write.out_dtype == FK_F32 && ch->write.layout == FK_PLANAR &&
+        ch->n_ops == 5 && o[0].kind == FK_OP_SWAP_RB && o[1].kind == FK_OP_CVT_F32 &&
+        o[2].kind == FK_OP_MUL && o[2].n_consts == 1 && o[3].kind == FK_OP_SUB &&
+        o[4].kind == FK_OP_DIV) {
+        consts.assign(7, 0.0f);
+        consts[0] = o[2].consts[0];
+        for (int c = 0; c < 3; ++c) {
+            consts[1 + c] = o[3].n_consts == 1 ? o[3].consts[0] : o[3].consts[c];
+            consts[4 + c] = o[4].n_consts == 1 ? o[4].consts[0] : o[4].consts[c];
+        }
+        n_ops = 5;
+        return FAM_NORMALIZE;
+    }
+    // plain u8x3 -> cvt, N alternating mul/add (scalar) -> packed f32
+    if (ch->read.kind == FK_READ_PLAIN && ch->read.in_dtype == FK_U8 && ch->read.channels == 3 &&
+        ch->write.out_dtype == FK_F32 && ch->write.layout == FK_PACKED && ch->n_ops >= 2 &&
+        o[0].kind == FK_OP_CVT_F32) {
+        const int N = ch->n_ops - 1;
+        if (N != 1 && N != 4 && N != 16 && N != 64 && N != 256)
+            return FAM_RUNTIME;
+        consts.assign(N, 0.0f);
+        for (int k = 0; k < N; ++k) {
+            const fk_op_desc &d = o[1 + k];
+            if (d.kind != (k % 2 == 0 ? FK_OP_MUL : FK_OP_ADD) || d.n_consts != 1)
+                return FAM_RUNTIME;
+            consts[k] = d.consts[0];
+        }
+        n_ops = N;
+        return FAM_MULADD;
+    }
+    return FAM_RUNTIME;
+}
+
+// ------------------------------------------------------------------ plan --
+
+static const fk_launch_config kDefaultConfig = {256, 1};
+
+bool fk::config_valid(const fk_launch_config &c)
+{
+    const bool t = c.block_threads == 64 || c.block_threads == 128 || c.block_threads == 256 ||
+                   c.block_threads == 512 || c.block_threads == 1024;
+    const bool k = c.coarsen == 1 || c.coarsen == 2 || c.coarsen == 4 || c.coarsen == 8;
+    return t && k;
+}
+
+const void *fk::plan_kernel(const fk_plan *p, const fk_launch_config &cfg)
+{
+    switch (p->family) {
+    case FAM_NORMALIZE: return kernel_normalize(cfg.coarsen, p->opts.strict_fp);
+    case FAM_MULADD: return kernel_muladd(p->static_n, cfg.coarsen, p->opts.strict_fp);
+    default:
+        return kernel_runtime(p->chain.read.kind, p->chain.read.in_dtype, p->chain.read.channels,
+                              p->chain.write.out_dtype, p->chain.write.layout, cfg.coarsen);
+    }
+}
+
+size_t fk::lds_bytes(const fk_plan *p, const fk_launch_config &cfg)
+{
+    if (p->chain.write.layout != FK_PACKED)
+        return 0;
+    const int ub = kUnitPx * p->chain.read.channels * dtype_size(p->chain.write.out_dtype);
+    if (ub == 16 || ub == 8)
+        return 0;
+    return (size_t)cfg.block_threads * ub;
+}
+
+static void free_slot(fk_plan::Slot &s)
+{
+    if (s.gexec)
+        (void)hipGraphExecDestroy(s.gexec);
+    if (s.done)
+        (void)hipEventDestroy(s.done);
+    if (s.d_table)
+        (void)hipFree(s.d_table);
+    if (s.h_stage)
+        (void)hipHostFree(s.h_stage);
+    s = fk_plan::Slot();
+}
+
+static void plan_free(fk_plan *p)
+{
+    if (!p)
+        return;
+    for (auto &s : p->slots)
+        free_slot(s);
+    if (p->d_ops)
+        (void)hipFree(p->d_ops);
+    if (p->d_consts)
+        (void)hipFree(p->d_consts);
+    if (p->capture_stream)
+        (void)hipStreamDestroy(p->capture_stream);
+    if (p->tune_stream)
+        (void)hipStreamDestroy(p->tune_stream);
+    delete p;
+}
+
+extern "C" fk_status fk_plan_create(const fk_chain_desc *chain, int32_t max_batch,
+                                    const fk_plan_opts *opts, fk_plan **out)
+{
+    try {
+        if (!out)
+            return set_error(FK_ERR_INVALID_ARG, "out is null");
+        *out = nullptr;
+        fk_status s = validate_chain(chain);
+        if (s)
+            return s;
+        if (max_batch < 1 || max_batch > (1 << 20))
+            return set_error(FK_ERR_INVALID_ARG, "max_batch %d outside 1..2^20", max_batch);
+        fk_plan_opts o = {FK_CONFIG_DEFAULT, kDefaultConfig, 0, 0, FK_TIER_AUTO};
+        if (opts)
+            o = *opts;
+        if (o.config_source == FK_CONFIG_MANUAL && !config_valid(o.manual))
+            return set_error(FK_ERR_INVALID_ARG, "manual config (%d threads, coarsen %d) invalid",
+                             o.manual.block_threads, o.manual.coarsen);
+        if (o.config_source < FK_CONFIG_DEFAULT || o.config_source > FK_CONFIG_MODEL)
+            return set_error(FK_ERR_INVALID_ARG, "unknown config source");
+        if (o.tier != FK_TIER_AUTO && o.tier != FK_TIER_RUNTIME)
+            return set_error(FK_ERR_INVALID_ARG, "unknown tier");
+
+        fk_plan *p = new (std::nothrow) fk_plan();
+        if (!p)
+            return set_error(FK_ERR_OUT_OF_MEMORY, "plan allocation");
+        p->chain = *chain;
+        p->op_descs.assign(chain->ops, chain->ops + chain->n_ops);
+        p->chain.ops = p->op_descs.data();
+        p->max_batch = max_batch;
+        p->opts = o;
+        p->cfg = o.config_source == FK_CONFIG_MANUAL ? o.manual : kDefaultConfig;
+        hipError_t e = hipGetDevice(&p->device);
+        if (e != hipSuccess) {
+            plan_free(p);
+            return hip_error(e, "hipGetDevice");
+        }
+        int cus = 0;
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+        p->num_cus = cus > 0 ? cus : 256;
+
+        std::vector<float> consts;
+        int sn = 0;
+        p->family = o.tier == FK_TIER_AUTO ? match_static(&p->chain, consts, sn) : FAM_RUNTIME;
+        p->static_n = sn;
+        normalise_chain(&p->chain, o.strict_fp != 0, p->ops, p->swap);
+        if (p->family != FAM_RUNTIME) {
+            e = hipMalloc(&p->d_consts, std::max<size_t>(consts.size(), 1) * sizeof(float));
+            if (e == hipSuccess)
+                e = hipMemcpy(p->d_consts, consts.data(), consts.size() * sizeof(float),
+                              hipMemcpyHostToDevice);
+        }
+        if (e == hipSuccess) {
+            e = hipMalloc(&p->d_ops, std::max<size_t>(p->ops.size(), 1) * sizeof(OpRec));
+            if (e == hipSuccess && !p->ops.empty())
+                e = hipMemcpy(p->d_ops, p->ops.data(), p->ops.size() * sizeof(OpRec),
+                              hipMemcpyHostToDevice);
+        }
+        p->table_bytes = sizeof(RunHeader) + sizeof(ItemRec) * (size_t)max_batch +
+                         sizeof(uint32_t) * ((size_t)max_batch + 1);
+        p->table_bytes = (p->table_bytes + 255) & ~(size_t)255;
+        for (auto &sl : p->slots) {
+            if (e != hipSuccess)
+                break;
+            e = hipHostMalloc(&sl.h_stage, p->table_bytes, hipHostMallocDefault);
+            if (e == hipSuccess)
+                e = hipMalloc(&sl.d_table, p->table_bytes);
+            if (e == hipSuccess)
+                e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        }
+        if (e == hipSuccess)
+            e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            plan_free(p);
+            return e == hipErrorOutOfMemory ? set_error(FK_ERR_OUT_OF_MEMORY, "plan buffers")
+                                            : hip_error(e, "plan buffers");
+        }
+        for (int k : {1, 2, 4, 8}) {
+            fk_launch_config c = {256, k};
+            if (!plan_kernel(p, c)) {
+                plan_free(p);
+                return set_error(FK_ERR_UNSUPPORTED, "no kernel built for this chain");
+            }
+        }
+        *out = p;
+        return FK_OK;
+    } catch (const std::bad_alloc &) {
+        return set_error(FK_ERR_OUT_OF_MEMORY, "host allocation");
+    } catch (...) {
+        return set_error(FK_ERR_INVALID_ARG, "exception");
+    }
+}
+
+extern "C" fk_status fk_plan_destroy(fk_plan *plan)
+{
+    try {
+        if (!plan)
+            return FK_OK;
+        for (auto &s : plan->slots)
+            if (s.used)
+                (void)hipEventSynchronize(s.done);
+        plan_free(plan);
+        return FK_OK;
+    } catch (...) {
+        return set_error(FK_ERR_INVALID_ARG, "exception");
+    }
+}
+
+extern "C" fk_status fk_plan_get_config(const fk_plan *plan, fk_launch_config *out)
+{
+    if (!plan || !out)
+        return set_error(FK_ERR_INVALID_ARG, "null argument");
+    *out = plan->cfg;
+    return FK_OK;
+}
+
+extern "C" fk_status fk_plan_set_config(fk_plan *plan, const fk_launch_config *cfg)
+{
+    if (!plan || !cfg)
+        return set_error(FK_ERR_INVALID_ARG, "null argument");
+    if (!config_valid(*cfg))
+        return set_error(FK_ERR_INVALID_ARG, "config (%d threads, coarsen %d) invalid",
+                         cfg->block_threads, cfg->coarsen);
+    plan->cfg = *cfg;
+    return FK_OK;
+}
+
+extern "C" fk_status fk_plan_get_tier(const fk_plan *plan, int32_t *is_static)
+{
+    if (!plan || !is_static)
+        return set_error(FK_ERR_INVALID_ARG, "null argument");
+    *is_static = plan->family != FAM_RUNTIME ? 1 : 0;
+    return FK_OK;
+}
+
+// -------------------------------------------------------------- run path --
+
+// Fill the host staging table of a run; returns the number of tiles.
+uint32_t fk::build_table(const fk_plan *p, const fk_item *items, int32_t n,
+                         const fk_launch_config &cfg, void *stage)
+{
+    RunHeader *hdr = (RunHeader *)stage;
+    ItemRec *recs = (ItemRec *)(hdr + 1);
+    uint32_t *tb = (uint32_t *)(recs + p->max_batch);
+    const int C = p->chain.read.channels;
+    const int es_in = dtype_size(p->chain.read.in_dtype);
+    const int es_out = dtype_size(p->chain.write.out_dtype);
+    const uint64_t tile_units = (uint64_t)cfg.block_threads * cfg.coarsen;
+    uint64_t tiles = 0;
+    for (int32_t b = 0; b < n; ++b) {
+        const fk_item &it = items[b];
+        ItemRec &r = recs[b];
+        std::memset(&r, 0, sizeof r);
+        r.src = (uint64_t)(uintptr_t)it.src.ptr;
+        r.dst = (uint64_t)(uintptr_t)it.dst;
+        r.pitch = it.src.pitch_bytes;
+        r.x = it.x;
+        r.y = it.y;
+        r.w = it.w;
+        r.h = it.h;
+        if (p->chain.read.kind == FK_READ_CROP_RESIZE) {
+            r.ow = it.out_w;
+            r.oh = it.out_h;
+            r.sx = (float)it.w / (float)it.out_w;
+            r.sy = (float)it.h / (float)it.out_h;
+        } else {
+            r.ow = it.w;
+            r.oh = it.h;
+            r.sx = 1.0f;
+            r.sy = 1.0f;
+        }
+        r.upr = (r.ow + kUnitPx - 1) / kUnitPx;
+        int flags = 0;
+        if ((uintptr_t)it.src.ptr % 4 == 0 && it.src.pitch_bytes % 4 == 0 &&
+            ((int64_t)it.x * C * es_in) % 4 == 0)
+            flags |= IF_SRC_VEC;
+        if (r.ow % kUnitPx == 0 && (uintptr_t)it.dst % 16 == 0)
+            flags |= IF_DST_VEC;
+        (void)es_out;
+        r.flags = flags;
+        tb[b] = (uint32_t)tiles;
+        const uint64_t units = (uint64_t)r.upr * (uint64_t)r.oh;
+        tiles += (units + tile_units - 1) / tile_units;
+    }
+    tb[n] = (uint32_t)tiles;
+    hdr->n_items = n;
+    hdr->total_tiles = (uint32_t)tiles;
+    hdr->pad[0] = hdr->pad[1] = 0;
+    return (uint32_t)tiles;
+}
+
+KArgs fk::make_args(const fk_plan *p, void *d_table)
+{
+    KArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.hdr = (const RunHeader *)d_table;
+    a.items = (const ItemRec *)((const RunHeader *)d_table + 1);
+    a.tile_begin = (const uint32_t *)(a.items + p->max_batch);
+    a.ops = (const OpRec *)p->d_ops;
+    a.consts = (const float *)p->d_consts;
+    a.n_ops = (int32_t)p->ops.size();
+    a.swap = p->family == FAM_RUNTIME ? p->swap : 0;
+    a.strict = p->opts.strict_fp;
+    return a;
+}
+
+// Blocks resident at once (persistent grid for graph replays).
+uint32_t fk::persistent_grid(const fk_plan *p, const fk_launch_config &cfg)
+{
+    const uint32_t per_cu = std::max(1, 2048 / cfg.block_threads);
+    return (uint32_t)p->num_cus * per_cu;
+}
+
+fk_status fk::launch(const fk_plan *p, const fk_launch_config &cfg, void *d_table, uint32_t grid,
+                     hipStream_t stream)
+{
+    const void *fn = plan_kernel(p, cfg);
+    if (!fn)
+        return set_error(FK_ERR_UNSUPPORTED, "no kernel for coarsening %d", cfg.coarsen);
+    KArgs a = make_args(p, d_table);
+    void *args[] = {&a};
+    hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(cfg.block_threads), args,
+                                   lds_bytes(p, cfg), stream);
+    if (e != hipSuccess)
+        return hip_error(e, "hipLaunchKernel");
+    return FK_OK;
+}
+
+fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_launch_config &cfg,
+                        bool graph, hipStream_t stream)
+{
+    fk_plan::Slot &sl = p->slots[p->next_slot];
+    p->next_slot = (p->next_slot + 1) % fk_plan::kRing;
+    hipError_t e;
+    if (sl.used) {
+        e = hipEventSynchronize(sl.done);
+        if (e != hipSuccess)
+            return hip_error(e, "hipEventSynchronize");
+    }
+    const uint32_t tiles = build_table(p, items, n, cfg, sl.h_stage);
+    if (tiles == 0)
+        return FK_OK;
+    const size_t used = sizeof(RunHeader) + sizeof(ItemRec) * (size_t)p->max_batch +
+                        sizeof(uint32_t) * ((size_t)n + 1);
+    if (graph) {
+        const bool stale = !sl.gexec || sl.gcfg.block_threads != cfg.block_threads ||
+                           sl.gcfg.coarsen != cfg.coarsen;
+        if (stale) {
+            if (sl.gexec) {
+                (void)hipGraphExecDestroy(sl.gexec);
+                sl.gexec = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess)
+                return hip_error(e, "hipStreamBeginCapture");
+            e = hipMemcpyAsync(sl.d_table, sl.h_stage, p->table_bytes, hipMemcpyHostToDevice,
+                               p->capture_stream);
+            fk_status s = FK_OK;
+            if (e == hipSuccess)
+                s = launch(p, cfg, sl.d_table, persistent_grid(p, cfg), p->capture_stream);
+            hipError_t e2 = hipStreamEndCapture(p->capture_stream, &g);
+            if (e != hipSuccess)
+                return hip_error(e, "hipMemcpyAsync (capture)");
+            if (s)
+                return s;
+            if (e2 != hipSuccess)
+                return hip_error(e2, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&sl.gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess)
+                return hip_error(e, "hipGraphInstantiate");
+            sl.gcfg = cfg;
+        }
+        e = hipGraphLaunch(sl.gexec, stream);
+        if (e != hipSuccess)
+            return hip_error(e, "hipGraphLaunch");
+    } else {
+        e = hipMemcpyAsync(sl.d_table, sl.h_stage, used, hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess)
+            return hip_error(e, "hipMemcpyAsync");
+        const uint32_t grid = std::min<uint32_t>(tiles, 1u << 20);
+        fk_status s = launch(p, cfg, sl.d_table, grid, stream);
+        if (s)
+            return s;
+    }
+    e = hipEventRecord(sl.done, stream);
+    if (e != hipSuccess)
+        return hip_error(e, "hipEventRecord");
+    sl.used = true;
+    return FK_OK;
+}
+
+extern "C" fk_status fk_run(fk_plan *plan, const fk_item *items, int32_t n_items, void *stream)
+{
+    try {
+        if (!plan)
+            return set_error(FK_ERR_INVALID_ARG, "plan is null");
+        if (n_items < 1 || n_items > plan->max_batch)
+            return set_error(FK_ERR_INVALID_ARG, "n_items %d outside 1..max_batch (%d)", n_items,
+                             plan->max_batch);
+        fk_status s = validate_items(&plan->chain, items, n_items);
+        if (s)
+            return s;
+        return run_fused(plan, items, n_items, plan->cfg, plan->opts.use_graph != 0,
+                         (hipStream_t)stream);
+    } catch (...) {
+        return set_error(FK_ERR_INVALID_ARG, "exception");
+    }
+}
+
+// ------------------------------------------------------------- autotune --
+
+extern "C" int32_t fk_autotune_space(fk_launch_config *configs, int32_t max_configs)
+{
+    int32_t n = 0;
+    for (int t : {64, 128, 256, 512, 1024})
+        for (int k : {1, 2, 4, 8}) {
+            if (configs && n < max_configs)
+                configs[n] = fk_launch_config{t, k};
+            ++n;
+        }
+    return n;
+}
+
+extern "C" fk_status fk_autotune(fk_plan *plan, const fk_item *items, int32_t n_items, int32_t reps,
+                                 float *times_ms, fk_launch_config *best)
+{
+    try {
+        if (!plan)
+            return set_error(FK_ERR_INVALID_ARG, "plan is null");
+        if (n_items < 1 || n_items > plan->max_batch)
+            return set_error(FK_ERR_INVALID_ARG, "n_items outside 1..max_batch");
+        if (reps < 1 || reps > 10000)
+            return set_error(FK_ERR_INVALID_ARG, "reps outside 1..10000");
+        fk_status s = validate_items(&plan->chain, items, n_items);
+        if (s)
+            return s;
+        hipError_t e;
+        if (!plan->tune_stream) {
+            e = hipStreamCreateWithFlags(&plan->tune_stream, hipStreamNonBlocking);
+            if (e != hipSuccess)
+                return hip_error(e, "hipStreamCreate");
+        }
+        fk_launch_config space[32];
+        const int n = fk_autotune_space(space, 32);
+        std::vector<float> med(n);
+        hipEvent_t t0, t1;
+        e = hipEventCreate(&t0);
+        if (e == hipSuccess)
+            e = hipEventCreate(&t1);
+        if (e != hipSuccess)
+            return hip_error(e, "hipEventCreate");
+        s = FK_OK;
+        for (int i = 0; i < n && !s; ++i) {
+            std::vector<float> ts;
+            for (int r = 0; r < reps + 2 && !s; ++r) {
+                e = hipEventRecord(t0, plan->tune_stream);
+                if (e == hipSuccess)
+                    s = run_fused(plan, items, n_items, space[i], false, plan->tune_stream);
+                if (e == hipSuccess && !s)
+                    e = hipEventRecord(t1, plan->tune_stream);
+                if (e == hipSuccess && !s)
+                    e = hipEventSynchronize(t1);
+                float ms = 0.0f;
+                if (e == hipSuccess && !s)
+                    e = hipEventElapsedTime(&ms, t0, t1);
+                if (e != hipSuccess && !s)
+                    s = hip_error(e, "autotune timing");
+                if (r >= 2)
+                    ts.push_back(ms);
+            }
+            if (!s) {
+                std::sort(ts.begin(), ts.end());
+                med[i] = ts[ts.size() / 2];
+            }
+        }
+        (void)hipEventDestroy(t0);
+        (void)hipEventDestroy(t1);
+        if (s)
+            return s;
+        int bi = 0;
+        for (int i = 1; i < n; ++i)  // strict < keeps the earlier (smaller T, then k) on ties
+            if (med[i] < med[bi])
+                bi = i;
+        plan->cfg = space[bi];
+        plan->opts.config_source = FK_CONFIG_AUTOTUNE;
+        if (times_ms)
+            for (int i = 0; i < n; ++i)
+                times_ms[i] = med[i];
+        if (best)
+            *best = space[bi];
+        return FK_OK;
+    } catch (...) {
+        return set_error(FK_ERR_INVALID_ARG, "exception");
+    }
+}

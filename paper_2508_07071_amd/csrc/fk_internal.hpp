@@ -1,0 +1,85 @@
+// fk_internal.hpp -- records shared by the host runtime and the kernels.
+//
+// The host turns a chain descriptor into these plain records once per plan
+// (compute ops) and once per run (batch items); the kernels read them with
+// uniform (scalar) loads.
+#pragma once
+#include <stdint.h>
+
+namespace fk {
+
+enum : int32_t { RD_PLAIN = 0, RD_CROP_RESIZE = 1 };
+enum : int32_t { DT_U8 = 0, DT_F16 = 1, DT_F32 = 2 };
+enum : int32_t { LY_PACKED = 0, LY_PLANAR = 1 };
+
+// Normalised compute op codes.  SUB becomes ADD of the negated constant
+// (IEEE x - y is x + (-y)), CVT disappears (fp32 from the read on), swaps
+// move to the read, and in the contracted mode a MUL followed by ADD/SUB
+// becomes FMA.
+enum : int32_t { OPC_MUL = 0, OPC_ADD = 1, OPC_DIV = 2, OPC_FMA = 3 };
+
+constexpr int kUnitPx = 4;       // output pixels per unit: one 16-byte planar fp32 store
+constexpr int kMaxBlock = 1024;  // largest block the kernels accept
+constexpr int kWave = 64;        // CDNA wavefront
+
+struct OpRec {          // 48 bytes
+    int32_t code;
+    int32_t pad[3];
+    float a[4];         // MUL/ADD/DIV constant per channel, or FMA multiplier
+    float b[4];         // FMA addend per channel
+};
+
+// Item flags.
+enum : int32_t {
+    IF_SRC_VEC = 1,     // source rows 4-byte aligned: unit loads as dwords
+    IF_DST_VEC = 2,     // output rows hold whole units and are 16/8-byte aligned
+};
+
+struct ItemRec {        // 64 bytes: one batch slot's parameters
+    uint64_t src;       // frame base address (device)
+    uint64_t dst;       // output base address (device)
+    int64_t pitch;      // frame row pitch in bytes
+    int32_t x, y, w, h; // region of interest in the frame
+    int32_t ow, oh;     // output size
+    float sx, sy;       // crop+resize scales w/ow and h/oh (fp32)
+    int32_t upr;        // units per output row = ceil(ow / kUnitPx)
+    int32_t flags;      // IF_*
+};
+static_assert(sizeof(ItemRec) == 64, "ItemRec layout");
+
+struct RunHeader {      // per-run header read by the kernel (graph-friendly)
+    int32_t n_items;
+    uint32_t total_tiles;
+    int32_t pad[2];
+};
+
+// Kernel arguments (by value).  Device table layout of one run:
+//   RunHeader | ItemRec[max_batch] | uint32 tile_begin[max_batch + 1]
+struct KArgs {
+    const RunHeader *hdr;
+    const ItemRec *items;
+    const uint32_t *tile_begin;
+    const OpRec *ops;      // run-time tier op list (device), n_ops entries
+    const float *consts;   // compile-time tier constants (device)
+    int32_t n_ops;
+    int32_t swap;          // net BGR<->RGB swap applied at the read
+    int32_t strict;        // compile-time tier: 1 = no contraction
+    int32_t pad;
+};
+
+// Kernel families.
+enum : int32_t {
+    FAM_RUNTIME = 0,       // any chain: run-time op list
+    FAM_NORMALIZE = 1,     // crop+resize u8x3 -> swap,cvt,mul,sub,div -> planar f32
+    FAM_MULADD = 2,        // plain u8x3 -> cvt, N x (mul, add) -> packed f32
+};
+
+// Kernel lookup (defined by the kernel translation units).  Returns the
+// host-side kernel handle to pass to hipLaunchKernel, or nullptr if the
+// combination is not built.
+const void *kernel_runtime(int read_kind, int in_dt, int channels, int out_dt, int layout,
+                           int coarsen);
+const void *kernel_normalize(int coarsen, int strict);
+const void *kernel_muladd(int n_ops, int coarsen, int strict);
+
+}  // namespace fk

@@ -1,0 +1,85 @@
+// fk_static.hip -- compile-time composed chains (the paper's method: the
+// op types are fixed when the library is compiled, only their parameters
+// arrive at run time) and the lookup of every fused kernel.
+#include "fk_device.hpp"
+
+namespace fk {
+
+const void *kernel_runtime_plain_u8(int, int, int, int);
+const void *kernel_runtime_plain_f16(int, int, int, int);
+const void *kernel_runtime_plain_f32(int, int, int, int);
+const void *kernel_runtime_resize_u8(int, int, int, int);
+const void *kernel_runtime_resize_f16(int, int, int, int);
+const void *kernel_runtime_resize_f32(int, int, int, int);
+
+const void *kernel_runtime(int read_kind, int in_dt, int channels, int out_dt, int layout,
+                           int coarsen)
+{
+    if (read_kind == RD_PLAIN) {
+        switch (in_dt) {
+        case DT_U8: return kernel_runtime_plain_u8(channels, out_dt, layout, coarsen);
+        case DT_F16: return kernel_runtime_plain_f16(channels, out_dt, layout, coarsen);
+        case DT_F32: return kernel_runtime_plain_f32(channels, out_dt, layout, coarsen);
+        }
+    } else if (read_kind == RD_CROP_RESIZE) {
+        switch (in_dt) {
+        case DT_U8: return kernel_runtime_resize_u8(channels, out_dt, layout, coarsen);
+        case DT_F16: return kernel_runtime_resize_f16(channels, out_dt, layout, coarsen);
+        case DT_F32: return kernel_runtime_resize_f32(channels, out_dt, layout, coarsen);
+        }
+    }
+    return nullptr;
+}
+
+// Crop+resize u8x3 -> swap, cvt, *k, -mean, /std -> planar fp32.
+template <bool Strict, int K>
+static const void *norm_ptr()
+{
+    return (const void *)&k_transform<ReadCropResize<DT_U8, 3>, StaticCompute<NormalizeChain<Strict>>,
+                                      WritePlanar<DT_F32, 3>, 3, K>;
+}
+
+const void *kernel_normalize(int coarsen, int strict)
+{
+    switch (coarsen) {
+    case 1: return strict ? norm_ptr<true, 1>() : norm_ptr<false, 1>();
+    case 2: return strict ? norm_ptr<true, 2>() : norm_ptr<false, 2>();
+    case 4: return strict ? norm_ptr<true, 4>() : norm_ptr<false, 4>();
+    case 8: return strict ? norm_ptr<true, 8>() : norm_ptr<false, 8>();
+    }
+    return nullptr;
+}
+
+// Plain u8x3 -> cvt, N alternating mul/add -> packed fp32.
+template <int N, bool Strict, int K>
+static const void *muladd_ptr()
+{
+    return (const void *)&k_transform<ReadPlain<DT_U8, 3>, StaticCompute<MulAddChain<N, Strict>>,
+                                      WritePacked<DT_F32, 3>, 3, K>;
+}
+
+template <int N>
+static const void *muladd_k(int coarsen, int strict)
+{
+    switch (coarsen) {
+    case 1: return strict ? muladd_ptr<N, true, 1>() : muladd_ptr<N, false, 1>();
+    case 2: return strict ? muladd_ptr<N, true, 2>() : muladd_ptr<N, false, 2>();
+    case 4: return strict ? muladd_ptr<N, true, 4>() : muladd_ptr<N, false, 4>();
+    case 8: return strict ? muladd_ptr<N, true, 8>() : muladd_ptr<N, false, 8>();
+    }
+    return nullptr;
+}
+
+const void *kernel_muladd(int n_ops, int coarsen, int strict)
+{
+    switch (n_ops) {
+    case 1: return muladd_k<1>(coarsen, strict);
+    case 4: return muladd_k<4>(coarsen, strict);
+    case 16: return muladd_k<16>(coarsen, strict);
+    case 64: return muladd_k<64>(coarsen, strict);
+    case 256: return muladd_k<256>(coarsen, strict);
+    }
+    return nullptr;
+}
+
+}  // namespace fk

@@ -1,0 +1,327 @@
+// fk_unfused.hip -- the unfused baseline: one kernel per operation and per
+// item, every intermediate written to and read back from device memory
+// (the separate-kernel pipeline of Section II's kernel-call algorithm and
+// of the vertical-fusion figure, part A).  The ops run in chain order with
+// per-op fp32 rounding, so the results equal the fused path's strict mode.
+//
+// Per item: [crop: 2-D copy of the ROI] -> [resize: bilinear to fp32] ->
+// one elementwise kernel per compute op (swap, cvt, mul, add, sub, div) ->
+// [write: packed or planar, fp32/fp16].  The last compute op writes the
+// output directly when the write is packed fp32 (no extra copy).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "fk_device.hpp"
+#include "fk_host.hpp"
+
+namespace fk {
+
+constexpr int kUnfusedBlock = 256;
+
+template <int DT>
+__device__ __forceinline__ float uload(const FK_GLOBAL uint8_t *p, int64_t e)
+{
+    return load_elem<DT>(p + e * DSize<DT>::v);
+}
+
+// Packed TIn image (contiguous w*h*C) -> packed fp32 resized image.
+template <int DT>
+__global__ __launch_bounds__(kUnfusedBlock) void k_resize(const uint8_t *src, int w, int h, int C,
+                                                         float *dst, int ow, int oh, float sx,
+                                                         float sy)
+{
+    const int64_t npix = (int64_t)ow * oh;
+    gsrc_t s = (gsrc_t)src;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npix;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int oy = (int)(p / ow), ox = (int)(p - (int64_t)oy * ow);
+        int y0, y1, x0, x1;
+        float ay, ax;
+        bilinear_coord(oy, sy, h, y0, y1, ay);
+        bilinear_coord(ox, sx, w, x0, x1, ax);
+        for (int c = 0; c < C; ++c) {
+            const float p00 = uload<DT>(s, ((int64_t)y0 * w + x0) * C + c);
+            const float p01 = uload<DT>(s, ((int64_t)y0 * w + x1) * C + c);
+            const float p10 = uload<DT>(s, ((int64_t)y1 * w + x0) * C + c);
+            const float p11 = uload<DT>(s, ((int64_t)y1 * w + x1) * C + c);
+            const float top = fmaf(ax, p01 - p00, p00);
+            const float bot = fmaf(ax, p11 - p10, p10);
+            ((FK_GLOBAL float *)dst)[p * C + c] = fmaf(ay, bot - top, top);
+        }
+    }
+}
+
+// One elementwise op over a packed image of n elements: TIn -> fp32.
+// code: -1 cvt (copy), OPC_MUL, OPC_ADD (SUB arrives as ADD of -k), OPC_DIV.
+template <int DT>
+__global__ __launch_bounds__(kUnfusedBlock) void k_elem(const uint8_t *src, float *dst, int64_t n,
+                                                       int C, int code, float k0, float k1, float k2,
+                                                       float k3)
+{
+    gsrc_t s = (gsrc_t)src;
+    FK_GLOBAL float *d = (FK_GLOBAL float *)dst;
+    const float kk[4] = {k0, k1, k2, k3};
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const float v = uload<DT>(s, e);
+        const float k = kk[(int)(e % C)];
+        float r;
+        if (code == OPC_MUL)
+            r = v * k;
+        else if (code == OPC_ADD)
+            r = v + k;
+        else if (code == OPC_DIV)
+            r = v / k;
+        else
+            r = v;
+        d[e] = r;
+    }
+}
+
+// BGR <-> RGB over a packed image of npix pixels: TIn -> fp32.
+template <int DT>
+__global__ __launch_bounds__(kUnfusedBlock) void k_swap(const uint8_t *src, float *dst,
+                                                       int64_t npix, int C)
+{
+    gsrc_t s = (gsrc_t)src;
+    FK_GLOBAL float *d = (FK_GLOBAL float *)dst;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npix;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        for (int c = 0; c < C; ++c) {
+            const int sc = (C >= 3 && c != 1 && c != 3) ? 2 - c : c;
+            d[p * C + c] = uload<DT>(s, p * C + sc);
+        }
+    }
+}
+
+// Final write: packed TIn image -> output dtype, packed or planar (Split).
+template <int DT, int DTO>
+__global__ __launch_bounds__(kUnfusedBlock) void k_write(const uint8_t *src, uint8_t *dst,
+                                                        int64_t npix, int C, int planar)
+{
+    gsrc_t s = (gsrc_t)src;
+    gdst_t d = (gdst_t)dst;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npix;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        for (int c = 0; c < C; ++c) {
+            const float v = uload<DT>(s, p * C + c);
+            const int64_t o = planar ? (int64_t)c * npix + p : p * C + c;
+            store_elem<DTO>(d + o * DSize<DTO>::v, v);
+        }
+    }
+}
+
+static unsigned grid_for(int64_t n)
+{
+    const int64_t g = (n + kUnfusedBlock - 1) / kUnfusedBlock;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 1 << 16));
+}
+
+static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct ScratchPlan {
+    size_t crop = 0, buf = 0;
+    size_t total() const { return align_up(crop) + 2 * align_up(buf); }
+};
+
+static ScratchPlan scratch_for(const fk_plan *p, const fk_item &it)
+{
+    const int C = p->chain.read.channels;
+    const int es = dtype_size(p->chain.read.in_dtype);
+    ScratchPlan s;
+    s.crop = (size_t)it.w * it.h * C * es;
+    size_t npix = (size_t)it.w * it.h;
+    if (p->chain.read.kind == FK_READ_CROP_RESIZE)
+        npix = std::max(npix, (size_t)it.out_w * it.out_h);
+    s.buf = npix * C * sizeof(float);
+    return s;
+}
+
+template <int DT>
+static void launch_elem(const void *src, float *dst, int64_t n, int C, int code, const float *k,
+                        hipStream_t st)
+{
+    k_elem<DT><<<grid_for(n), kUnfusedBlock, 0, st>>>((const uint8_t *)src, dst, n, C, code, k[0],
+                                                      k[1], k[2], k[3]);
+}
+
+static void elem_any(int dt, const void *src, float *dst, int64_t n, int C, int code,
+                     const float *k, hipStream_t st)
+{
+    if (dt == DT_U8)
+        launch_elem<DT_U8>(src, dst, n, C, code, k, st);
+    else if (dt == DT_F16)
+        launch_elem<DT_F16>(src, dst, n, C, code, k, st);
+    else
+        launch_elem<DT_F32>(src, dst, n, C, code, k, st);
+}
+
+static void swap_any(int dt, const void *src, float *dst, int64_t npix, int C, hipStream_t st)
+{
+    const unsigned g = grid_for(npix);
+    if (dt == DT_U8)
+        k_swap<DT_U8><<<g, kUnfusedBlock, 0, st>>>((const uint8_t *)src, dst, npix, C);
+    else if (dt == DT_F16)
+        k_swap<DT_F16><<<g, kUnfusedBlock, 0, st>>>((const uint8_t *)src, dst, npix, C);
+    else
+        k_swap<DT_F32><<<g, kUnfusedBlock, 0, st>>>((const uint8_t *)src, dst, npix, C);
+}
+
+template <int DTO>
+static void write_out(int dt, const void *src, void *dst, int64_t npix, int C, int planar,
+                      hipStream_t st)
+{
+    const unsigned g = grid_for(npix);
+    if (dt == DT_U8)
+        k_write<DT_U8, DTO><<<g, kUnfusedBlock, 0, st>>>((const uint8_t *)src, (uint8_t *)dst, npix, C, planar);
+    else if (dt == DT_F16)
+        k_write<DT_F16, DTO><<<g, kUnfusedBlock, 0, st>>>((const uint8_t *)src, (uint8_t *)dst, npix, C, planar);
+    else
+        k_write<DT_F32, DTO><<<g, kUnfusedBlock, 0, st>>>((const uint8_t *)src, (uint8_t *)dst, npix, C, planar);
+}
+
+static fk_status run_item_unfused(const fk_plan *p, const fk_item &it, uint8_t *scratch,
+                                  hipStream_t st)
+{
+    const int C = p->chain.read.channels;
+    const int din = p->chain.read.in_dtype;
+    const int es = dtype_size(din);
+    const ScratchPlan sp = scratch_for(p, it);
+    uint8_t *crop = scratch;
+    float *buf[2] = {(float *)(scratch + align_up(sp.crop)),
+                     (float *)(scratch + align_up(sp.crop) + align_up(sp.buf))};
+    const uint8_t *roi = (const uint8_t *)it.src.ptr + (int64_t)it.y * it.src.pitch_bytes +
+                         (int64_t)it.x * C * es;
+    const size_t row_bytes = (size_t)it.w * C * es;
+    const void *cur = nullptr;
+    int cur_dt = din;
+    int nb = 0;  // next ping-pong buffer
+    int64_t npix = (int64_t)it.w * it.h;
+    hipError_t e = hipSuccess;
+
+    const bool contiguous = (size_t)it.src.pitch_bytes == row_bytes ||
+                            (it.h == 1);
+    if (p->chain.read.kind == FK_READ_PLAIN && contiguous) {
+        cur = roi;  // the ROI already is a dense image: no crop kernel
+    } else {
+        e = hipMemcpy2DAsync(crop, row_bytes, roi, it.src.pitch_bytes, row_bytes, it.h,
+                             hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess)
+            return hip_error(e, "crop copy");
+        cur = crop;
+    }
+    if (p->chain.read.kind == FK_READ_CROP_RESIZE) {
+        const float sx = (float)it.w / (float)it.out_w, sy = (float)it.h / (float)it.out_h;
+        npix = (int64_t)it.out_w * it.out_h;
+        float *o = buf[nb];
+        nb ^= 1;
+        const unsigned g = grid_for(npix);
+        if (din == DT_U8)
+            k_resize<DT_U8><<<g, kUnfusedBlock, 0, st>>>((const uint8_t *)cur, it.w, it.h, C, o, it.out_w, it.out_h, sx, sy);
+        else if (din == DT_F16)
+            k_resize<DT_F16><<<g, kUnfusedBlock, 0, st>>>((const uint8_t *)cur, it.w, it.h, C, o, it.out_w, it.out_h, sx, sy);
+        else
+            k_resize<DT_F32><<<g, kUnfusedBlock, 0, st>>>((const uint8_t *)cur, it.w, it.h, C, o, it.out_w, it.out_h, sx, sy);
+        cur = o;
+        cur_dt = DT_F32;
+    }
+    const bool direct = p->chain.write.layout == FK_PACKED && p->chain.write.out_dtype == FK_F32;
+    int last_op = -1;
+    for (int i = 0; i < p->chain.n_ops; ++i)
+        if (p->chain.ops[i].kind != FK_OP_SWAP_RB || C >= 3)
+            last_op = i;
+    for (int i = 0; i < p->chain.n_ops; ++i) {
+        const fk_op_desc &d = p->chain.ops[i];
+        if (d.kind == FK_OP_SWAP_RB && C < 3)
+            continue;  // a no-op: no kernel
+        float *o = (direct && i == last_op) ? (float *)it.dst : buf[nb];
+        if (o != (float *)it.dst)
+            nb ^= 1;
+        if (d.kind == FK_OP_SWAP_RB) {
+            swap_any(cur_dt, cur, o, npix, C, st);
+        } else {
+            float k[4];
+            for (int c = 0; c < 4; ++c)
+                k[c] = d.n_consts == 1 ? d.consts[0] : (c < C ? d.consts[c] : 0.0f);
+            int code = -1;
+            if (d.kind == FK_OP_MUL) {
+                code = OPC_MUL;
+            } else if (d.kind == FK_OP_ADD) {
+                code = OPC_ADD;
+            } else if (d.kind == FK_OP_SUB) {
+                code = OPC_ADD;
+                for (int c = 0; c < 4; ++c)
+                    k[c] = -k[c];
+            } else if (d.kind == FK_OP_DIV) {
+                code = OPC_DIV;
+            }
+            elem_any(cur_dt, cur, o, npix * C, C, code, k, st);
+        }
+        cur = o;
+        cur_dt = DT_F32;
+    }
+    if (!(direct && last_op >= 0)) {
+        const int planar = p->chain.write.layout == FK_PLANAR;
+        if (p->chain.write.out_dtype == FK_F16)
+            write_out<DT_F16>(cur_dt, cur, it.dst, npix, C, planar, st);
+        else
+            write_out<DT_F32>(cur_dt, cur, it.dst, npix, C, planar, st);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_error(e, "unfused launch");
+    return FK_OK;
+}
+
+}  // namespace fk
+
+using namespace fk;
+
+extern "C" fk_status fk_unfused_scratch_bytes(const fk_plan *plan, const fk_item *items,
+                                              int32_t n_items, int64_t *bytes)
+{
+    try {
+        if (!plan || !bytes)
+            return set_error(FK_ERR_INVALID_ARG, "null argument");
+        fk_status s = validate_items(&plan->chain, items, n_items);
+        if (s)
+            return s;
+        size_t need = 0;
+        for (int32_t b = 0; b < n_items; ++b)
+            need = std::max(need, scratch_for(plan, items[b]).total());
+        *bytes = (int64_t)need;
+        return FK_OK;
+    } catch (...) {
+        return set_error(FK_ERR_INVALID_ARG, "exception");
+    }
+}
+
+extern "C" fk_status fk_run_unfused(fk_plan *plan, const fk_item *items, int32_t n_items,
+                                    void *d_scratch, int64_t scratch_bytes, void *stream)
+{
+    try {
+        if (!plan)
+            return set_error(FK_ERR_INVALID_ARG, "plan is null");
+        if (n_items < 1 || n_items > plan->max_batch)
+            return set_error(FK_ERR_INVALID_ARG, "n_items outside 1..max_batch");
+        fk_status s = validate_items(&plan->chain, items, n_items);
+        if (s)
+            return s;
+        int64_t need = 0;
+        for (int32_t b = 0; b < n_items; ++b)
+            need = std::max<int64_t>(need, (int64_t)scratch_for(plan, items[b]).total());
+        if (!d_scratch || scratch_bytes < need)
+            return set_error(FK_ERR_INVALID_ARG, "scratch too small: %lld < %lld bytes",
+                             (long long)scratch_bytes, (long long)need);
+        for (int32_t b = 0; b < n_items; ++b) {
+            s = run_item_unfused(plan, items[b], (uint8_t *)d_scratch, (hipStream_t)stream);
+            if (s)
+                return s;
+        }
+        return FK_OK;
+    } catch (...) {
+        return set_error(FK_ERR_INVALID_ARG, "exception");
+    }
+}

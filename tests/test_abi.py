@@ -1,0 +1,130 @@
+"""The C ABI library on the host: it loads next to torch's HIP runtime,
+exports every symbol include/fk.h declares, and rejects bad chains and
+items before any device work (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+import torch
+
+import paper_2508_07071_amd as fk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "fk.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fk_\w+)\s*\(", text)))
+
+
+def test_library_loads_with_one_hip_runtime():
+    L = fk.lib()
+    assert L is not None
+    runtimes = fk._hip_runtimes()
+    assert len(runtimes) <= 1
+    assert "gfx950" in fk.fk_version()
+
+
+def test_exports_every_declared_symbol():
+    declared = header_functions()
+    assert declared, "no declarations parsed"
+    L = fk.lib()
+    for name in declared:
+        assert hasattr(L, name), f"{name} declared in fk.h but not exported"
+    assert sorted(fk.EXPORTS) == declared
+
+
+def test_status_strings():
+    assert fk.fk_status_string(fk.FK_OK) == "ok"
+    assert fk.fk_status_string(fk.FK_ERR_INVALID_ARG) == "invalid argument"
+    assert fk.fk_status_string(fk.FK_ERR_HIP) == "HIP error"
+    assert fk.fk_status_string(12345) == "unknown status"
+
+
+def norm_chain():
+    import datagen
+    return datagen.normalize_chain(64, 128)
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda c: c["read"].update(kind="warp"), None),
+    (lambda c: c["read"].update(channels=2), fk.FK_ERR_UNSUPPORTED),
+    (lambda c: c["write"].update(dtype="u8"), fk.FK_ERR_UNSUPPORTED),
+    (lambda c: c["ops"].__setitem__(2, {"kind": "mul", "k": [1.0, 2.0]}), fk.FK_ERR_INVALID_ARG),
+    (lambda c: c["ops"].__setitem__(0, {"kind": "swap", "k": [1.0]}), fk.FK_ERR_INVALID_ARG),
+])
+def test_chain_validation_rejects(mutate, status):
+    c = norm_chain()
+    assert fk.fk_chain_validate(fk.chain_desc(c)) == fk.FK_OK
+    try:
+        mutate(c)
+        d = fk.chain_desc(c)
+    except KeyError:
+        # unknown names cannot even be marshalled: build the bad code directly
+        d = fk.chain_desc(norm_chain())
+        d.read.kind = 7
+        status = fk.FK_ERR_INVALID_ARG
+    assert fk.fk_chain_validate(d) == status
+    assert fk.fk_last_error()
+
+
+def test_chain_validation_limits():
+    d = fk.chain_desc(norm_chain())
+    d.n_ops = 5000
+    assert fk.fk_chain_validate(d) == fk.FK_ERR_INVALID_ARG
+    d = fk.chain_desc(norm_chain())
+    d.ops = None
+    assert fk.fk_chain_validate(d) == fk.FK_ERR_INVALID_ARG
+    assert fk.lib().fk_chain_validate(None) == fk.FK_ERR_INVALID_ARG
+
+
+def fake_items(chain, n=1, **kw):
+    arr = (fk.fk_item * n)()
+    for a in arr:
+        a.src.ptr = 0x10000
+        a.src.width, a.src.height = 640, 480
+        a.src.pitch_bytes = 640 * 3
+        a.x, a.y, a.w, a.h = 10, 20, 100, 80
+        a.dst = 0x20000
+        a.out_w, a.out_h = 64, 128
+        for k, v in kw.items():
+            if k in ("ptr", "width", "height", "pitch_bytes"):
+                setattr(a.src, k, v)
+            else:
+                setattr(a, k, v)
+    return arr
+
+
+@pytest.mark.parametrize("kw", [dict(x=-1), dict(y=-1), dict(w=0), dict(h=0), dict(x=541), dict(y=401),
+                                dict(pitch_bytes=100), dict(ptr=None), dict(dst=None), dict(out_w=0),
+                                dict(width=0)])
+def test_item_validation_rejects(kw):
+    d = fk.chain_desc(norm_chain())
+    assert fk.fk_items_validate(d, fake_items(norm_chain()), 1) == fk.FK_OK
+    assert fk.fk_items_validate(d, fake_items(norm_chain(), **kw), 1) == fk.FK_ERR_INVALID_ARG
+
+
+def test_plain_read_output_size_must_match_roi():
+    import datagen
+    c = datagen.muladd_chain(4, datagen.rng(0))
+    d = fk.chain_desc(c)
+    assert fk.fk_items_validate(d, fake_items(c, out_w=0, out_h=0), 1) == fk.FK_OK
+    assert fk.fk_items_validate(d, fake_items(c, out_w=100, out_h=80), 1) == fk.FK_OK
+    assert fk.fk_items_validate(d, fake_items(c, out_w=64, out_h=128), 1) == fk.FK_ERR_INVALID_ARG
+
+
+def test_autotune_space_order():
+    space = fk.fk_autotune_space()
+    assert len(space) == 20
+    got = [(c.block_threads, c.coarsen) for c in space]
+    assert got == [(t, k) for t in (64, 128, 256, 512, 1024) for k in (1, 2, 4, 8)]
+
+
+@pytest.mark.skipif(torch.cuda.is_available(), reason="checks the no-GPU error path")
+def test_plan_create_without_gpu_fails_cleanly():
+    d = fk.chain_desc(norm_chain())
+    with pytest.raises(fk.FKError) as e:
+        fk.fk_plan_create(d, 4)
+    assert e.value.status == fk.FK_ERR_HIP
