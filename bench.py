@@ -1,0 +1,363 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused memory-bound chain on one MI355X.
+
+Default workload (vertical-fusion depth sweep): one 3840x2160x3 uint8 frame
+(seeded uniform bytes); chain = convert to fp32, then N alternating
+multiply/add ops with seeded constants, written packed HWC fp32, for
+N in {1, 4, 16, 64, 256}.  One step runs the fused chain once at every
+depth (five launches).  Buffers rotate over four (frame, output) sets, 0.5
+GB in all, so the 256 MB Infinity Cache cannot hold the working set.
+
+Printed JSON line:
+  value        algorithmic bytes of the step (5 x 124,416,000 B) / step time
+  roofline     the dominant kernel (the longest per step) against its bound;
+               its average duration comes from HIP events around each of its
+               launches inside the timed region
+  per_depth    every depth's average kernel time, GB/s, fraction of HBM peak,
+               and the unfused one-kernel-per-op baseline with the speedup
+  cpu_baseline the CPU oracle (single thread) on a band of rows of the same
+               frame through the whole sweep, scaled to GB/s
+
+Other workloads (--workload): "hf" (batched uneven crops, config 2 sizes)
+and "norm" (the single-crop hot chain, config 0); these are for the design
+notes, not the headline line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+# fp32 FMA without packed math: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz x 2 flops
+ALU_PEAK_TFLOPS = 78.6
+DEPTHS = [1, 4, 16, 64, 256]
+FRAME_HW = (2160, 3840)
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def vf_sweep(args):
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2508_07071_amd as fk
+
+    dev = torch.device("cuda:0")
+    H, W = FRAME_HW
+    in_bytes = H * W * 3
+    out_bytes = H * W * 3 * 4
+    alg_bytes = in_bytes + out_bytes  # 124,416,000 B per launch, any depth
+    R = args.rotate
+
+    cfgs = {n: datagen.config1(n, seed=args.seed, frame_hw=FRAME_HW) for n in DEPTHS}
+    frame_np = cfgs[DEPTHS[0]]["frames"][0]
+    frames = [torch.from_numpy(frame_np).to(dev) for _ in range(R)]
+    outs = [torch.empty((H, W, 3), dtype=torch.float32, device=dev) for _ in range(R)]
+    item = datagen.whole_frame_item(frame_np)
+    stream = fk.stream_handle()
+
+    plans, items_by_set, tuned = {}, {}, {}
+    for n in DEPTHS:
+        ch = cfgs[n]["chain"]
+        desc = fk.chain_desc(ch)
+        opts = fk.plan_opts(strict=args.strict)
+        h = fk.fk_plan_create(desc, R, opts)
+        plans[n] = (h, desc)
+        items_by_set[n] = [fk.make_items(ch, [frames[r]], [item], [outs[r]]) for r in range(R)]
+        # autotune over all R sets in one batched launch (HBM-resident working set)
+        allsets = fk.make_items(ch, frames, [dict(item, frame=r) for r in range(R)], outs)
+        if args.autotune:
+            best, times = fk.fk_autotune(h, allsets, R, 7)
+            log(f"N={n} autotune (4 sets/launch) ms:",
+                {f"{c.block_threads}x{c.coarsen}": round(t / R, 4) for c, t in zip(fk.fk_autotune_space(), times)})
+        else:
+            best = fk.fk_plan_get_config(h)
+        tuned[n] = (best.block_threads, best.coarsen, fk.fk_plan_get_tier(h))
+        log(f"N={n}: config {best.block_threads}x{best.coarsen} static={tuned[n][2]}")
+
+    counter = [0]
+
+    def step(events=None):
+        for n in DEPTHS:
+            r = counter[0] % R
+            counter[0] += 1
+            if events is not None:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+            fk.fk_run(plans[n][0], items_by_set[n][r], 1, stream)
+            if events is not None:
+                e1.record()
+                events[n].append((e0, e1))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    events = {n: [] for n in DEPTHS}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(events)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    kern_ms = {n: float(np.mean([a.elapsed_time(b) for a, b in events[n]])) for n in DEPTHS}
+    log("kernel ms", {n: round(v, 4) for n, v in kern_ms.items()}, "step ms", round(ms_per_step, 4))
+
+    # unfused baseline (outside the timed region): one kernel per op
+    unfused_ms = {}
+    if not args.no_unfused:
+        for n in DEPTHS:
+            h = plans[n][0]
+            it = items_by_set[n][0]
+            nbytes = fk.fk_unfused_scratch_bytes(h, it, 1)
+            scratch = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            reps = 3 if n <= 64 else 2
+            fk.fk_run_unfused(h, items_by_set[n][1 % R], 1, scratch.data_ptr(), nbytes, stream)
+            torch.cuda.synchronize()
+            ts = []
+            for i in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fk.fk_run_unfused(h, items_by_set[n][i % R], 1, scratch.data_ptr(), nbytes, stream)
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            unfused_ms[n] = float(np.median(ts))
+            del scratch
+        log("unfused ms", {n: round(v, 3) for n, v in unfused_ms.items()})
+
+    per_depth = []
+    for n in DEPTHS:
+        gbps = alg_bytes / (kern_ms[n] * 1e-3) / 1e9
+        flops = 2.0 * (n // 2) * in_bytes + (n % 2) * in_bytes  # n element-ops per element
+        d = {"n_ops": n, "kernel_ms": round(kern_ms[n], 5), "gbps": round(gbps, 1),
+             "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4),
+             "alu_frac": round(flops / (kern_ms[n] * 1e-3) / 1e12 / ALU_PEAK_TFLOPS, 4),
+             "launch_config": list(tuned[n][:2]), "compile_time_chain": bool(tuned[n][2])}
+        if n in unfused_ms:
+            ubytes = in_bytes + out_bytes + n * 2 * out_bytes  # every op reads+writes fp32
+            ubytes -= out_bytes  # the first op reads u8 instead of fp32
+            d["unfused_ms"] = round(unfused_ms[n], 4)
+            d["unfused_gbps_alg"] = round(alg_bytes / (unfused_ms[n] * 1e-3) / 1e9, 1)
+            d["unfused_moved_gb"] = round(ubytes / 1e9, 3)
+            d["speedup_vs_unfused"] = round(unfused_ms[n] / kern_ms[n], 2)
+        per_depth.append(d)
+
+    dom = max(DEPTHS, key=lambda n: kern_ms[n])
+    n = dom
+    flops = 2.0 * (n // 2) * in_bytes + (n % 2) * in_bytes
+    alu_s = flops / (ALU_PEAK_TFLOPS * 1e12)
+    hbm_s = alg_bytes / (HBM_PEAK_GBPS * 1e9)
+    if alu_s > hbm_s:
+        achieved = flops / (kern_ms[n] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": ALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4)}
+    else:
+        achieved = alg_bytes / (kern_ms[n] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4)}
+    roof["kernel"] = f"fused cvt+{n} mul/add ops, 3840x2160x3 u8 -> packed fp32"
+    roof["kernel_ms"] = round(kern_ms[n], 5)
+    roof["traffic"] = measured_traffic(n)
+
+    value = len(DEPTHS) * alg_bytes / (ms_per_step * 1e-3) / 1e9
+    res = {
+        "metric": "fused-chain GB/s (fraction of HBM peak) vs unfused per-op",
+        "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "hbm_frac": round(value / HBM_PEAK_GBPS, 4),
+        "config": {"workload": "vf_depth_sweep: 3840x2160x3 u8 frame, cvt + N alternating mul/add, "
+                               "N in {1,4,16,64,256}, packed HWC fp32 out",
+                   "frame": "3840x2160x3 u8", "depths": DEPTHS, "bytes_per_launch": alg_bytes,
+                   "rotation_sets": R, "fp_mode": "strict" if args.strict else "contracted",
+                   "seed": args.seed},
+        "roofline": roof,
+        "per_depth": per_depth,
+    }
+    if unfused_ms:
+        tot_f = sum(kern_ms.values())
+        tot_u = sum(unfused_ms.values())
+        res["unfused"] = {"ms_per_step": round(tot_u, 4),
+                          "value": round(len(DEPTHS) * alg_bytes / (tot_u * 1e-3) / 1e9, 1),
+                          "unit": "GB/s", "speedup": round(tot_u / tot_f, 2)}
+    for n in DEPTHS:
+        fk.fk_plan_destroy(plans[n][0])
+    return res, cfgs
+
+
+def measured_traffic(n_ops):
+    """HBM bytes per launch of the depth-n kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary (copy-kernel scaled), or None
+    when the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "vf_depth_sweep_4k_traffic.json")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256()
+        for f in ("fk_device.hpp", "fk_internal.hpp", "fk_static.hip"):
+            h.update(open(os.path.join(ROOT, "paper_2508_07071_amd", "csrc", f), "rb").read())
+        if h.hexdigest()[:16] != rec["source_digest"]:
+            return None
+        return rec["traffic_bytes_per_launch"].get(str(n_ops))
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def cpu_baseline_vf(args, cfgs):
+    """The oracle, single-threaded, on a band of rows through the sweep."""
+    import numpy as np
+
+    import datagen
+    import oracle
+
+    rows = args.cpu_rows
+    frame = cfgs[DEPTHS[0]]["frames"][0]
+    band = np.ascontiguousarray(frame[:rows])
+    item = datagen.whole_frame_item(band)
+    t0 = time.perf_counter()
+    for n in DEPTHS:
+        oracle.run_chain(cfgs[n]["chain"], [band], [item], shadow=True)
+    dt = time.perf_counter() - t0
+    alg = len(DEPTHS) * band.size * (1 + 4)
+    return {"value": round(alg / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"rows 0..{rows - 1} of the 3840x2160 frame ({band.size} elements) through "
+                      f"all five depths, {dt:.1f} s; unfused per-op fp32 with fp64 shadow"}
+
+
+def hf_workload(args):
+    """Batched uneven crops (config 2 sizes): fused single launch vs per-crop
+    launches vs unfused per-op per-crop, eager and hipGraph."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2508_07071_amd as fk
+
+    dev = torch.device("cuda:0")
+    stream = fk.stream_handle()
+    rows = []
+    for B in (1, 8, 50, 256):
+        cfg = datagen.config2(B, seed=args.seed)
+        ch = cfg["chain"]
+        frame = torch.from_numpy(cfg["frames"][0]).to(dev)
+        out = torch.empty((B, 3, 128, 64), dtype=torch.float32, device=dev)
+        arr = fk.make_items(ch, [frame], cfg["items"], [out[b] for b in range(B)])
+        desc = fk.chain_desc(ch)
+        tapped = 0
+        for it in cfg["items"]:
+            tapped += min(it["w"], 2 * 64) * min(it["h"], 2 * 128) * 3
+        alg = tapped + B * 3 * 128 * 64 * 4
+
+        def timeit(fn, reps=50):
+            for _ in range(5):
+                fn()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        res = {"batch": B, "alg_bytes": alg}
+        for graph in (False, True):
+            h = fk.fk_plan_create(desc, B, fk.plan_opts(use_graph=graph))
+            if not graph:
+                best, _ = fk.fk_autotune(h, arr, B, 10)
+                res["autotuned"] = [best.block_threads, best.coarsen]
+                cfg_best = best
+            else:
+                fk.fk_plan_set_config(h, cfg_best)
+            ms = timeit(lambda: fk.fk_run(h, arr, B, stream))
+            res["graph_ms" if graph else "fused_ms"] = round(ms, 4)
+            if not graph:
+                singles = [fk.make_items(ch, [frame], [it], [out[b]]) for b, it in enumerate(cfg["items"])]
+                res["per_crop_ms"] = round(timeit(lambda: [fk.fk_run(h, s, 1, stream) for s in singles], 10), 4)
+                nbytes = fk.fk_unfused_scratch_bytes(h, arr, B)
+                scratch = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+                res["unfused_ms"] = round(timeit(lambda: fk.fk_run_unfused(h, arr, B, scratch.data_ptr(), nbytes, stream), 5), 4)
+            fk.fk_plan_destroy(h)
+        res["fused_gbps"] = round(alg / (res["fused_ms"] * 1e-3) / 1e9, 1)
+        res["speedup_vs_per_crop"] = round(res["per_crop_ms"] / res["fused_ms"], 2)
+        res["speedup_vs_unfused"] = round(res["unfused_ms"] / res["fused_ms"], 2)
+        log(res)
+        rows.append(res)
+    return {"workload": "hf_batch_sweep (config 2 sizes)", "rows": rows}
+
+
+def copy_workload(args):
+    """Device-to-device copy of known size (torch's copy kernel): measured
+    HBM bandwidth for context, and the reference for scaling rocprofv3's
+    FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    nbytes = 256 << 20
+    bufs = [torch.empty(nbytes, dtype=torch.uint8, device=dev) for _ in range(8)]
+    for b in bufs:
+        b.fill_(1)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    for i in range(args.warmup):
+        bufs[(2 * i + 1) % 8].copy_(bufs[(2 * i) % 8])
+    torch.cuda.synchronize()
+    e0.record()
+    for i in range(args.steps):
+        bufs[(2 * i + 1) % 8].copy_(bufs[(2 * i) % 8])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    return {"workload": "d2d copy 256 MiB (read + write), 4 rotating pairs", "bytes_per_copy": 2 * nbytes,
+            "ms": round(ms, 5), "gbps": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="vf", choices=["vf", "hf", "copy"])
+    ap.add_argument("--rotate", type=int, default=4)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--strict", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune each depth's launch config first (default: the library default)")
+    ap.add_argument("--no-unfused", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=540)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(items and frames shard across GPUs with no exchange; see the design notes).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    if args.workload == "hf":
+        print(json.dumps(hf_workload(args)))
+        return
+    if args.workload == "copy":
+        print(json.dumps(copy_workload(args)))
+        return
+    res, cfgs = vf_sweep(args)
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        res["cpu_baseline"] = cpu_baseline_vf(args, cfgs)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

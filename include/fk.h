@@ -138,7 +138,8 @@ typedef struct {
     int32_t coarsen;
 } fk_launch_config;
 
-#define FK_CONFIG_DEFAULT 0  /* 256 threads, coarsening 1 */
+#define FK_CONFIG_DEFAULT 0  /* 256 threads; coarsening 1, or 4 for chains of
+                                more than 32 normalised ops */
 #define FK_CONFIG_MANUAL 1   /* opts.manual */
 #define FK_CONFIG_AUTOTUNE 2 /* set by fk_autotune (default until then) */
 #define FK_CONFIG_MODEL 3    /* predicted by a cost model (fk_plan_use_model) */

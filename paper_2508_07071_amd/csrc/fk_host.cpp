@@ -258,6 +258,16 @@ int fk::match_static(const fk_chain_desc *ch, std::vector<float> &consts, int &n
 
 static const fk_launch_config kDefaultConfig = {256, 1};
 
+// Default launch configuration: 256 threads; long op lists get coarsening 4
+// so that each scalar constant load is amortised over more values.
+static fk_launch_config default_config(const fk_plan *p)
+{
+    fk_launch_config c = kDefaultConfig;
+    if (p->ops.size() > 32 || p->static_n > 64)
+        c.coarsen = 4;
+    return c;
+}
+
 bool fk::config_valid(const fk_launch_config &c)
 {
     const bool t = c.block_threads == 64 || c.block_threads == 128 || c.block_threads == 256 ||
@@ -348,7 +358,7 @@ extern "C" fk_status fk_plan_create(const fk_chain_desc *chain, int32_t max_batc
         p->chain.ops = p->op_descs.data();
         p->max_batch = max_batch;
         p->opts = o;
-        p->cfg = o.config_source == FK_CONFIG_MANUAL ? o.manual : kDefaultConfig;
+        p->cfg = kDefaultConfig;
         hipError_t e = hipGetDevice(&p->device);
         if (e != hipSuccess) {
             plan_free(p);
@@ -363,6 +373,7 @@ extern "C" fk_status fk_plan_create(const fk_chain_desc *chain, int32_t max_batc
         p->family = o.tier == FK_TIER_AUTO ? match_static(&p->chain, consts, sn) : FAM_RUNTIME;
         p->static_n = sn;
         normalise_chain(&p->chain, o.strict_fp != 0, p->ops, p->swap);
+        p->cfg = o.config_source == FK_CONFIG_MANUAL ? o.manual : default_config(p);
         if (p->family != FAM_RUNTIME) {
             e = hipMalloc(&p->d_consts, std::max<size_t>(consts.size(), 1) * sizeof(float));
             if (e == hipSuccess)
@@ -454,13 +465,11 @@ extern "C" fk_status fk_plan_get_tier(const fk_plan *plan, int32_t *is_static)
 
 // -------------------------------------------------------------- run path --
 
-// Fill the host staging table of a run; returns the number of tiles.
-uint32_t fk::build_table(const fk_plan *p, const fk_item *items, int32_t n,
-                         const fk_launch_config &cfg, void *stage)
+// Fill the item records and tile prefix sums of a run; returns the number
+// of tiles.
+uint32_t fk::build_items(const fk_plan *p, const fk_item *items, int32_t n,
+                         const fk_launch_config &cfg, ItemRec *recs, uint32_t *tb)
 {
-    RunHeader *hdr = (RunHeader *)stage;
-    ItemRec *recs = (ItemRec *)(hdr + 1);
-    uint32_t *tb = (uint32_t *)(recs + p->max_batch);
     const int C = p->chain.read.channels;
     const int es_in = dtype_size(p->chain.read.in_dtype);
     const int es_out = dtype_size(p->chain.write.out_dtype);
@@ -502,10 +511,21 @@ uint32_t fk::build_table(const fk_plan *p, const fk_item *items, int32_t n,
         tiles += (units + tile_units - 1) / tile_units;
     }
     tb[n] = (uint32_t)tiles;
-    hdr->n_items = n;
-    hdr->total_tiles = (uint32_t)tiles;
-    hdr->pad[0] = hdr->pad[1] = 0;
     return (uint32_t)tiles;
+}
+
+// Fill the host staging table of a run (header, items, prefix sums).
+uint32_t fk::build_table(const fk_plan *p, const fk_item *items, int32_t n,
+                         const fk_launch_config &cfg, void *stage)
+{
+    RunHeader *hdr = (RunHeader *)stage;
+    ItemRec *recs = (ItemRec *)(hdr + 1);
+    uint32_t *tb = (uint32_t *)(recs + p->max_batch);
+    const uint32_t tiles = build_items(p, items, n, cfg, recs, tb);
+    hdr->n_items = n;
+    hdr->total_tiles = tiles;
+    hdr->pad[0] = hdr->pad[1] = 0;
+    return tiles;
 }
 
 KArgs fk::make_args(const fk_plan *p, void *d_table)
@@ -530,13 +550,12 @@ uint32_t fk::persistent_grid(const fk_plan *p, const fk_launch_config &cfg)
     return (uint32_t)p->num_cus * per_cu;
 }
 
-fk_status fk::launch(const fk_plan *p, const fk_launch_config &cfg, void *d_table, uint32_t grid,
-                     hipStream_t stream)
+fk_status fk::launch_args(const fk_plan *p, const fk_launch_config &cfg, KArgs &a, uint32_t grid,
+                          hipStream_t stream)
 {
     const void *fn = plan_kernel(p, cfg);
     if (!fn)
         return set_error(FK_ERR_UNSUPPORTED, "no kernel for coarsening %d", cfg.coarsen);
-    KArgs a = make_args(p, d_table);
     void *args[] = {&a};
     hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(cfg.block_threads), args,
                                    lds_bytes(p, cfg), stream);
@@ -545,9 +564,27 @@ fk_status fk::launch(const fk_plan *p, const fk_launch_config &cfg, void *d_tabl
     return FK_OK;
 }
 
+fk_status fk::launch(const fk_plan *p, const fk_launch_config &cfg, void *d_table, uint32_t grid,
+                     hipStream_t stream)
+{
+    KArgs a = make_args(p, d_table);
+    return launch_args(p, cfg, a, grid, stream);
+}
+
 fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_launch_config &cfg,
                         bool graph, hipStream_t stream)
 {
+    if (!graph && n <= kInlineItems) {
+        // small batch: the parameters travel in the kernel arguments
+        KArgs a = make_args(p, nullptr);
+        a.hdr = nullptr;
+        a.items = nullptr;
+        a.tile_begin = nullptr;
+        a.inl_n = n;
+        a.inl_total_tiles = build_items(p, items, n, cfg, a.inl_items, a.inl_tile_begin);
+        const uint32_t grid = std::min<uint32_t>(a.inl_total_tiles, 1u << 20);
+        return launch_args(p, cfg, a, grid, stream);
+    }
     fk_plan::Slot &sl = p->slots[p->next_slot];
     p->next_slot = (p->next_slot + 1) % fk_plan::kRing;
     hipError_t e;

@@ -51,10 +51,14 @@ int match_static(const fk_chain_desc *ch, std::vector<float> &consts, int &n_ops
 bool config_valid(const fk_launch_config &c);
 const void *plan_kernel(const fk_plan *p, const fk_launch_config &cfg);
 size_t lds_bytes(const fk_plan *p, const fk_launch_config &cfg);
+uint32_t build_items(const fk_plan *p, const fk_item *items, int32_t n, const fk_launch_config &cfg,
+                     ItemRec *recs, uint32_t *tb);
 uint32_t build_table(const fk_plan *p, const fk_item *items, int32_t n, const fk_launch_config &cfg,
                      void *stage);
 KArgs make_args(const fk_plan *p, void *d_table);
 uint32_t persistent_grid(const fk_plan *p, const fk_launch_config &cfg);
+fk_status launch_args(const fk_plan *p, const fk_launch_config &cfg, KArgs &a, uint32_t grid,
+                      hipStream_t stream);
 fk_status launch(const fk_plan *p, const fk_launch_config &cfg, void *d_table, uint32_t grid,
                  hipStream_t stream);
 fk_status run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_launch_config &cfg,

@@ -53,7 +53,10 @@ struct RunHeader {      // per-run header read by the kernel (graph-friendly)
     int32_t pad[2];
 };
 
-// Kernel arguments (by value).  Device table layout of one run:
+constexpr int kInlineItems = 8;  // batches up to this size ride in the kernel arguments
+
+// Kernel arguments (by value, the only kernel argument, so it starts the
+// kernarg segment).  Device table layout of one run:
 //   RunHeader | ItemRec[max_batch] | uint32 tile_begin[max_batch + 1]
 struct KArgs {
     const RunHeader *hdr;
@@ -64,7 +67,10 @@ struct KArgs {
     int32_t n_ops;
     int32_t swap;          // net BGR<->RGB swap applied at the read
     int32_t strict;        // compile-time tier: 1 = no contraction
-    int32_t pad;
+    int32_t inl_n;         // > 0: the run's items are inl_items[0..inl_n)
+    uint32_t inl_total_tiles;
+    uint32_t inl_tile_begin[kInlineItems + 1];
+    ItemRec inl_items[kInlineItems];
 };
 
 // Kernel families.
