@@ -176,7 +176,9 @@ fk_status fk_items_validate(const fk_chain_desc *chain, const fk_item *items, in
 
 /* Create a plan for `chain` and up to `max_batch` items per run (the batch
  * capacity; each run passes its own count, Section IV-B).  `opts` may be
- * NULL (defaults).  Allocates the plan's device item tables (a small ring).
+ * NULL (defaults).  Allocates the plan's op list on the device; the ring
+ * of run tables for batches too large for the kernel arguments (and for
+ * graph replays) is allocated on first use.
  * Selects the kernel: a compile-time composed chain when the chain matches
  * one built into the library, else the run-time op-list kernel. */
 fk_status fk_plan_create(const fk_chain_desc *chain, int32_t max_batch, const fk_plan_opts *opts,
@@ -211,13 +213,163 @@ fk_status fk_run_unfused(fk_plan *plan, const fk_item *items, int32_t n_items, v
 /* Number of launch configurations the autotuner tries (20) and the i-th. */
 int32_t fk_autotune_space(fk_launch_config *configs, int32_t max_configs);
 
-/* Time every launch configuration on these items (median of `reps` timed
- * launches after warm-up, HIP events on an internal stream), write the 20
+/* Time every launch configuration on these items (one warm-up launch, then
+ * the median of 3 samples of `reps` back-to-back launches timed by HIP
+ * events on an internal stream, divided by `reps`), write the 20
  * median times in milliseconds to `times_ms` (may be NULL), select the
  * fastest (ties: fewer threads, then less coarsening) into the plan and
  * `best` (may be NULL).  Synchronous; outputs are overwritten. */
 fk_status fk_autotune(fk_plan *plan, const fk_item *items, int32_t n_items, int32_t reps,
                       float *times_ms, fk_launch_config *best);
+
+/* ------------------------------------------------------------------------
+ * Launch-configuration cost model (not in the paper: the paper fixes its
+ * launch shapes, e.g. 32x8x1 blocks).  A fully connected ReLU network,
+ * FK_MODEL_FEATURES -> hidden -> hidden -> hidden -> FK_MODEL_OUTPUTS,
+ * fp32, that predicts the log-time ratio t(config) / t(best) of each of the
+ * autotuner's 20 configurations; the prediction's argmin is the chosen
+ * configuration.  Trained and run on the GPU by the library's own kernels
+ * (tiled fp32 GEMM with bias/ReLU epilogues, column sums, MSE, Adam). */
+#define FK_MODEL_FEATURES 32
+#define FK_MODEL_OUTPUTS 20
+
+typedef struct fk_model fk_model;
+
+/* New model with `hidden` units per hidden layer (1..1024), weights drawn
+ * He-uniform from `seed`, biases zero, feature normalisation identity.
+ * Allocates device memory. */
+fk_status fk_model_create(int32_t hidden, uint64_t seed, fk_model **out);
+fk_status fk_model_destroy(fk_model *model);
+
+/* Number of fp32 parameters; layout: for each layer l, W_l (out x in,
+ * row-major) then b_l (out). */
+int64_t fk_model_param_count(const fk_model *model);
+fk_status fk_model_get_params(const fk_model *model, float *out, int64_t n);
+fk_status fk_model_set_params(fk_model *model, const float *in, int64_t n);
+/* Per-feature normalisation x' = (x - mean) / std applied before the
+ * network (host arrays of FK_MODEL_FEATURES). */
+fk_status fk_model_get_normalization(const fk_model *model, float *mean, float *std);
+fk_status fk_model_set_normalization(fk_model *model, const float *mean, const float *std);
+
+/* Features of a (plan, items) pair: chain shape (read kind, dtypes,
+ * channels, layout, normalised op counts, tier) and item geometry (sizes,
+ * scales, bytes, alignment), FK_MODEL_FEATURES floats into `out` (host).
+ * Host only. */
+fk_status fk_model_features(const fk_plan *plan, const fk_item *items, int32_t n_items, float *out);
+
+/* Train on n samples (host arrays: features n x FK_MODEL_FEATURES, targets
+ * n x FK_MODEL_OUTPUTS) for `epochs` passes of shuffled mini-batches of
+ * `batch` rows, Adam (beta1 0.9, beta2 0.999, eps 1e-8) at learning rate lr,
+ * MSE loss.  The first call fixes the feature normalisation from these
+ * features.  loss_curve (host, may be NULL) receives each epoch's mean
+ * mini-batch loss.  Synchronous. */
+fk_status fk_model_train(fk_model *model, const float *features, const float *targets, int32_t n,
+                         int32_t epochs, int32_t batch, float lr, uint64_t seed, float *loss_curve);
+
+/* Network outputs for n feature rows (host in, host out n x
+ * FK_MODEL_OUTPUTS).  Synchronous. */
+fk_status fk_model_predict_batch(fk_model *model, const float *features, int32_t n, float *out);
+
+/* One forward + backward pass without an update: mean-squared-error loss of
+ * n rows against `targets` and its gradient w.r.t. every parameter (host,
+ * fk_model_param_count floats, same layout as the parameters). */
+fk_status fk_model_loss_grad(fk_model *model, const float *features, const float *targets,
+                             int32_t n, float *loss, float *grad);
+
+/* Predicted best launch configuration for running `plan` on these items,
+ * and the same applied to the plan (config source FK_CONFIG_MODEL). */
+fk_status fk_model_predict(fk_model *model, const fk_plan *plan, const fk_item *items, int32_t n,
+                           fk_launch_config *out);
+fk_status fk_plan_use_model(fk_plan *plan, fk_model *model, const fk_item *items, int32_t n);
+
+/* Save / load: one JSON header line, then feature mean, feature std and
+ * parameters as little-endian fp32. */
+fk_status fk_model_save(const fk_model *model, const char *path);
+fk_status fk_model_load(const char *path, fk_model **out);
+
+/* ------------------------------------------------------------------------
+ * Serving loop (not in the paper; its production use is the motivation of
+ * Sections I and VII).  Requests -- one host frame with crops -- are admitted
+ * first-in first-out against a device-memory budget; each admitted frame is
+ * copied to the device on a copy stream and stays there until released; a
+ * scheduler thread continuously batches the crops of every request whose
+ * frame has arrived into horizontally fused launches (several in flight on
+ * a compute stream), so requests arriving while others run join the next
+ * launch.  Each crop's result depends only on its own pixels, so it is the
+ * same alone and in any mix. */
+typedef struct {
+    int32_t x, y, w, h;  /* ROI in the request's frame */
+    int32_t out_w, out_h;
+} fk_crop;
+
+typedef struct {
+    const void *frame;   /* host, packed HWC of the chain's read dtype/channels;
+                            valid until the request completes (pinned memory
+                            gives an asynchronous copy) */
+    int32_t width, height;
+    int64_t pitch_bytes;
+    const fk_crop *crops; /* copied by fk_server_submit */
+    int32_t n_crops;      /* 1..max_batch_items */
+    double t_arrival;     /* fk_server_clock() seconds; latency starts here */
+} fk_request;
+
+#define FK_SERVER_BATCHED 0      /* continuous batching across requests */
+#define FK_SERVER_PER_REQUEST 1  /* one fused launch per request, FIFO */
+#define FK_SERVER_UNFUSED 2      /* one kernel per op per crop, FIFO */
+
+typedef struct {
+    const fk_chain_desc *chain;  /* read kind FK_READ_CROP_RESIZE; copied */
+    void *arena;                 /* device memory for frames, outputs, scratch; caller-owned */
+    int64_t arena_bytes;
+    int64_t budget_bytes;        /* admission budget, 0 = arena_bytes */
+    int32_t max_batch_items;     /* crops per launch (1..65536) */
+    int32_t max_inflight;        /* launches in flight (1..4) */
+    int32_t mode;                /* FK_SERVER_* */
+    int32_t strict_fp;
+    fk_launch_config config;     /* {0, 0}: the plan's default */
+} fk_server_opts;
+
+typedef struct {
+    uint64_t ticket;
+    int32_t status;              /* FK_OK, or the failure */
+    int32_t n_crops;
+    void *outputs;               /* device: crop i starts at the 256-byte aligned
+                                    offset after crop i-1's output (dense, in the
+                                    chain's write layout and dtype) */
+    int64_t output_bytes;
+    double t_arrival, t_admit, t_launch, t_done;  /* fk_server_clock() seconds */
+} fk_completion;
+
+typedef struct {
+    int64_t submitted, admitted, completed, launches, crops_launched;
+    int64_t bytes_in_use, peak_bytes;
+    int64_t pending;             /* submitted, not yet admitted */
+} fk_server_stats;
+
+typedef struct fk_server fk_server;
+
+/* Seconds on the monotonic clock used for every server timestamp. */
+double fk_server_clock(void);
+
+/* Start a server (creates its streams, plan and scheduler thread). */
+fk_status fk_server_create(const fk_server_opts *opts, fk_server **out);
+
+/* Queue a request; returns at once with its ticket.  FK_ERR_BUDGET if the
+ * request alone exceeds the budget; FK_ERR_BAD_STATE after a device error or
+ * while shutting down. */
+fk_status fk_server_submit(fk_server *srv, const fk_request *req, uint64_t *ticket);
+
+/* Up to `max` completions (oldest first) into `out`; their count in *n. */
+fk_status fk_server_poll(fk_server *srv, fk_completion *out, int32_t max, int32_t *n);
+
+/* Return a completed request's device memory to the budget. */
+fk_status fk_server_release(fk_server *srv, uint64_t ticket);
+
+fk_status fk_server_stats_get(fk_server *srv, fk_server_stats *out);
+
+/* Stop the scheduler after the work in flight, free everything the server
+ * owns (not the arena).  NULL is allowed. */
+fk_status fk_server_destroy(fk_server *srv);
 
 #ifdef __cplusplus
 }

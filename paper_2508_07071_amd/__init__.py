@@ -83,6 +83,38 @@ class fk_plan_opts(C.Structure):
                 ("strict_fp", C.c_int32), ("tier", C.c_int32)]
 
 
+class fk_crop(C.Structure):
+    _fields_ = [("x", C.c_int32), ("y", C.c_int32), ("w", C.c_int32), ("h", C.c_int32),
+                ("out_w", C.c_int32), ("out_h", C.c_int32)]
+
+
+class fk_request(C.Structure):
+    _fields_ = [("frame", C.c_void_p), ("width", C.c_int32), ("height", C.c_int32),
+                ("pitch_bytes", C.c_int64), ("crops", C.POINTER(fk_crop)), ("n_crops", C.c_int32),
+                ("t_arrival", C.c_double)]
+
+
+class fk_server_opts(C.Structure):
+    _fields_ = [("chain", C.POINTER(fk_chain_desc)), ("arena", C.c_void_p), ("arena_bytes", C.c_int64),
+                ("budget_bytes", C.c_int64), ("max_batch_items", C.c_int32), ("max_inflight", C.c_int32),
+                ("mode", C.c_int32), ("strict_fp", C.c_int32), ("config", fk_launch_config)]
+
+
+class fk_completion(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("status", C.c_int32), ("n_crops", C.c_int32),
+                ("outputs", C.c_void_p), ("output_bytes", C.c_int64), ("t_arrival", C.c_double),
+                ("t_admit", C.c_double), ("t_launch", C.c_double), ("t_done", C.c_double)]
+
+
+class fk_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("launches", C.c_int64), ("crops_launched", C.c_int64), ("bytes_in_use", C.c_int64),
+                ("peak_bytes", C.c_int64), ("pending", C.c_int64)]
+
+
+FK_SERVER_BATCHED, FK_SERVER_PER_REQUEST, FK_SERVER_UNFUSED = 0, 1, 2
+
+
 class FKError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{msg} (status {status})")
@@ -129,6 +161,30 @@ def lib():
         "fk_autotune_space": ([C.POINTER(fk_launch_config), C.c_int32], C.c_int32),
         "fk_autotune": ([P, C.POINTER(fk_item), C.c_int32, C.c_int32, C.POINTER(C.c_float),
                          C.POINTER(fk_launch_config)], C.c_int32),
+        "fk_model_create": ([C.c_int32, C.c_uint64, C.POINTER(P)], C.c_int32),
+        "fk_model_destroy": ([P], C.c_int32),
+        "fk_model_param_count": ([P], C.c_int64),
+        "fk_model_get_params": ([P, P, C.c_int64], C.c_int32),
+        "fk_model_set_params": ([P, P, C.c_int64], C.c_int32),
+        "fk_model_get_normalization": ([P, P, P], C.c_int32),
+        "fk_model_set_normalization": ([P, P, P], C.c_int32),
+        "fk_model_features": ([P, C.POINTER(fk_item), C.c_int32, P], C.c_int32),
+        "fk_model_train": ([P, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_uint64, P],
+                           C.c_int32),
+        "fk_model_predict_batch": ([P, P, C.c_int32, P], C.c_int32),
+        "fk_model_loss_grad": ([P, P, P, C.c_int32, P, P], C.c_int32),
+        "fk_model_predict": ([P, P, C.POINTER(fk_item), C.c_int32, C.POINTER(fk_launch_config)],
+                             C.c_int32),
+        "fk_plan_use_model": ([P, P, C.POINTER(fk_item), C.c_int32], C.c_int32),
+        "fk_model_save": ([P, C.c_char_p], C.c_int32),
+        "fk_model_load": ([C.c_char_p, C.POINTER(P)], C.c_int32),
+        "fk_server_clock": ([], C.c_double),
+        "fk_server_create": ([C.POINTER(fk_server_opts), C.POINTER(P)], C.c_int32),
+        "fk_server_submit": ([P, C.POINTER(fk_request), C.POINTER(C.c_uint64)], C.c_int32),
+        "fk_server_poll": ([P, C.POINTER(fk_completion), C.c_int32, C.POINTER(C.c_int32)], C.c_int32),
+        "fk_server_release": ([P, C.c_uint64], C.c_int32),
+        "fk_server_stats_get": ([P, C.POINTER(fk_server_stats)], C.c_int32),
+        "fk_server_destroy": ([P], C.c_int32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -144,7 +200,16 @@ EXPORTS = [
     "fk_plan_create", "fk_plan_destroy", "fk_plan_get_config", "fk_plan_set_config",
     "fk_plan_get_tier", "fk_run", "fk_unfused_scratch_bytes", "fk_run_unfused",
     "fk_autotune_space", "fk_autotune",
+    "fk_model_create", "fk_model_destroy", "fk_model_param_count", "fk_model_get_params",
+    "fk_model_set_params", "fk_model_get_normalization", "fk_model_set_normalization",
+    "fk_model_features", "fk_model_train", "fk_model_predict_batch", "fk_model_loss_grad",
+    "fk_model_predict", "fk_plan_use_model", "fk_model_save", "fk_model_load",
+    "fk_server_clock", "fk_server_create", "fk_server_submit", "fk_server_poll", "fk_server_release",
+    "fk_server_stats_get", "fk_server_destroy",
 ]
+
+FK_MODEL_FEATURES = 32
+FK_MODEL_OUTPUTS = 20
 
 
 def check(status: int) -> int:
@@ -290,6 +355,193 @@ def fk_autotune(plan: int, items, n: int, reps: int):
     best = fk_launch_config()
     check(lib().fk_autotune(plan, items, n, reps, times, C.byref(best)))
     return best, list(times)
+
+
+# ----------------------------------------------------------- cost model --
+
+def _f32(a):
+    import numpy as np
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def fk_model_create(hidden: int = 128, seed: int = 0) -> int:
+    h = C.c_void_p()
+    check(lib().fk_model_create(hidden, seed, C.byref(h)))
+    return h.value
+
+
+def fk_model_destroy(model: int) -> None:
+    check(lib().fk_model_destroy(model))
+
+
+def fk_model_param_count(model: int) -> int:
+    return int(lib().fk_model_param_count(model))
+
+
+def fk_model_get_params(model: int):
+    import numpy as np
+    out = np.zeros(fk_model_param_count(model), np.float32)
+    check(lib().fk_model_get_params(model, out.ctypes.data, out.size))
+    return out
+
+
+def fk_model_set_params(model: int, params) -> None:
+    p = _f32(params)
+    check(lib().fk_model_set_params(model, p.ctypes.data, p.size))
+
+
+def fk_model_get_normalization(model: int):
+    import numpy as np
+    mean = np.zeros(FK_MODEL_FEATURES, np.float32)
+    std = np.zeros(FK_MODEL_FEATURES, np.float32)
+    check(lib().fk_model_get_normalization(model, mean.ctypes.data, std.ctypes.data))
+    return mean, std
+
+
+def fk_model_set_normalization(model: int, mean, std) -> None:
+    m, s = _f32(mean), _f32(std)
+    check(lib().fk_model_set_normalization(model, m.ctypes.data, s.ctypes.data))
+
+
+def fk_model_features(plan: int, items, n: int):
+    import numpy as np
+    out = np.zeros(FK_MODEL_FEATURES, np.float32)
+    check(lib().fk_model_features(plan, items, n, out.ctypes.data))
+    return out
+
+
+def fk_model_train(model: int, features, targets, epochs: int, batch: int, lr: float, seed: int = 0):
+    """Returns the per-epoch mean mini-batch loss."""
+    import numpy as np
+    x, t = _f32(features), _f32(targets)
+    curve = np.zeros(max(epochs, 1), np.float32)
+    check(lib().fk_model_train(model, x.ctypes.data, t.ctypes.data, x.shape[0], epochs, batch, lr, seed,
+                               curve.ctypes.data))
+    return curve[:epochs]
+
+
+def fk_model_predict_batch(model: int, features):
+    import numpy as np
+    x = _f32(features)
+    out = np.zeros((x.shape[0], FK_MODEL_OUTPUTS), np.float32)
+    check(lib().fk_model_predict_batch(model, x.ctypes.data, x.shape[0], out.ctypes.data))
+    return out
+
+
+def fk_model_loss_grad(model: int, features, targets):
+    import numpy as np
+    x, t = _f32(features), _f32(targets)
+    loss = np.zeros(1, np.float32)
+    grad = np.zeros(fk_model_param_count(model), np.float32)
+    check(lib().fk_model_loss_grad(model, x.ctypes.data, t.ctypes.data, x.shape[0], loss.ctypes.data,
+                                   grad.ctypes.data))
+    return float(loss[0]), grad
+
+
+def fk_model_predict(model: int, plan: int, items, n: int) -> fk_launch_config:
+    c = fk_launch_config()
+    check(lib().fk_model_predict(model, plan, items, n, C.byref(c)))
+    return c
+
+
+def fk_plan_use_model(plan: int, model: int, items, n: int) -> None:
+    check(lib().fk_plan_use_model(plan, model, items, n))
+
+
+def fk_model_save(model: int, path: str) -> None:
+    check(lib().fk_model_save(model, path.encode()))
+
+
+def fk_model_load(path: str) -> int:
+    h = C.c_void_p()
+    check(lib().fk_model_load(path.encode(), C.byref(h)))
+    return h.value
+
+
+# -------------------------------------------------------------- server --
+
+def fk_server_clock() -> float:
+    return float(lib().fk_server_clock())
+
+
+def fk_server_create(opts: fk_server_opts) -> int:
+    h = C.c_void_p()
+    check(lib().fk_server_create(C.byref(opts), C.byref(h)))
+    return h.value
+
+
+def fk_server_submit(srv: int, req: fk_request) -> int:
+    t = C.c_uint64()
+    check(lib().fk_server_submit(srv, C.byref(req), C.byref(t)))
+    return t.value
+
+
+def fk_server_poll(srv: int, max_n: int = 256) -> list:
+    arr = (fk_completion * max_n)()
+    n = C.c_int32()
+    check(lib().fk_server_poll(srv, arr, max_n, C.byref(n)))
+    return [arr[i] for i in range(n.value)]
+
+
+def fk_server_release(srv: int, ticket: int) -> None:
+    check(lib().fk_server_release(srv, ticket))
+
+
+def fk_server_stats_get(srv: int) -> fk_server_stats:
+    st = fk_server_stats()
+    check(lib().fk_server_stats_get(srv, C.byref(st)))
+    return st
+
+
+def fk_server_destroy(srv: int) -> None:
+    check(lib().fk_server_destroy(srv))
+
+
+def server_opts(desc, arena, budget_bytes=0, max_batch_items=1024, max_inflight=3,
+                mode=FK_SERVER_BATCHED, strict=False, config=(0, 0)) -> fk_server_opts:
+    """Options for fk_server_create; `desc` from chain_desc() (kept alive by
+    the returned object), `arena` a uint8 device tensor."""
+    o = fk_server_opts()
+    o.chain = C.pointer(desc)
+    o.arena = arena.data_ptr()
+    o.arena_bytes = arena.numel()
+    o.budget_bytes = budget_bytes
+    o.max_batch_items = max_batch_items
+    o.max_inflight = max_inflight
+    o.mode = mode
+    o.strict_fp = int(bool(strict))
+    o.config.block_threads, o.config.coarsen = config
+    o._desc = desc
+    return o
+
+
+def make_request(frame, crops, t_arrival=None) -> fk_request:
+    """fk_request for a host frame tensor (H, W, C) (pinned for async copies)
+    and a list of crop dicts; keeps the crop array alive."""
+    arr = (fk_crop * len(crops))()
+    for i, c in enumerate(crops):
+        arr[i].x, arr[i].y, arr[i].w, arr[i].h = c["x"], c["y"], c["w"], c["h"]
+        arr[i].out_w, arr[i].out_h = c["out_w"], c["out_h"]
+    r = fk_request()
+    r.frame = frame.data_ptr()
+    r.height, r.width = int(frame.shape[0]), int(frame.shape[1])
+    r.pitch_bytes = int(frame.stride(0)) * frame.element_size()
+    r.crops = arr
+    r.n_crops = len(crops)
+    r.t_arrival = fk_server_clock() if t_arrival is None else t_arrival
+    r._crops = arr
+    return r
+
+
+def output_offsets(chain: dict, crops) -> list:
+    """Byte offset of each crop's output inside a completion's buffer."""
+    c = chain["read"]["channels"]
+    es = {"f32": 4, "f16": 2}[chain["write"]["dtype"]]
+    offs, off = [], 0
+    for cr in crops:
+        offs.append(off)
+        off = (off + cr["out_w"] * cr["out_h"] * c * es + 255) // 256 * 256
+    return offs
 
 
 def plan_opts(config_source=FK_CONFIG_DEFAULT, manual=(256, 1), use_graph=False, strict=False,

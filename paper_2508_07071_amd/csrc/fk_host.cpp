@@ -389,17 +389,6 @@ extern "C" fk_status fk_plan_create(const fk_chain_desc *chain, int32_t max_batc
         p->table_bytes = sizeof(RunHeader) + sizeof(ItemRec) * (size_t)max_batch +
                          sizeof(uint32_t) * ((size_t)max_batch + 1);
         p->table_bytes = (p->table_bytes + 255) & ~(size_t)255;
-        for (auto &sl : p->slots) {
-            if (e != hipSuccess)
-                break;
-            e = hipHostMalloc(&sl.h_stage, p->table_bytes, hipHostMallocDefault);
-            if (e == hipSuccess)
-                e = hipMalloc(&sl.d_table, p->table_bytes);
-            if (e == hipSuccess)
-                e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
-        }
-        if (e == hipSuccess)
-            e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
         if (e != hipSuccess) {
             plan_free(p);
             return e == hipErrorOutOfMemory ? set_error(FK_ERR_OUT_OF_MEMORY, "plan buffers")
@@ -587,7 +576,24 @@ fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_la
     }
     fk_plan::Slot &sl = p->slots[p->next_slot];
     p->next_slot = (p->next_slot + 1) % fk_plan::kRing;
-    hipError_t e;
+    hipError_t e = hipSuccess;
+    if (!sl.h_stage) {  // the table ring is allocated on first use
+        e = hipHostMalloc(&sl.h_stage, p->table_bytes, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipMalloc(&sl.d_table, p->table_bytes);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            free_slot(sl);
+            return e == hipErrorOutOfMemory ? set_error(FK_ERR_OUT_OF_MEMORY, "run table")
+                                            : hip_error(e, "run table");
+        }
+    }
+    if (graph && !p->capture_stream) {
+        e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
+        if (e != hipSuccess)
+            return hip_error(e, "hipStreamCreate");
+    }
     if (sl.used) {
         e = hipEventSynchronize(sl.done);
         if (e != hipSuccess)
@@ -708,11 +714,15 @@ extern "C" fk_status fk_autotune(fk_plan *plan, const fk_item *items, int32_t n_
         if (e != hipSuccess)
             return hip_error(e, "hipEventCreate");
         s = FK_OK;
+        // per config: one warm-up launch, then 3 samples of `reps`
+        // back-to-back launches between two events; the per-launch time is
+        // the median of the 3 sample averages
         for (int i = 0; i < n && !s; ++i) {
             std::vector<float> ts;
-            for (int r = 0; r < reps + 2 && !s; ++r) {
+            s = run_fused(plan, items, n_items, space[i], false, plan->tune_stream);
+            for (int r = 0; r < 3 && !s; ++r) {
                 e = hipEventRecord(t0, plan->tune_stream);
-                if (e == hipSuccess)
+                for (int k = 0; k < reps && e == hipSuccess && !s; ++k)
                     s = run_fused(plan, items, n_items, space[i], false, plan->tune_stream);
                 if (e == hipSuccess && !s)
                     e = hipEventRecord(t1, plan->tune_stream);
@@ -723,12 +733,11 @@ extern "C" fk_status fk_autotune(fk_plan *plan, const fk_item *items, int32_t n_
                     e = hipEventElapsedTime(&ms, t0, t1);
                 if (e != hipSuccess && !s)
                     s = hip_error(e, "autotune timing");
-                if (r >= 2)
-                    ts.push_back(ms);
+                ts.push_back(ms / (float)reps);
             }
             if (!s) {
                 std::sort(ts.begin(), ts.end());
-                med[i] = ts[ts.size() / 2];
+                med[i] = ts[1];
             }
         }
         (void)hipEventDestroy(t0);

@@ -53,7 +53,7 @@ struct RunHeader {      // per-run header read by the kernel (graph-friendly)
     int32_t pad[2];
 };
 
-constexpr int kInlineItems = 8;  // batches up to this size ride in the kernel arguments
+constexpr int kInlineItems = 32;  // batches up to this size ride in the kernel arguments
 
 // Kernel arguments (by value, the only kernel argument, so it starts the
 // kernarg segment).  Device table layout of one run:
