@@ -296,6 +296,34 @@ def hf_workload(args):
     return {"workload": "hf_batch_sweep (config 2 sizes)", "rows": rows}
 
 
+def serve_workload(args):
+    """Serving loop (config 4 sizes): open-loop Poisson arrivals, continuous
+    batching vs per-request fused vs per-request unfused; p50/p99 latency."""
+    import torch
+
+    from paper_2508_07071_amd import serve
+
+    import paper_2508_07071_amd as fk
+
+    dev = torch.device("cuda:0")
+    arena = torch.empty(args.arena_gb << 30, dtype=torch.uint8, device=dev)
+    pool = serve.make_pool(8, seed=args.seed)
+    rows = []
+    modes = [fk.FK_SERVER_BATCHED, fk.FK_SERVER_PER_REQUEST, fk.FK_SERVER_UNFUSED]
+    for rate in args.rates:
+        for mode in modes:
+            n = max(200, int(rate * args.serve_seconds))
+            if mode == fk.FK_SERVER_UNFUSED:
+                n = min(n, 400)  # the baseline saturates: bound its backlog
+            log(f"serve rate={rate} mode={mode} n={n}")
+            r = serve.run(rate, n, mode, pool, arena, seed=args.seed, budget_bytes=args.budget_gb << 30)
+            log(r)
+            rows.append(r)
+    return {"workload": "serving: Poisson arrivals, 640x480..3840x2160 u8 frames, 1-64 crops -> "
+                        "224x224 or 64x128 normalised planar fp32", "arena_gb": args.arena_gb,
+            "budget_gb": args.budget_gb, "rows": rows}
+
+
 def copy_workload(args):
     """Device-to-device copy of known size (torch's copy kernel): measured
     HBM bandwidth for context, and the reference for scaling rocprofv3's
@@ -328,7 +356,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="vf", choices=["vf", "hf", "copy"])
+    ap.add_argument("--workload", default="vf", choices=["vf", "hf", "copy", "serve"])
+    ap.add_argument("--rates", type=float, nargs="+", default=[200, 500, 1000, 2000])
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--arena-gb", type=int, default=16)
+    ap.add_argument("--budget-gb", type=int, default=0, help="0 = the whole arena")
     ap.add_argument("--rotate", type=int, default=4)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--strict", action="store_true")
@@ -348,6 +380,9 @@ def main():
 
     if args.workload == "hf":
         print(json.dumps(hf_workload(args)))
+        return
+    if args.workload == "serve":
+        print(json.dumps(serve_workload(args)))
         return
     if args.workload == "copy":
         print(json.dumps(copy_workload(args)))

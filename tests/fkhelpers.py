@@ -93,8 +93,14 @@ def assert_close(g, ref, s_floor=None, rel=1e-5, what=""):
         tol = tol + np.abs(r) * 2.0 ** -10 + 2.0 ** -24
     nan = np.isnan(r)
     assert np.array_equal(np.isnan(g), nan), f"{what}: NaN pattern differs"
-    err = np.abs(g - r)
+    with np.errstate(invalid="ignore"):
+        err = np.abs(g - r)
     err[nan] = 0
+    if ref["out"].dtype == np.float16:
+        # at the fp16 overflow boundary one side may round to +-inf, the other
+        # to +-65504: both mean "out of fp16 range" with the same sign
+        big = (np.abs(r) >= 65504) & (np.abs(g) >= 65504) & (np.sign(r) == np.sign(g))
+        err[big] = 0
     bad = err > tol
     assert not bad.any(), f"{what}: {bad.sum()} elements beyond tolerance, worst {err.max():.3g} " \
                           f"(tol there {tol.ravel()[np.argmax(err)]:.3g})"

@@ -305,3 +305,32 @@ def test_invalid_runs_return_status_and_launch_nothing():
         assert torch.isnan(outs[0]).all()
         with pytest.raises(fk.FKError):
             fk.fk_plan_set_config(p.h, fk.fk_launch_config(100, 1))
+
+
+# ------------------------------------------- random chains (cost-model set) --
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_chains_match_oracle(seed):
+    """Chains drawn like the cost model's dataset (any read kind, dtype,
+    channel count, op mix, layout and output dtype), at reduced sizes."""
+    say("random chains, seed", seed)
+    g = datagen.rng(500 + seed)
+    for k in range(10):
+        spec = datagen.random_chain_spec(g, max_ops=64, side=(16, 300), max_batch=4)
+        ch = spec["chain"]
+        fh, fw = spec["frame_hw"]
+        frames = [datagen.frame(g, fh, fw, ch["read"]["channels"], dtype=ch["read"]["dtype"])
+                  for _ in range(spec["batch"])]
+        items = spec["items"]
+        refs = oracle.run_chain(ch, frames, items)
+        dframes = to_dev(frames)
+        for strict in (True, False):
+            with Plan(ch, len(items), strict=strict) as p:
+                outs = host(p.run(dframes, items))
+            for b, (o, r) in enumerate(zip(outs, refs)):
+                what = f"chain {k} item {b} ({ch['read']['kind']} {ch['read']['dtype']}x{ch['read']['channels']} " \
+                       f"{len(ch['ops'])} ops -> {ch['write']['dtype']} {ch['write']['layout']})"
+                if strict:
+                    assert_bitexact(o, r["out"], what)
+                else:
+                    assert_close(o, r, what=what)

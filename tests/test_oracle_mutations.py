@@ -1,0 +1,95 @@
+"""The oracle's pins are strong enough: each plausible mistake planted in a
+copy of the oracle (a dropped term, a wrong sign or index, a transposed
+operand) makes at least one pin fail.  Runs on the CPU only."""
+import ctypes
+import os
+import subprocess
+import tempfile
+
+import pytest
+
+import oracle
+import test_oracle_pins as pins
+
+SRC = open(oracle.SRC).read()
+
+# (name, text in fk_oracle.c, planted replacement); every variant stays in
+# bounds of its buffers
+MUTATIONS = [
+    ("half-pixel offset dropped", "fmaf((float)o + 0.5f, scale, -0.5f)", "fmaf((float)o + 0.5f, scale, 0.0f)"),
+    ("vertical lerp uses the x weight", "float v = fmaf(ay, bot - top, top);", "float v = fmaf(ax, bot - top, top);"),
+    ("second tap dropped", "*i1 = lo + 1 < in_size ? lo + 1 : in_size - 1;", "*i1 = lo;"),
+    ("coordinate not clamped at 0", "    if (s < 0.0f)\n        s = 0.0f;\n", ""),
+    ("swap exchanges channels 0 and 1", "size_t a = p * (size_t)m->C, b = a + 2;", "size_t a = p * (size_t)m->C, b = a + 1;"),
+    ("per-channel constant index ignored", "float k = op->nconst == 1 ? op->k[0] : op->k[c];", "float k = op->k[0];"),
+    ("planar plane transposed",
+     "((size_t)c * (size_t)m->h + (size_t)y) * (size_t)m->w + (size_t)x",
+     "((size_t)c * (size_t)m->w + (size_t)x) * (size_t)m->h + (size_t)y"),
+    ("subtraction sign flipped", "case ORC_SUB: r = v - k;", "case ORC_SUB: r = k - v;"),
+    ("division by reciprocal", "default:      r = v / k;", "default:      r = v * (1.0f / k);"),
+    ("crop x offset dropped", "frame_elem(it, ch->in_dtype, C, it->x + i, it->y + j, c)", "frame_elem(it, ch->in_dtype, C, i, it->y + j, c)"),
+    ("fp16 rounding truncates", "double q = nearbyint(ldexp(a, -ulp_exp));", "double q = floor(ldexp(a, -ulp_exp));"),
+    ("mul and add exchanged", "case ORC_MUL: r = v * k;", "case ORC_MUL: r = v + k;"),
+]
+
+PINS = [
+    ("test_resize_same_size_is_identity", {}),
+    ("test_resize_constant_image_stays_constant", {"src": (100, 60), "dst": (37, 91)}),
+    ("test_resize_linear_ramp_is_source_coordinate", {"w": 200, "h": 150, "ow": 64, "oh": 128}),
+    ("test_resize_linear_ramp_is_source_coordinate", {"w": 60, "h": 90, "ow": 224, "oh": 224}),
+    ("test_resize_integer_downscale_is_box_mean", {"f": 2}),
+    ("test_resize_2x_upscale_weights_quarter_three_quarters", {}),
+    ("test_resize_matches_torch_bilinear", {"seed": 0}),
+    ("test_crop_swap_split_index_coded", {"layout": "planar", "kind": "crop_resize"}),
+    ("test_crop_swap_split_index_coded", {"layout": "packed", "kind": "plain"}),
+    ("test_per_channel_constants_follow_swapped_positions", {}),
+    ("test_normalise_chain_is_per_op_ieee_fp32", {}),
+    ("test_muladd_chain_matches_affine_closed_form", {"n_ops": 4}),
+    ("test_division_is_true_division_not_reciprocal", {}),
+    ("test_float_to_half_round_to_nearest_even_matches_numpy", {}),
+]
+
+
+def build_variant(src_text, path):
+    c = path + ".c"
+    with open(c, "w") as f:
+        f.write(src_text)
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-fno-fast-math", "-ffp-contract=off", "-fPIC",
+                           "-shared", "-w", "-o", path, c, "-lm"])
+
+
+def load_as_oracle(path, monkeypatch):
+    L = ctypes.CDLL(path)
+    real = oracle.lib()
+    for name in ("orc_run", "orc_validate", "orc_resize_f32", "orc_half_to_float", "orc_float_to_half"):
+        fn = getattr(L, name)
+        fn.argtypes = getattr(real, name).argtypes
+        fn.restype = getattr(real, name).restype
+    monkeypatch.setattr(oracle, "_lib", L)
+
+
+def caught_by_pins():
+    for name, kw in PINS:
+        try:
+            getattr(pins, name)(**kw)
+        except AssertionError:
+            return name
+    return None
+
+
+def test_unmodified_oracle_passes_the_pin_subset(monkeypatch):
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "orig.so")
+        build_variant(SRC, path)
+        load_as_oracle(path, monkeypatch)
+        assert caught_by_pins() is None
+
+
+@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_planted_mistake_is_caught(name, old, new, monkeypatch):
+    assert SRC.count(old) == 1, f"mutation site for '{name}' not found exactly once"
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "mut.so")
+        build_variant(SRC.replace(old, new), path)
+        load_as_oracle(path, monkeypatch)
+        assert caught_by_pins() is not None, f"no pin caught: {name}"
