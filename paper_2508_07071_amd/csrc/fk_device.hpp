@@ -125,6 +125,7 @@ __device__ __forceinline__ void store_elem<DT_F16>(gdst_t p, float v)
 template <int DT, int C>
 struct ReadPlain {
     static constexpr int kind = RD_PLAIN;
+    static constexpr int elem_size = DSize<DT>::v;
     __device__ __forceinline__ static void load(const ItemRec &it, int oy, int ox0, int n,
                                                 float (&r)[kUnitPx][C])
     {
@@ -168,9 +169,54 @@ __device__ __forceinline__ void bilinear_coord(int o, float scale, int in_size, 
 }
 
 // Crop + bilinear resize: the ROI resized to (ow, oh).
+//
+// u8 frames: each tap row of a pixel (its two neighbouring source pixels,
+// 2C bytes) is fetched as one dword-aligned window of WB bytes and the bytes
+// are picked out with v_alignbyte -- one load instead of 2C byte loads.  A
+// window may extend up to WB - 1 bytes past the last tapped pixel and 3
+// bytes before the first, so it is used only when the frame base is dword
+// aligned, a frame row holds at least WB bytes, and either the ROI stops
+// above the frame's last row or its last window still ends inside that
+// row.  Other items, and fp16/fp32 frames, load element by element.
 template <int DT, int C>
 struct ReadCropResize {
     static constexpr int kind = RD_CROP_RESIZE;
+    static constexpr int elem_size = DSize<DT>::v;
+    static constexpr int WB = (C == 1) ? 8 : 12;  // window bytes
+
+    __device__ __forceinline__ static bool window_ok(const ItemRec &it)
+    {
+        if constexpr (DT != DT_U8) {
+            return false;
+        } else {
+            // the overrun past a row's last pixel stays inside the row, or
+            // inside the next row (which holds at least WB bytes)
+            return (it.src % 4 == 0) && C * (int)it.fw >= WB &&
+                   (it.y + it.h < (int)it.fh || C * (it.x + it.w - 1) + WB <= C * (int)it.fw);
+        }
+    }
+
+    // bytes [0, 2C) of the tap pair starting at absolute address `addr`
+    __device__ __forceinline__ static void window(uint64_t addr, uint32_t (&d)[2])
+    {
+        const FK_GLOBAL uint32_t *p = (const FK_GLOBAL uint32_t *)(addr & ~(uint64_t)3);
+        const uint32_t sh = (uint32_t)(addr & 3);
+        if constexpr (WB == 8) {
+            const uint32_t w0 = p[0], w1 = p[1];
+            d[0] = __builtin_amdgcn_alignbyte(w1, w0, sh);
+            d[1] = 0;
+        } else {
+            const uint32_t w0 = p[0], w1 = p[1], w2 = p[2];
+            d[0] = __builtin_amdgcn_alignbyte(w1, w0, sh);
+            d[1] = __builtin_amdgcn_alignbyte(w2, w1, sh);
+        }
+    }
+
+    __device__ __forceinline__ static float byte_at(const uint32_t (&d)[2], int k)
+    {
+        return (float)((d[k >> 2] >> (8 * (k & 3))) & 0xffu);
+    }
+
     __device__ __forceinline__ static void load(const ItemRec &it, int oy, int ox0, int n,
                                                 float (&r)[kUnitPx][C])
     {
@@ -181,20 +227,39 @@ struct ReadCropResize {
         gsrc_t base = (gsrc_t)it.src + (int64_t)it.x * (C * ES);
         gsrc_t r0 = base + (int64_t)(it.y + y0) * it.pitch;
         gsrc_t r1 = base + (int64_t)(it.y + y1) * it.pitch;
+        const bool win = window_ok(it);
 #pragma unroll
         for (int i = 0; i < kUnitPx; ++i) {
             if (i < n) {
                 int x0, x1;
                 float ax;
                 bilinear_coord(ox0 + i, it.sx, it.w, x0, x1, ax);
+                float p00[C], p01[C], p10[C], p11[C];
+                if (DT == DT_U8 && win) {
+                    uint32_t t[2], b[2];
+                    window((uint64_t)(uintptr_t)(r0 + x0 * C), t);
+                    window((uint64_t)(uintptr_t)(r1 + x0 * C), b);
+                    const int o1 = (x1 == x0) ? 0 : C;  // clamped tap: the same pixel
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        p00[c] = byte_at(t, c);
+                        p01[c] = byte_at(t, o1 + c);
+                        p10[c] = byte_at(b, c);
+                        p11[c] = byte_at(b, o1 + c);
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        p00[c] = load_elem<DT>(r0 + (x0 * C + c) * ES);
+                        p01[c] = load_elem<DT>(r0 + (x1 * C + c) * ES);
+                        p10[c] = load_elem<DT>(r1 + (x0 * C + c) * ES);
+                        p11[c] = load_elem<DT>(r1 + (x1 * C + c) * ES);
+                    }
+                }
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
-                    const float p00 = load_elem<DT>(r0 + (x0 * C + c) * ES);
-                    const float p01 = load_elem<DT>(r0 + (x1 * C + c) * ES);
-                    const float p10 = load_elem<DT>(r1 + (x0 * C + c) * ES);
-                    const float p11 = load_elem<DT>(r1 + (x1 * C + c) * ES);
-                    const float top = fmaf(ax, p01 - p00, p00);
-                    const float bot = fmaf(ax, p11 - p10, p10);
+                    const float top = fmaf(ax, p01[c] - p00[c], p00[c]);
+                    const float bot = fmaf(ax, p11[c] - p10[c], p10[c]);
                     r[i][c] = fmaf(ay, bot - top, top);
                 }
             } else {
@@ -632,8 +697,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_transform(const KArgs a)
     // larger ones, and graph replays, read the device table.
     const FK_CONST KArgs *ka = (const FK_CONST KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
     const bool inl = a.inl_n > 0;
-    const FK_CONST uint32_t *tb = inl ? ka->inl_tile_begin : cptr(a.tile_begin);
-    const FK_CONST ItemRec *items = inl ? ka->inl_items : cptr(a.items);
+    const bool compact = inl && a.inl_compact;
+    const FK_CONST uint32_t *tb =
+        inl ? (const FK_CONST uint32_t *)(ka->inl + kInlineTileBegin) : cptr(a.tile_begin);
+    const FK_CONST ItemRec *items = inl ? (const FK_CONST ItemRec *)ka->inl : cptr(a.items);
     const int n_items = inl ? a.inl_n : cptr(a.hdr)->n_items;
     const uint32_t total = inl ? a.inl_total_tiles : cptr(a.hdr)->total_tiles;
     const int T = blockDim.x;
@@ -643,10 +710,36 @@ __global__ __launch_bounds__(kMaxBlock) void k_transform(const KArgs a)
     const bool swap = a.swap != 0;
 
     for (uint32_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
-        const int b = find_item(tb, n_items, tile);
-        const ItemRec it = load_item(items + b);
-        const uint32_t units = (uint32_t)it.upr * (uint32_t)it.oh;
-        const uint32_t ubase = (tile - tb[b]) * tile_units;
+        int b;
+        ItemRec it;
+        uint32_t first_tile;
+        if (compact) {
+            b = (int)(tile / a.inl_tiles_per_item);
+            first_tile = (uint32_t)b * a.inl_tiles_per_item;
+            it = load_item(items);  // the template (item 0)
+            const FK_CONST Roi16 *roi = (const FK_CONST Roi16 *)(ka->inl + 64) + b;
+            it.x = roi->x;
+            it.y = roi->y;
+            it.w = roi->w;
+            it.h = roi->h;
+            it.dst += (uint64_t)b * (uint64_t)a.inl_dst_stride;
+            if constexpr (Read::kind == RD_CROP_RESIZE) {
+                // the same IEEE fp32 divisions the host performs for the table forms
+                it.sx = (float)it.w / (float)it.ow;
+                it.sy = (float)it.h / (float)it.oh;
+            }
+            // template bit: frame base and pitch dword-aligned; the ROI's
+            // column offset decides the rest
+            if ((it.x * C * Read::elem_size) % 4 != 0)
+                it.flags &= ~IF_SRC_VEC;
+        } else {
+            b = find_item(tb, n_items, tile);
+            it = load_item(items + b);
+            first_tile = tb[b];
+        }
+        const uint32_t upr = (uint32_t)(it.ow + kUnitPx - 1) / kUnitPx;
+        const uint32_t units = upr * (uint32_t)it.oh;
+        const uint32_t ubase = (tile - first_tile) * tile_units;
 
         float v[K][kUnitPx][C];
         int oy[K], ox0[K], nv[K];
@@ -654,9 +747,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_transform(const KArgs a)
         for (int j = 0; j < K; ++j) {
             const uint32_t u = ubase + (uint32_t)(j * T + tid);
             if (u < units) {
-                const uint32_t row = u / (uint32_t)it.upr;
+                const uint32_t row = u / upr;
                 oy[j] = (int)row;
-                ox0[j] = (int)(u - row * (uint32_t)it.upr) * kUnitPx;
+                ox0[j] = (int)(u - row * upr) * kUnitPx;
                 const int left = it.ow - ox0[j];
                 nv[j] = left < kUnitPx ? left : kUnitPx;
                 Read::load(it, oy[j], ox0[j], nv[j], v[j]);

@@ -109,6 +109,8 @@ fk_status fk::validate_items(const fk_chain_desc *ch, const fk_item *items, int3
             return set_error(FK_ERR_INVALID_ARG, "item %d: null src or dst", b);
         if (it.src.width < 1 || it.src.height < 1)
             return set_error(FK_ERR_INVALID_ARG, "item %d: empty frame", b);
+        if (it.src.width > 65535 || it.src.height > 65535)
+            return set_error(FK_ERR_UNSUPPORTED, "item %d: frame sides above 65535", b);
         if (it.src.pitch_bytes < it.src.width * C * es || it.src.pitch_bytes % es != 0)
             return set_error(FK_ERR_INVALID_ARG, "item %d: bad pitch %lld", b,
                              (long long)it.src.pitch_bytes);
@@ -486,7 +488,9 @@ uint32_t fk::build_items(const fk_plan *p, const fk_item *items, int32_t n,
             r.sx = 1.0f;
             r.sy = 1.0f;
         }
-        r.upr = (r.ow + kUnitPx - 1) / kUnitPx;
+        r.fw = (uint16_t)it.src.width;
+        r.fh = (uint16_t)it.src.height;
+        const int64_t upr = (r.ow + kUnitPx - 1) / kUnitPx;
         int flags = 0;
         if ((uintptr_t)it.src.ptr % 4 == 0 && it.src.pitch_bytes % 4 == 0 &&
             ((int64_t)it.x * C * es_in) % 4 == 0)
@@ -496,7 +500,7 @@ uint32_t fk::build_items(const fk_plan *p, const fk_item *items, int32_t n,
         (void)es_out;
         r.flags = flags;
         tb[b] = (uint32_t)tiles;
-        const uint64_t units = (uint64_t)r.upr * (uint64_t)r.oh;
+        const uint64_t units = (uint64_t)upr * (uint64_t)r.oh;
         tiles += (units + tile_units - 1) / tile_units;
     }
     tb[n] = (uint32_t)tiles;
@@ -560,6 +564,31 @@ fk_status fk::launch(const fk_plan *p, const fk_launch_config &cfg, void *d_tabl
     return launch_args(p, cfg, a, grid, stream);
 }
 
+// A batch that can travel in the compact kernel-argument form: one frame,
+// one output size, outputs at a constant non-negative stride, coordinates
+// that fit 16 bits.
+bool fk::compact_batch(const fk_plan *p, const fk_item *items, int32_t n)
+{
+    if (n < 2)
+        return false;
+    const fk_item &f = items[0];
+    const bool rs = p->chain.read.kind == FK_READ_CROP_RESIZE;
+    const intptr_t stride = (intptr_t)items[1].dst - (intptr_t)items[0].dst;
+    if (stride < 0 || f.src.width > 65535 || f.src.height > 65535)
+        return false;
+    for (int32_t b = 0; b < n; ++b) {
+        const fk_item &it = items[b];
+        if (it.src.ptr != f.src.ptr || it.src.width != f.src.width ||
+            it.src.height != f.src.height || it.src.pitch_bytes != f.src.pitch_bytes)
+            return false;
+        if ((intptr_t)it.dst != (intptr_t)f.dst + (intptr_t)b * stride)
+            return false;
+        if (rs ? (it.out_w != f.out_w || it.out_h != f.out_h) : (it.w != f.w || it.h != f.h))
+            return false;
+    }
+    return true;
+}
+
 fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_launch_config &cfg,
                         bool graph, hipStream_t stream)
 {
@@ -570,7 +599,34 @@ fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_la
         a.items = nullptr;
         a.tile_begin = nullptr;
         a.inl_n = n;
-        a.inl_total_tiles = build_items(p, items, n, cfg, a.inl_items, a.inl_tile_begin);
+        a.inl_total_tiles = build_items(p, items, n, cfg, (ItemRec *)a.inl,
+                                        (uint32_t *)(a.inl + kInlineTileBegin));
+        const uint32_t grid = std::min<uint32_t>(a.inl_total_tiles, 1u << 20);
+        return launch_args(p, cfg, a, grid, stream);
+    }
+    if (!graph && n <= kCompactItems && compact_batch(p, items, n)) {
+        KArgs a = make_args(p, nullptr);
+        a.hdr = nullptr;
+        a.items = nullptr;
+        a.tile_begin = nullptr;
+        a.inl_n = n;
+        a.inl_compact = 1;
+        uint32_t tb[2];
+        ItemRec &t = *(ItemRec *)a.inl;
+        a.inl_tiles_per_item = build_items(p, items, 1, cfg, &t, tb);
+        a.inl_total_tiles = a.inl_tiles_per_item * (uint32_t)n;
+        a.inl_dst_stride = (int64_t)((uintptr_t)items[1].dst - (uintptr_t)items[0].dst);
+        // template flags: frame base and pitch dword-aligned; outputs aligned
+        // for every item (base and stride multiples of 16)
+        t.flags = 0;
+        if ((uintptr_t)items[0].src.ptr % 4 == 0 && items[0].src.pitch_bytes % 4 == 0)
+            t.flags |= IF_SRC_VEC;
+        if (t.ow % kUnitPx == 0 && (uintptr_t)items[0].dst % 16 == 0 && a.inl_dst_stride % 16 == 0)
+            t.flags |= IF_DST_VEC;
+        Roi16 *roi = (Roi16 *)(a.inl + 64);
+        for (int32_t b = 0; b < n; ++b)
+            roi[b] = Roi16{(uint16_t)items[b].x, (uint16_t)items[b].y, (uint16_t)items[b].w,
+                           (uint16_t)items[b].h};
         const uint32_t grid = std::min<uint32_t>(a.inl_total_tiles, 1u << 20);
         return launch_args(p, cfg, a, grid, stream);
     }

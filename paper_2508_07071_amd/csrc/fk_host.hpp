@@ -61,6 +61,7 @@ fk_status launch_args(const fk_plan *p, const fk_launch_config &cfg, KArgs &a, u
                       hipStream_t stream);
 fk_status launch(const fk_plan *p, const fk_launch_config &cfg, void *d_table, uint32_t grid,
                  hipStream_t stream);
+bool compact_batch(const fk_plan *p, const fk_item *items, int32_t n);
 fk_status run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_launch_config &cfg,
                     bool graph, hipStream_t stream);
 

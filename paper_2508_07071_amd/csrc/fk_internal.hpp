@@ -42,7 +42,7 @@ struct ItemRec {        // 64 bytes: one batch slot's parameters
     int32_t x, y, w, h; // region of interest in the frame
     int32_t ow, oh;     // output size
     float sx, sy;       // crop+resize scales w/ow and h/oh (fp32)
-    int32_t upr;        // units per output row = ceil(ow / kUnitPx)
+    uint16_t fw, fh;    // frame size in pixels (bounds of window reads)
     int32_t flags;      // IF_*
 };
 static_assert(sizeof(ItemRec) == 64, "ItemRec layout");
@@ -53,7 +53,25 @@ struct RunHeader {      // per-run header read by the kernel (graph-friendly)
     int32_t pad[2];
 };
 
-constexpr int kInlineItems = 32;  // batches up to this size ride in the kernel arguments
+// Small batches ride in the kernel arguments instead of a device table:
+//  - full:    ItemRec[inl_n] at inl[0..], uint32 tile_begin[inl_n + 1] at
+//             inl[kInlineTileBegin..] (inl_n <= kInlineItems);
+//  - compact: items sharing one frame, one output size and a constant
+//             output stride: an ItemRec template at inl[0..64) (item 0) and
+//             one Roi16 (x, y, w, h) per item at inl[64 + 8 b]
+//             (inl_n <= kCompactItems); item b owns tiles
+//             [b * inl_tiles_per_item, (b + 1) * inl_tiles_per_item).
+#ifndef FK_INLINE_BYTES
+#define FK_INLINE_BYTES 2560
+#endif
+constexpr int kInlineBytes = FK_INLINE_BYTES;
+constexpr int kInlineItems = (kInlineBytes - 4) / 68 < 32 ? (kInlineBytes - 4) / 68 : 32;
+constexpr int kInlineTileBegin = kInlineItems * 64;
+constexpr int kCompactItems = (kInlineBytes - 64) / 8;  // 312
+
+struct Roi16 {
+    uint16_t x, y, w, h;
+};
 
 // Kernel arguments (by value, the only kernel argument, so it starts the
 // kernarg segment).  Device table layout of one run:
@@ -67,10 +85,13 @@ struct KArgs {
     int32_t n_ops;
     int32_t swap;          // net BGR<->RGB swap applied at the read
     int32_t strict;        // compile-time tier: 1 = no contraction
-    int32_t inl_n;         // > 0: the run's items are inl_items[0..inl_n)
+    int32_t inl_n;         // > 0: the run's items are in `inl`
+    int32_t inl_compact;   // 1: compact form
     uint32_t inl_total_tiles;
-    uint32_t inl_tile_begin[kInlineItems + 1];
-    ItemRec inl_items[kInlineItems];
+    uint32_t inl_tiles_per_item;  // compact form
+    int32_t pad;
+    int64_t inl_dst_stride;       // compact form: bytes between item outputs
+    alignas(16) uint8_t inl[kInlineBytes];
 };
 
 // Kernel families.

@@ -75,6 +75,7 @@ struct Req {
     std::vector<fk_crop> crops;
     std::vector<int64_t> out_off;  // relative to the block
     int64_t frame_bytes = 0, out_bytes = 0, scratch_bytes = 0, block_bytes = 0;
+    int64_t dev_pitch = 0;         // row pitch of the frame on the device
     int64_t off = -1;              // block offset in the arena
     hipEvent_t ready = nullptr;    // frame copy done
     int launched = 0, done = 0;
@@ -179,7 +180,7 @@ fk_item crop_item(fk_server *s, Req *r, int i)
     it.src.ptr = base + r->out_bytes;  // the frame follows the outputs
     it.src.width = r->desc.width;
     it.src.height = r->desc.height;
-    it.src.pitch_bytes = (int64_t)r->desc.width * s->C * s->es_in;
+    it.src.pitch_bytes = r->dev_pitch;
     it.x = c.x;
     it.y = c.y;
     it.w = c.w;
@@ -207,8 +208,9 @@ bool admit(fk_server *s)
         uint8_t *dframe = (uint8_t *)s->opts.arena + off + r->out_bytes;
         const int64_t row = (int64_t)r->desc.width * s->C * s->es_in;
         hipError_t e;
-        if (r->desc.pitch_bytes == row)
-            e = hipMemcpyAsync(dframe, r->desc.frame, (size_t)(row * r->desc.height),
+        if (r->dev_pitch == r->desc.pitch_bytes)  // one contiguous copy, rows keep their pitch
+            e = hipMemcpyAsync(dframe, r->desc.frame,
+                               (size_t)((r->desc.height - 1) * r->dev_pitch + row),
                                hipMemcpyHostToDevice, s->copy_stream);
         else
             e = hipMemcpy2DAsync(dframe, (size_t)row, r->desc.frame, (size_t)r->desc.pitch_bytes,
@@ -476,7 +478,11 @@ extern "C" fk_status fk_server_submit(fk_server *s, const fk_request *req, uint6
             off = align256(off + (int64_t)c.out_w * c.out_h * s->C * s->es_out);
         }
         r->out_bytes = off;
-        r->frame_bytes = align256((int64_t)req->width * req->height * s->C * s->es_in);
+        // a pitched frame is copied in one piece (rows keep the host pitch)
+        // unless its padding would more than double the bytes moved
+        const int64_t row = (int64_t)req->width * s->C * s->es_in;
+        r->dev_pitch = req->pitch_bytes <= 2 * row ? req->pitch_bytes : row;
+        r->frame_bytes = align256((int64_t)(req->height - 1) * r->dev_pitch + row);
         if (s->opts.mode == FK_SERVER_UNFUSED) {
             int64_t need = 0;
             for (int i = 0; i < req->n_crops; ++i) {
@@ -484,7 +490,7 @@ extern "C" fk_status fk_server_submit(fk_server *s, const fk_request *req, uint6
                 it.src.ptr = (void *)(uintptr_t)256;
                 it.src.width = req->width;
                 it.src.height = req->height;
-                it.src.pitch_bytes = (int64_t)req->width * s->C * s->es_in;
+                it.src.pitch_bytes = r->dev_pitch;
                 const fk_crop &c = r->crops[(size_t)i];
                 it.x = c.x;
                 it.y = c.y;

@@ -3,8 +3,8 @@
 Poisson arrivals at a fixed rate; each request is one uint8 BGR frame
 (sides uniform in 640x480 .. 3840x2160) with 1..64 crops, each resized to
 224x224 or 64x128 (width x height) and normalised to planar fp32.  Frames
-come from a pool of pinned host buffers (a request's frame is the top-left
-W x H of a pool frame, row pitch 3840 pixels).  Latency = completion time -
+come from a pool of pinned host buffers: a request's W x H frame is a dense
+image over the first W*H*3 bytes of a pool frame.  Latency = completion time -
 scheduled arrival time on the server's monotonic clock.
 """
 from __future__ import annotations
@@ -43,7 +43,8 @@ def run(rate_hz, n_requests, mode, pool, arena, seed=0, warmup_frac=0.1, max_bat
         built = []
         for i, r in enumerate(reqs):
             fh, fw = r["frame_hw"]
-            frame = pool[i % len(pool)][:fh, :fw]
+            # a dense fh x fw x 3 image over the pool frame's (random) bytes
+            frame = pool[i % len(pool)].view(-1)[:fh * fw * 3].view(fh, fw, 3)
             built.append(fk.make_request(frame, r["crops"], 0.0))
             in_bytes += fh * fw * 3
             crops += len(r["crops"])

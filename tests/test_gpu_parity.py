@@ -334,3 +334,39 @@ def test_random_chains_match_oracle(seed):
                     assert_bitexact(o, r["out"], what)
                 else:
                     assert_close(o, r, what=what)
+
+
+# ------------------------------------------ compact kernel-argument batches --
+
+def test_compact_argument_batches_match_table_path_and_oracle():
+    """Batches of one frame, one output size and a constant output stride
+    travel in the kernel arguments (up to 312 items); the table path (graph
+    replay) and the oracle agree with them bit for bit."""
+    say("compact batches")
+    cfg = datagen.config2(50, seed=8)
+    dframes = to_dev(cfg["frames"])
+    out_c = torch.full((50, 3, 128, 64), float("nan"), dtype=torch.float32, device="cuda:0")
+    out_t = torch.full((50, 3, 128, 64), float("nan"), dtype=torch.float32, device="cuda:0")
+    with Plan(cfg["chain"], 50, strict=True) as pc, Plan(cfg["chain"], 50, strict=True, use_graph=True) as pt:
+        pc.run(dframes, cfg["items"], outs=[out_c[b] for b in range(50)])
+        pt.run(dframes, cfg["items"], outs=[out_t[b] for b in range(50)])
+        a, b = host([out_c, out_t])
+    assert_bitexact(a, b, "compact vs table")
+    refs = oracle.run_chain(cfg["chain"], cfg["frames"], cfg["items"][::7])
+    for k, r in zip(range(0, 50, 7), refs):
+        assert_bitexact(a[k], r["out"], f"item {k}")
+    # plain reads: equal-size ROIs at odd offsets (unaligned source rows)
+    g = datagen.rng(9)
+    fr = datagen.frame(g, 200, 301, 3)
+    chain = {"read": {"kind": "plain", "dtype": "u8", "channels": 3, "out_w": 0, "out_h": 0},
+             "ops": [{"kind": "swap", "k": []}, {"kind": "mul", "k": [0.5]}, {"kind": "add", "k": [1.0, 2.0, 3.0]}],
+             "write": {"dtype": "f32", "layout": "packed"}}
+    items = [{"frame": 0, "x": int(g.integers(0, 301 - 37)), "y": int(g.integers(0, 200 - 21)), "w": 37, "h": 21,
+              "out_w": 37, "out_h": 21} for _ in range(40)]
+    out = torch.full((40, 21, 37, 3), float("nan"), dtype=torch.float32, device="cuda:0")
+    with Plan(chain, 40, strict=True) as p:
+        p.run(to_dev([fr]), items, outs=[out[b] for b in range(40)])
+        o = host([out])[0]
+    refs = oracle.run_chain(chain, [fr], items)
+    for k in range(40):
+        assert_bitexact(o[k], refs[k]["out"], f"plain item {k}")
