@@ -84,26 +84,25 @@ def vf_sweep(args):
 
     counter = [0]
 
-    def step(events=None):
+    def step(events=None, i=0):
         for n in DEPTHS:
             r = counter[0] % R
             counter[0] += 1
             if events is not None:
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record()
+                events[n][i][0].record()
             fk.fk_run(plans[n][0], items_by_set[n][r], 1, stream)
             if events is not None:
-                e1.record()
-                events[n].append((e0, e1))
+                events[n][i][1].record()
 
     for _ in range(args.warmup):
         step()
+    # timing events are created up front: none is created inside the timed loop
+    events = {n: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(args.steps)] for n in DEPTHS}
     torch.cuda.synchronize()
-    events = {n: [] for n in DEPTHS}
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(events)
+    for i in range(args.steps):
+        step(events, i)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -298,7 +297,17 @@ def hf_workload(args):
         log(res)
         rows.append(res)
     rows.append(hf_large(args))
-    return {"workload": "hf_batch_sweep (config 2 sizes)", "rows": rows}
+    out = {"workload": "hf_batch_sweep (config 2 sizes)", "rows": rows}
+    if not args.no_cpu_baseline:
+        import datagen
+        import oracle
+        cfg = datagen.config2(50, seed=args.seed)
+        t0 = time.perf_counter()
+        oracle.run_chain(cfg["chain"], cfg["frames"], cfg["items"], shadow=True)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(50 / dt, 1), "unit": "crops/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the B=50 batch (64x128 outputs), {dt:.2f} s single-threaded"}
+    return out
 
 
 def hf_large(args, n_frames=8, per_frame=512):
@@ -362,9 +371,55 @@ def serve_workload(args):
             r = serve.run(rate, n, mode, pool, arena, seed=args.seed, budget_bytes=args.budget_gb << 30)
             log(r)
             rows.append(r)
-    return {"workload": "serving: Poisson arrivals, 640x480..3840x2160 u8 frames, 1-64 crops -> "
-                        "224x224 or 64x128 normalised planar fp32", "arena_gb": args.arena_gb,
-            "budget_gb": args.budget_gb, "rows": rows}
+    out = {"workload": "serving: Poisson arrivals, 640x480..3840x2160 u8 frames, 1-64 crops -> "
+                       "224x224 or 64x128 normalised planar fp32", "arena_gb": args.arena_gb,
+           "budget_gb": args.budget_gb, "rows": rows}
+    if not args.no_cpu_baseline:
+        import datagen
+        import oracle
+        g = datagen.rng(args.seed)
+        reqs = datagen.poisson_requests(g, 200.0, 10)
+        chain = datagen.normalize_chain(224, 224)
+        t0 = time.perf_counter()
+        for i, r in enumerate(reqs):
+            fh, fw = r["frame_hw"]
+            frame = pool[i % len(pool)].numpy().reshape(-1)[:fh * fw * 3].reshape(fh, fw, 3)
+            oracle.run_chain(chain, [frame], [dict(c, frame=0) for c in r["crops"]], shadow=True)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(len(reqs) / dt, 2), "unit": "req/s", "cores": 1, "kind": "oracle",
+                               "sample": f"10 requests of the same distribution, {dt:.2f} s single-threaded"}
+    return out
+
+
+def costmodel_workload(args):
+    """Learned cost model (config 3): train on the GPU from labelled shards,
+    evaluate on the held-out chains; the fp64 numpy oracle's epoch time is
+    the CPU baseline."""
+    import numpy as np
+
+    import paper_2508_07071_amd as fk
+    from paper_2508_07071_amd import costmodel as cm
+
+    data = cm.load_shards(args.data)
+    model, rep = cm.fit(data, epochs=args.epochs)
+    out = {"workload": "cost model: 20,000 training / 2,000 held-out random chains", "report": rep}
+    if not args.no_cpu_baseline:
+        from oracle import mlp
+        X = data["features"][:rep["n_train"]]
+        Y = cm.targets_from_times(data["times_ms"][:rep["n_train"]])
+        p = fk.fk_model_get_params(model).astype(np.float64)
+        mean, std = fk.fk_model_get_normalization(model)
+        Xs = ((X - mean) / std).astype(np.float64)
+        dims = [fk.FK_MODEL_FEATURES, rep["hidden"], rep["hidden"], rep["hidden"], fk.FK_MODEL_OUTPUTS]
+        t0 = time.perf_counter()
+        for r0 in range(0, Xs.shape[0], rep["batch"]):
+            mlp.loss_grad(p, dims, Xs[r0:r0 + rep["batch"]], Y[r0:r0 + rep["batch"]])
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(dt, 3), "unit": "s/epoch", "cores": 1, "kind": "oracle",
+                               "sample": "one epoch of forward+backward on the training set, numpy fp64",
+                               "gpu_s_per_epoch": rep["gpu_seconds_per_epoch"]}
+    fk.fk_model_destroy(model)
+    return out
 
 
 def copy_workload(args):
@@ -399,7 +454,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="vf", choices=["vf", "hf", "copy", "serve"])
+    ap.add_argument("--workload", default="vf", choices=["vf", "hf", "copy", "serve", "costmodel"])
+    ap.add_argument("--data", nargs="+", default=[], help="cost-model label shards")
+    ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--rates", type=float, nargs="+", default=[200, 500, 1000, 2000])
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--arena-gb", type=int, default=16)
@@ -423,6 +480,9 @@ def main():
 
     if args.workload == "hf":
         print(json.dumps(hf_workload(args)))
+        return
+    if args.workload == "costmodel":
+        print(json.dumps(costmodel_workload(args)))
         return
     if args.workload == "serve":
         print(json.dumps(serve_workload(args)))

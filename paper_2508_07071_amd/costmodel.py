@@ -174,6 +174,7 @@ def fit(data, hidden=128, epochs=300, batch=512, lr=2e-3, seed=0, n_train=N_TRAI
     rep["best_fixed"] = summarize(quality(test_t, np.full(test_t.shape[0], jbest)))
     pred_tr = fk.fk_model_predict_batch(model, X[:n_train])
     rep["model_train_set"] = summarize(quality(Tm[:n_train], pred_tr.argmin(axis=1)))
+    rep["gpu_seconds_per_epoch"] = round(train_s / max(epochs, 1), 5)
     return model, rep
 
 

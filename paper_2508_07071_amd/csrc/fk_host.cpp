@@ -463,7 +463,6 @@ uint32_t fk::build_items(const fk_plan *p, const fk_item *items, int32_t n,
 {
     const int C = p->chain.read.channels;
     const int es_in = dtype_size(p->chain.read.in_dtype);
-    const int es_out = dtype_size(p->chain.write.out_dtype);
     const uint64_t tile_units = (uint64_t)cfg.block_threads * cfg.coarsen;
     uint64_t tiles = 0;
     for (int32_t b = 0; b < n; ++b) {
@@ -497,7 +496,6 @@ uint32_t fk::build_items(const fk_plan *p, const fk_item *items, int32_t n,
             flags |= IF_SRC_VEC;
         if (r.ow % kUnitPx == 0 && (uintptr_t)it.dst % 16 == 0)
             flags |= IF_DST_VEC;
-        (void)es_out;
         r.flags = flags;
         tb[b] = (uint32_t)tiles;
         const uint64_t units = (uint64_t)upr * (uint64_t)r.oh;

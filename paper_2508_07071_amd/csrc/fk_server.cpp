@@ -80,7 +80,6 @@ struct Req {
     hipEvent_t ready = nullptr;    // frame copy done
     int launched = 0, done = 0;
     double t_admit = 0, t_launch = 0;
-    bool released_early = false;
 };
 
 struct Launch {
