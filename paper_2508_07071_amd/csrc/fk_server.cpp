@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/fk.h"
+#include "fk_arena.hpp"
 #include "fk_host.hpp"
 #include "fk_internal.hpp"
 
@@ -30,44 +31,6 @@ using namespace fk;
 namespace {
 
 int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
-
-// First-fit allocator over [0, size) with coalescing free blocks.
-class Arena {
-public:
-    explicit Arena(int64_t size) { free_[0] = size; }
-    int64_t alloc(int64_t bytes)
-    {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                const int64_t off = it->first, rest = it->second - bytes;
-                free_.erase(it);
-                if (rest > 0)
-                    free_[off + bytes] = rest;
-                return off;
-            }
-        }
-        return -1;
-    }
-    void release(int64_t off, int64_t bytes)
-    {
-        auto it = free_.emplace(off, bytes).first;
-        auto next = std::next(it);
-        if (next != free_.end() && it->first + it->second == next->first) {
-            it->second += next->second;
-            free_.erase(next);
-        }
-        if (it != free_.begin()) {
-            auto prev = std::prev(it);
-            if (prev->first + prev->second == it->first) {
-                prev->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-
-private:
-    std::map<int64_t, int64_t> free_;
-};
 
 struct Req {
     uint64_t ticket = 0;
