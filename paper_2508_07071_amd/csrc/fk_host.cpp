@@ -161,101 +161,6 @@ extern "C" fk_status fk_items_validate(const fk_chain_desc *chain, const fk_item
     }
 }
 
-// --------------------------------------------------------- normalisation --
-
-// Run-time op list: swaps moved to the read (each later-crossed op's
-// per-channel constants permuted), CVT dropped, SUB -> ADD(-k), and unless
-// strict, MUL immediately followed by ADD -> FMA.  Every rewrite preserves
-// the per-element fp32 arithmetic exactly except the contraction.
-void fk::normalise_chain(const fk_chain_desc *ch, bool strict, std::vector<OpRec> &ops,
-                         int32_t &swap)
-{
-    const int C = ch->read.channels;
-    // swaps after op i (parity)
-    std::vector<int> after(ch->n_ops + 1, 0);
-    for (int i = ch->n_ops - 1; i >= 0; --i)
-        after[i] = after[i + 1] ^ (ch->ops[i].kind == FK_OP_SWAP_RB ? 1 : 0);
-    swap = (C >= 3) ? after[0] : 0;
-    std::vector<OpRec> lin;
-    for (int i = 0; i < ch->n_ops; ++i) {
-        const fk_op_desc &d = ch->ops[i];
-        if (d.kind == FK_OP_SWAP_RB || d.kind == FK_OP_CVT_F32)
-            continue;
-        OpRec r;
-        std::memset(&r, 0, sizeof r);
-        float k[4];
-        for (int c = 0; c < 4; ++c)
-            k[c] = d.n_consts == 1 ? d.consts[0] : (c < C ? d.consts[c] : 0.0f);
-        if (C >= 3 && after[i + 1] && d.n_consts != 1)
-            std::swap(k[0], k[2]);
-        switch (d.kind) {
-        case FK_OP_MUL: r.code = OPC_MUL; break;
-        case FK_OP_ADD: r.code = OPC_ADD; break;
-        case FK_OP_SUB:
-            r.code = OPC_ADD;
-            for (int c = 0; c < 4; ++c)
-                k[c] = -k[c];
-            break;
-        default: r.code = OPC_DIV; break;
-        }
-        for (int c = 0; c < 4; ++c)
-            r.a[c] = k[c];
-        lin.push_back(r);
-    }
-    ops.clear();
-    for (size_t i = 0; i < lin.size(); ++i) {
-        if (!strict && lin[i].code == OPC_MUL && i + 1 < lin.size() && lin[i + 1].code == OPC_ADD) {
-            OpRec f = lin[i];
-            f.code = OPC_FMA;
-            for (int c = 0; c < 4; ++c)
-                f.b[c] = lin[i + 1].a[c];
-            ops.push_back(f);
-            ++i;
-        } else {
-            ops.push_back(lin[i]);
-        }
-    }
-}
-
-// Compile-time chains built into the library.
-int fk::match_static(const fk_chain_desc *ch, std::vector<float> &consts, int &n_ops)
-{
-    const fk_op_desc *o = ch->ops;
-    // crop+resize u8x3 -> swap, cvt, mul(1), sub, div -> planar f32
-    if (ch->read.kind == FK_READ_CROP_RESIZE && ch->read.in_dtype == FK_U8 &&
-        ch->read.channels == 3 && ch->write.out_dtype == FK_F32 && ch->write.layout == FK_PLANAR &&
-        ch->n_ops == 5 && o[0].kind == FK_OP_SWAP_RB && o[1].kind == FK_OP_CVT_F32 &&
-        o[2].kind == FK_OP_MUL && o[2].n_consts == 1 && o[3].kind == FK_OP_SUB &&
-        o[4].kind == FK_OP_DIV) {
-        consts.assign(7, 0.0f);
-        consts[0] = o[2].consts[0];
-        for (int c = 0; c < 3; ++c) {
-            consts[1 + c] = o[3].n_consts == 1 ? o[3].consts[0] : o[3].consts[c];
-            consts[4 + c] = o[4].n_consts == 1 ? o[4].consts[0] : o[4].consts[c];
-        }
-        n_ops = 5;
-        return FAM_NORMALIZE;
-    }
-    // plain u8x3 -> cvt, N alternating mul/add (scalar) -> packed f32
-    if (ch->read.kind == FK_READ_PLAIN && ch->read.in_dtype == FK_U8 && ch->read.channels == 3 &&
-        ch->write.out_dtype == FK_F32 && ch->write.layout == FK_PACKED && ch->n_ops >= 2 &&
-        o[0].kind == FK_OP_CVT_F32) {
-        const int N = ch->n_ops - 1;
-        if (N != 1 && N != 4 && N != 16 && N != 64 && N != 256)
-            return FAM_RUNTIME;
-        consts.assign(N, 0.0f);
-        for (int k = 0; k < N; ++k) {
-            const fk_op_desc &d = o[1 + k];
-            if (d.kind != (k % 2 == 0 ? FK_OP_MUL : FK_OP_ADD) || d.n_consts != 1)
-                return FAM_RUNTIME;
-            consts[k] = d.consts[0];
-        }
-        n_ops = N;
-        return FAM_MULADD;
-    }
-    return FAM_RUNTIME;
-}
-
 // ------------------------------------------------------------------ plan --
 
 static const fk_launch_config kDefaultConfig = {256, 1};

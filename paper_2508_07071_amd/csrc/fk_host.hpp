@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "../../include/fk.h"
+#include "fk_chain.hpp"
 #include "fk_internal.hpp"
 
 struct fk_plan {
@@ -46,8 +47,6 @@ fk_status hip_error(hipError_t e, const char *what);
 int dtype_size(int32_t dt);
 fk_status validate_chain(const fk_chain_desc *ch);
 fk_status validate_items(const fk_chain_desc *ch, const fk_item *items, int32_t n);
-void normalise_chain(const fk_chain_desc *ch, bool strict, std::vector<OpRec> &ops, int32_t &swap);
-int match_static(const fk_chain_desc *ch, std::vector<float> &consts, int &n_ops);
 bool config_valid(const fk_launch_config &c);
 const void *plan_kernel(const fk_plan *p, const fk_launch_config &cfg);
 size_t lds_bytes(const fk_plan *p, const fk_launch_config &cfg);

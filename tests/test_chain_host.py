@@ -1,0 +1,194 @@
+"""Plan-time chain rewriting (host C++, built here with g++): the run-time
+tier's normalised op list must compute what the chain computes.  The list
+is evaluated here in numpy fp32, one IEEE operation per op, and compared
+with the oracle on the same frames: bit for bit in the strict mode, within
+the fp32 tolerance when MUL+ADD pairs are contracted to FMA."""
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2508_07071_amd", "csrc")
+KINDS = {k: i for i, k in enumerate(datagen.OP_KINDS)}  # same order as FK_OP_*
+
+DRIVER = r"""
+#include "fk_chain.hpp"
+#include <cstdio>
+#include <vector>
+int main() {
+    int C, n, strict, rk, dt, odt, lay;
+    while (std::scanf("%d %d %d %d %d %d %d", &C, &n, &strict, &rk, &dt, &odt, &lay) == 7) {
+        std::vector<fk_op_desc> ops(n);
+        for (auto &o : ops)
+            std::scanf("%d %d %a %a %a %a", &o.kind, &o.n_consts, &o.consts[0], &o.consts[1],
+                       &o.consts[2], &o.consts[3]);
+        fk_chain_desc ch{};
+        ch.read.kind = rk; ch.read.in_dtype = dt; ch.read.channels = C;
+        ch.ops = ops.data(); ch.n_ops = n;
+        ch.write.out_dtype = odt; ch.write.layout = lay;
+        std::vector<fk::OpRec> rec;
+        int32_t swap = 0;
+        fk::normalise_chain(&ch, strict != 0, rec, swap);
+        std::vector<float> k;
+        int sn = 0;
+        int fam = fk::match_static(&ch, k, sn);
+        std::printf("%d %zu %d %d %zu\n", swap, rec.size(), fam, sn, k.size());
+        for (auto &r : rec)
+            std::printf("%d %a %a %a %a %a %a %a %a\n", r.code, r.a[0], r.a[1], r.a[2], r.a[3],
+                        r.b[0], r.b[1], r.b[2], r.b[3]);
+        for (float v : k) std::printf("%a\n", v);
+    }
+    return 0;
+}
+"""
+
+OPC_MUL, OPC_ADD, OPC_DIV, OPC_FMA = 0, 1, 2, 3
+FAM_RUNTIME, FAM_NORMALIZE, FAM_MULADD = 0, 1, 2
+
+
+@pytest.fixture(scope="module")
+def driver():
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "drv.cpp"), os.path.join(d, "drv")
+        open(src, "w").write(DRIVER)
+        subprocess.check_call(["g++", "-O1", "-std=c++17", "-ffp-contract=off", "-I", CSRC, "-o", exe,
+                               src, os.path.join(CSRC, "fk_chain.cpp")])
+
+        def run(chains):
+            """[(chain dict, strict)] -> [(swap, ops, family, consts)]"""
+            lines = []
+            for ch, strict in chains:
+                r, w = ch["read"], ch["write"]
+                lines.append(f"{r['channels']} {len(ch['ops'])} {int(strict)} "
+                             f"{int(r['kind'] == 'crop_resize')} {['u8', 'f16', 'f32'].index(r['dtype'])} "
+                             f"{['u8', 'f16', 'f32'].index(w['dtype'])} {int(w['layout'] == 'planar')}")
+                for o in ch["ops"]:
+                    k = list(o["k"]) + [0.0] * (4 - len(o["k"]))
+                    lines.append(f"{KINDS[o['kind']]} {len(o['k'])} " + " ".join(float(v).hex() for v in k))
+            out = subprocess.run([exe], input="\n".join(lines) + "\n", capture_output=True, text=True,
+                                 check=True).stdout.split("\n")
+            res, i = [], 0
+            for _ in chains:
+                swap, n, fam, sn, nk = (int(v) for v in out[i].split())
+                i += 1
+                ops = []
+                for _ in range(n):
+                    f = out[i].split()
+                    ops.append((int(f[0]), np.array([float.fromhex(v) for v in f[1:5]], np.float32),
+                                np.array([float.fromhex(v) for v in f[5:9]], np.float32)))
+                    i += 1
+                ks = [float.fromhex(out[i + j]) for j in range(nk)]
+                i += nk
+                res.append((swap, ops, fam, sn, ks))
+            return res
+        yield run
+
+
+def evaluate(frame, C, swap, ops):
+    """The normalised list applied to a packed frame, fp32 per operation."""
+    x = frame.astype(np.float32).reshape(-1, C)
+    if swap:
+        x = x[:, [2, 1, 0] + list(range(3, C))]
+    for code, a, b in ops:
+        a, b = a[:C], b[:C]
+        if code == OPC_MUL:
+            x = x * a
+        elif code == OPC_ADD:
+            x = x + a
+        elif code == OPC_DIV:
+            x = x / a
+        else:  # one rounding of the exact product-sum; exact for all but ties of a double rounding
+            x = (x.astype(np.float64) * a + b).astype(np.float32)
+    return x.reshape(frame.shape)
+
+
+def random_chain(g, C, dtype, max_ops=24):
+    spec = datagen.random_chain_spec(g, max_ops=max_ops)
+    ch = spec["chain"]
+    for o in ch["ops"]:  # re-draw per-channel constants for this C
+        if len(o["k"]) > 1:
+            o["k"] = [datagen.f32(g.uniform(*((0.5, 1.5) if o["kind"] in ("mul", "div") else (-1, 1))))
+                      for _ in range(C)]
+    ch["read"] = {"kind": "plain", "dtype": dtype, "channels": C, "out_w": 0, "out_h": 0}
+    ch["write"] = {"dtype": "f32", "layout": "packed"}
+    return ch
+
+
+@pytest.mark.parametrize("strict", [True, False])
+def test_normalised_list_matches_oracle(driver, strict):
+    g = datagen.rng(11 + strict)
+    cases = []
+    for t in range(120):
+        C = [1, 3, 4][t % 3]
+        dtype = ["u8", "f32"][(t // 3) % 2]
+        ch = random_chain(g, C, dtype)
+        if t % 7 == 0:  # swaps around per-channel constants
+            ch["ops"] = [{"kind": "mul", "k": [1.5, 0.75, 0.625, 1.25][:C]}, {"kind": "swap", "k": []},
+                         {"kind": "sub", "k": [0.25, -0.5, 0.125, 1.0][:C]}, {"kind": "swap", "k": []},
+                         {"kind": "div", "k": [0.5, 0.875, 1.375, 1.0][:C]}, {"kind": "swap", "k": []}]
+        if dtype == "u8":
+            fr = datagen.frame(g, 5, 7, C)
+        else:
+            fr = (g.uniform(-300, 300, size=(5, 7, C))).astype(np.float32)
+        cases.append((ch, fr))
+    outs = driver([(ch, strict) for ch, _ in cases])
+    for (ch, fr), (swap, ops, _, _, _) in zip(cases, outs):
+        C = ch["read"]["channels"]
+        n_arith = sum(o["kind"] in ("mul", "add", "sub", "div") for o in ch["ops"])
+        assert len(ops) <= n_arith and (not strict or len(ops) == n_arith)
+        assert all(code != OPC_FMA for code, _, _ in ops) or not strict
+        n_swaps = sum(o["kind"] == "swap" for o in ch["ops"])
+        assert swap == (n_swaps % 2 if C >= 3 else 0)
+        got = evaluate(fr, C, swap, ops)
+        ref = oracle.run_chain(ch, [fr], [{"frame": 0, "x": 0, "y": 0, "w": 7, "h": 5}])[0]
+        if strict:
+            np.testing.assert_array_equal(got.view(np.uint32), ref["out"].view(np.uint32))
+        else:
+            tol = 1e-5 * np.maximum(np.abs(ref["out"]), ref["smax"]) + 1e-30
+            assert np.all(np.abs(got - ref["out"]) <= tol)
+
+
+def test_contraction_pairs_mul_then_add_only(driver):
+    ch = {"read": {"kind": "plain", "dtype": "f32", "channels": 3, "out_w": 0, "out_h": 0},
+          "write": {"dtype": "f32", "layout": "packed"},
+          "ops": [{"kind": "mul", "k": [2.0]}, {"kind": "sub", "k": [1.0, 2.0, 3.0]},
+                  {"kind": "add", "k": [4.0]}, {"kind": "mul", "k": [3.0]},
+                  {"kind": "cvt", "k": []}, {"kind": "add", "k": [0.5]},
+                  {"kind": "mul", "k": [5.0]}, {"kind": "div", "k": [2.0]}]}
+    (swap, ops, fam, _, _), = driver([(ch, False)])
+    codes = [c for c, _, _ in ops]
+    # mul,sub -> fma(2,-k); add stays; mul,(cvt),add -> fma; mul; div
+    assert codes == [OPC_FMA, OPC_ADD, OPC_FMA, OPC_MUL, OPC_DIV]
+    np.testing.assert_array_equal(ops[0][1][:3], [2, 2, 2])
+    np.testing.assert_array_equal(ops[0][2][:3], [-1, -2, -3])
+    assert swap == 0 and fam == FAM_RUNTIME
+
+
+def test_static_chain_match(driver):
+    norm = datagen.normalize_chain(224, 224)
+    mulsub = {**norm, "ops": [dict(o) for o in norm["ops"]]}
+    mulsub["ops"][2] = {"kind": "mul", "k": [1.0, 2.0, 3.0]}  # per-channel scale: not the built-in chain
+    f16 = {**norm, "write": {"dtype": "f16", "layout": "planar"}}
+    cases = [(norm, True), (mulsub, True), (f16, True)]
+    g = datagen.rng(0)
+    for n in (1, 2, 4, 16, 64, 256, 257):
+        cases.append((datagen.muladd_chain(n, g), True))
+    res = driver(cases)
+    assert res[0][2] == FAM_NORMALIZE and res[0][3] == 5
+    k = res[0][4]
+    assert k[0] == np.float32(norm["ops"][2]["k"][0])
+    np.testing.assert_array_equal(k[1:4], np.float32(norm["ops"][3]["k"]))
+    np.testing.assert_array_equal(k[4:7], np.float32(norm["ops"][4]["k"]))
+    assert res[1][2] == FAM_RUNTIME and res[2][2] == FAM_RUNTIME
+    for (ch, _), r, n in zip(cases[3:], res[3:], (1, 2, 4, 16, 64, 256, 257)):
+        if n in (1, 4, 16, 64, 256):
+            assert r[2] == FAM_MULADD and r[3] == n
+            np.testing.assert_array_equal(r[4], [np.float32(o["k"][0]) for o in ch["ops"][1:]])
+        else:
+            assert r[2] == FAM_RUNTIME
