@@ -13,11 +13,13 @@ A chain is a dict::
 
     {"read":  {"kind": "plain" | "crop_resize", "dtype": "u8"|"f16"|"f32",
                "channels": 1|3|4, "out_w": int, "out_h": int},
-     "ops":   [{"kind": "swap"|"cvt"|"mul"|"add"|"sub"|"div", "k": [floats]}],
+     "ops":   [{"kind": "swap"|"cvt"|"mul"|"add"|"sub"|"div", "k": [floats]}
+               | {"kind": "loop", "span": s, "count": n}],
      "write": {"dtype": "f32"|"f16", "layout": "packed"|"planar"}}
 
 ``k`` holds 0 (swap/cvt), 1 (scalar) or ``channels`` fp32-representable
-constants.  An item is a dict ``{"frame": index, "x", "y", "w", "h",
+constants.  A loop op repeats the ``s`` ops just before it so that they run
+``n`` times in all.  An item is a dict ``{"frame": index, "x", "y", "w", "h",
 "out_w", "out_h"}`` naming a region of interest of one of the frames.
 
 The workloads mirror the paper's synthetic benchmarks (Section VI): uint8
@@ -108,6 +110,36 @@ def muladd_chain(n_ops: int, g: np.random.Generator, channels: int = 3,
         "ops": ops,
         "write": {"dtype": "f32", "layout": layout},
     }
+
+
+def loop_chain(pairs: int, g: np.random.Generator, channels: int = 1,
+               layout: str = "packed") -> dict:
+    """Plain read -> fp32 -> one Mul and one Add run `pairs` times through a
+    loop op (Sections VI-B and VI-D: one instance of each op type repeated
+    by a loop op).  Multiplier uniform in [0.5, 0.95), addend uniform in
+    [-1, 1), drawn in that order: the map is a contraction, so values stay
+    within max(255, 20) for any number of pairs."""
+    m = f32(g.uniform(0.5, 0.95))
+    a = f32(g.uniform(-1.0, 1.0))
+    ops = [{"kind": "cvt", "k": []}, {"kind": "mul", "k": [m]}, {"kind": "add", "k": [a]},
+           {"kind": "loop", "span": 2, "count": int(pairs)}]
+    return {
+        "read": {"kind": "plain", "dtype": "u8", "channels": channels, "out_w": 0, "out_h": 0},
+        "ops": ops,
+        "write": {"dtype": "f32", "layout": layout},
+    }
+
+
+def loop_batch(pairs: int, seed: int = 0, batch: int = 50, hw=(120, 60), channels: int = 1) -> dict:
+    """`batch` u8 images of hw (height, width) stacked in one frame, image b
+    in rows [b*h, (b+1)*h); one item per image; loop_chain(pairs)
+    (Section VI-D: batch 50 of 60 x 120 uchar images, Mul+Add pairs)."""
+    g = rng(seed)
+    h, w = hw
+    fr = frame(g, batch * h, w, channels)
+    items = [{"frame": 0, "x": 0, "y": b * h, "w": w, "h": h, "out_w": w, "out_h": h}
+             for b in range(batch)]
+    return {"frames": [fr], "items": items, "chain": loop_chain(pairs, g, channels), "seed": seed}
 
 
 def whole_frame_item(fr: np.ndarray, frame_index: int = 0) -> dict:

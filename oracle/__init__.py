@@ -25,13 +25,14 @@ LIB = os.path.join(HERE, "libfkoracle.so")
 
 _DT = {"u8": 0, "f16": 1, "f32": 2}
 _READ = {"plain": 0, "crop_resize": 1}
-_OP = {"swap": 0, "cvt": 1, "mul": 2, "add": 3, "sub": 4, "div": 5}
+_OP = {"swap": 0, "cvt": 1, "mul": 2, "add": 3, "sub": 4, "div": 5, "loop": 6}
 _LAYOUT = {"packed": 0, "planar": 1}
 _NP_OUT = {"f32": np.float32, "f16": np.float16}
 
 
 class _Op(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("nconst", C.c_int32), ("k", C.c_float * 4)]
+    _fields_ = [("kind", C.c_int32), ("nconst", C.c_int32), ("k", C.c_float * 4),
+                ("span", C.c_int32), ("count", C.c_int32)]
 
 
 class _Chain(C.Structure):
@@ -86,6 +87,8 @@ def _chain_struct(chain: dict):
         arr[i].nconst = len(ks)
         for j, v in enumerate(ks[:4]):
             arr[i].k[j] = v
+        arr[i].span = op.get("span", 0)
+        arr[i].count = op.get("count", 0)
     ch = _Chain()
     ch.read_kind = _READ[chain["read"]["kind"]]
     ch.in_dtype = _DT[chain["read"]["dtype"]]

@@ -38,6 +38,11 @@
  *    no contraction; Div is a true division.
  *  - Write: packed out[(y*W + x)*C + c] or planar out[(c*H + y)*W + x];
  *    fp16 outputs round to nearest even.
+ *  - Loop (the repeat op of Section VI-B, which applies one op many times
+ *    without spending kernel parameters on each copy): the `span` ops just
+ *    before it run `count` times in all, in order, before the chain goes
+ *    on.  Its body holds Mul/Add/Sub/Div ops only, so a loop neither
+ *    crosses a swap nor contains another loop.
  *
  * Build: gcc -O2 -std=c11 -fno-fast-math -ffp-contract=off -shared -fPIC.
  */
@@ -48,7 +53,7 @@
 
 enum { ORC_U8 = 0, ORC_F16 = 1, ORC_F32 = 2 };
 enum { ORC_READ_PLAIN = 0, ORC_READ_CROP_RESIZE = 1 };
-enum { ORC_SWAP = 0, ORC_CVT = 1, ORC_MUL = 2, ORC_ADD = 3, ORC_SUB = 4, ORC_DIV = 5 };
+enum { ORC_SWAP = 0, ORC_CVT = 1, ORC_MUL = 2, ORC_ADD = 3, ORC_SUB = 4, ORC_DIV = 5, ORC_LOOP = 6 };
 enum { ORC_PACKED = 0, ORC_PLANAR = 1 };
 
 enum {
@@ -61,6 +66,8 @@ typedef struct {
     int32_t kind;
     int32_t nconst; /* 0, 1 (scalar) or C (one per channel) */
     float k[4];
+    int32_t span;   /* ORC_LOOP: number of ops just before it that repeat */
+    int32_t count;  /* ORC_LOOP: how many times they run in all (>= 1) */
 } orc_op;
 
 typedef struct {
@@ -365,9 +372,15 @@ static int chain_ok(const orc_chain *ch)
         return 0;
     for (int32_t i = 0; i < ch->n_ops; ++i) {
         const orc_op *op = &ch->ops[i];
-        if (op->kind < ORC_SWAP || op->kind > ORC_DIV)
+        if (op->kind < ORC_SWAP || op->kind > ORC_LOOP)
             return 0;
-        if (op->kind == ORC_SWAP || op->kind == ORC_CVT) {
+        if (op->kind == ORC_LOOP) {
+            if (op->nconst != 0 || op->span < 1 || op->span > i || op->count < 1)
+                return 0;
+            for (int32_t j = i - op->span; j < i; ++j)
+                if (ch->ops[j].kind < ORC_MUL || ch->ops[j].kind > ORC_DIV)
+                    return 0;
+        } else if (op->kind == ORC_SWAP || op->kind == ORC_CVT) {
             if (op->nconst != 0)
                 return 0;
         } else if (op->nconst != 1 && op->nconst != ch->channels) {
@@ -425,6 +438,11 @@ int orc_run(const orc_chain *ch, const orc_item *items, int32_t n)
                 step_swap(&cur);
             else if (op->kind == ORC_CVT)
                 ; /* fp32 conversion already exact at the read */
+            else if (op->kind == ORC_LOOP)
+                /* the body ran once on the way here: count - 1 more times */
+                for (int32_t r = 1; r < op->count; ++r)
+                    for (int32_t j = i - op->span; j < i; ++j)
+                        step_arith(&cur, &ch->ops[j]);
             else
                 step_arith(&cur, op);
         }

@@ -30,6 +30,11 @@ MUTATIONS = [
     ("crop x offset dropped", "frame_elem(it, ch->in_dtype, C, it->x + i, it->y + j, c)", "frame_elem(it, ch->in_dtype, C, i, it->y + j, c)"),
     ("fp16 rounding truncates", "double q = nearbyint(ldexp(a, -ulp_exp));", "double q = floor(ldexp(a, -ulp_exp));"),
     ("mul and add exchanged", "case ORC_MUL: r = v * k;", "case ORC_MUL: r = v + k;"),
+    ("loop runs its body once too often", "for (int32_t r = 1; r < op->count; ++r)",
+     "for (int32_t r = 0; r < op->count; ++r)"),
+    ("loop skips the first op of its body",
+     "for (int32_t j = i - op->span; j < i; ++j)\n                        step_arith",
+     "for (int32_t j = i - op->span + 1; j < i; ++j)\n                        step_arith"),
 ]
 
 PINS = [
@@ -45,6 +50,8 @@ PINS = [
     ("test_per_channel_constants_follow_swapped_positions", {}),
     ("test_normalise_chain_is_per_op_ieee_fp32", {}),
     ("test_muladd_chain_matches_affine_closed_form", {"n_ops": 4}),
+    ("test_loop_equals_unrolled_body", {"span": 3, "count": 4}),
+    ("test_loop_chain_matches_affine_closed_form", {"pairs": 7}),
     ("test_division_is_true_division_not_reciprocal", {}),
     ("test_float_to_half_round_to_nearest_even_matches_numpy", {}),
 ]

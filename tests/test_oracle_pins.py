@@ -225,6 +225,77 @@ def test_muladd_chain_matches_affine_closed_form(n_ops):
     assert np.all(res["smax"] >= np.abs(res["out"]))
 
 
+def _loop_body(g, C):
+    body = []
+    for kind in ("mul", "sub", "div", "add"):
+        lo, hi = (0.5, 1.5) if kind in ("mul", "div") else (-1.0, 1.0)
+        body.append({"kind": kind, "k": [datagen.f32(g.uniform(lo, hi)) for _ in range(C)]})
+    return body
+
+
+@pytest.mark.parametrize("span,count", [(1, 5), (3, 4), (4, 3), (2, 1)])
+def test_loop_equals_unrolled_body(span, count):
+    """A loop op is its body written out `count` times (Section VI-B's repeat
+    op): same results bit for bit, with ops before and after the loop and a
+    swap in between so per-channel constants keep their positions."""
+    g = datagen.rng(span * 10 + count)
+    fr = datagen.frame(g, 9, 11, 3)
+    body = _loop_body(g, 3)[:span]
+    head = [{"kind": "cvt", "k": []}, {"kind": "mul", "k": [0.75, 1.25, 1.5]}, {"kind": "swap", "k": []}]
+    tail = [{"kind": "swap", "k": []}, {"kind": "sub", "k": [0.5, -0.25, 0.125]}]
+    looped = plain(ops=head + body + [{"kind": "loop", "span": span, "count": count}] + tail)
+    unrolled = plain(ops=head + body * count + tail)
+    it = [item(1, 2, 8, 6)]
+    a = oracle.run_chain(looped, [fr], it)[0]
+    b = oracle.run_chain(unrolled, [fr], it)[0]
+    np.testing.assert_array_equal(a["out"].view(np.uint32), b["out"].view(np.uint32))
+    np.testing.assert_array_equal(a["v64"], b["v64"])
+    if count == 1:  # a loop that runs once is no op at all
+        c = oracle.run_chain(plain(ops=head + body + tail), [fr], it)[0]
+        np.testing.assert_array_equal(a["out"].view(np.uint32), c["out"].view(np.uint32))
+
+
+@pytest.mark.parametrize("pairs", [1, 7, 1000])
+def test_loop_chain_matches_affine_closed_form(pairs):
+    """v -> m v + a repeated P times is v -> m^P v + a (1 - m^P) / (1 - m):
+    the fp64 shadow equals it to fp64 rounding and the fp32 result stays
+    within the first-order bound of one half-ulp per op, each damped by the
+    multipliers that follow it."""
+    cfg = datagen.loop_batch(pairs, seed=pairs, batch=2, hw=(5, 7), channels=1)
+    ch = cfg["chain"]
+    m, a = ch["ops"][1]["k"][0], ch["ops"][2]["k"][0]
+    res = oracle.run_chain(ch, cfg["frames"], cfg["items"][1:])[0]
+    x = cfg["frames"][0][5:10].astype(np.float64)
+    mp = m ** pairs
+    exact = mp * x + a * (1.0 - mp) / (1.0 - m)
+    np.testing.assert_allclose(res["v64"], exact, rtol=1e-11, atol=1e-11)
+    u = 2.0 ** -24
+    v = x.copy()
+    bound = np.zeros_like(x)
+    for p in range(pairs):
+        rest = m ** (pairs - 1 - p)  # multipliers after this pair's add
+        v = v * m
+        bound += u * np.abs(v) * m * rest
+        v = v + a
+        bound += u * np.abs(v) * rest
+    assert np.all(np.abs(res["out"] - exact) <= 1.01 * bound + 1e-30)
+    assert np.all(res["smax"] >= np.abs(res["out"]))
+
+
+@pytest.mark.parametrize("ops", [
+    [{"kind": "loop", "span": 1, "count": 2}],                                    # nothing before it
+    [{"kind": "mul", "k": [2.0]}, {"kind": "loop", "span": 2, "count": 2}],       # span past the start
+    [{"kind": "mul", "k": [2.0]}, {"kind": "loop", "span": 1, "count": 0}],       # count < 1
+    [{"kind": "swap", "k": []}, {"kind": "mul", "k": [2.0]}, {"kind": "loop", "span": 2, "count": 2}],
+    [{"kind": "cvt", "k": []}, {"kind": "loop", "span": 1, "count": 2}],
+    [{"kind": "mul", "k": [2.0]}, {"kind": "loop", "span": 1, "count": 2},
+     {"kind": "loop", "span": 2, "count": 2}],                                    # nested
+])
+def test_bad_loops_are_rejected(ops):
+    fr = np.zeros((4, 4, 3), np.uint8)
+    assert oracle.validate(plain(ops=ops), [fr], [item(0, 0, 4, 4)]) < 0
+
+
 def test_division_is_true_division_not_reciprocal():
     fr = np.full((1, 4, 1), 1, np.uint8)
     fr[0, :, 0] = [3, 7, 11, 13]
