@@ -18,9 +18,11 @@ Printed JSON line:
   cpu_baseline the CPU oracle (single thread) on a band of rows of the same
                frame through the whole sweep, scaled to GB/s
 
-Other workloads (--workload): "hf" (batched uneven crops, config 2 sizes)
-and "norm" (the single-crop hot chain, config 0); these are for the design
-notes, not the headline line.
+Other workloads (--workload), for the design notes, not the headline line:
+"hf" (batched uneven crops), "loop" (long Mul+Add chains through the loop
+op on a batch of small images), "serve" (the serving loop), "costmodel"
+(training and evaluating the launch-configuration model) and "copy" (a
+plain device copy, the bandwidth reference).
 """
 import argparse
 import json
@@ -348,6 +350,101 @@ def hf_large(args, n_frames=8, per_frame=512):
     return res
 
 
+LOOP_PAIRS = [1, 10, 100, 1000, 5000, 10000]
+
+
+def loop_workload(args):
+    """Vertical plus horizontal fusion with long chains (Section VI-D): a
+    batch of 50 uint8 images of 60x120 held in one tensor; convert to fp32,
+    then P Mul+Add pairs through the loop op, packed fp32 out, for P in
+    LOOP_PAIRS.  For each P: the fused batched launch (the compile-time loop
+    chain), the same fused chain launched once per image (vertical fusion
+    only), and the unfused baseline (one kernel per op per image).
+    Algorithmic work per launch: 2 P flops per element (a multiply and an
+    add), 50 x 7200 elements; bytes 7200 x (1 + 4) per image."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2508_07071_amd as fk
+
+    dev = torch.device("cuda:0")
+    stream = fk.stream_handle()
+    B, (h, w) = 50, (120, 60)
+    elems = B * h * w
+    alg_bytes = elems * (1 + 4)
+
+    def timeit(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    rows = []
+    for P in LOOP_PAIRS:
+        cfg = datagen.loop_batch(P, seed=args.seed)
+        ch = cfg["chain"]
+        frame = torch.from_numpy(cfg["frames"][0]).to(dev)
+        out = torch.empty((B, h, w, 1), dtype=torch.float32, device=dev)
+        arr = fk.make_items(ch, [frame], cfg["items"], [out[b] for b in range(B)])
+        plan = fk.fk_plan_create(fk.chain_desc(ch), B, fk.plan_opts(strict=args.strict))
+        c = fk.fk_plan_get_config(plan)
+        flops = 2.0 * P * elems
+        r = {"pairs": P, "compile_time_chain": bool(fk.fk_plan_get_tier(plan)),
+             "launch_config": [c.block_threads, c.coarsen]}
+        r["fused_ms"] = round(timeit(lambda: fk.fk_run(plan, arr, B, stream), 100), 5)
+        singles = [fk.make_items(ch, [frame], [it], [out[b]]) for b, it in enumerate(cfg["items"])]
+        r["per_image_ms"] = round(timeit(lambda: [fk.fk_run(plan, s1, 1, stream) for s1 in singles],
+                                         20 if P <= 1000 else 3), 5)
+        if not args.no_unfused:
+            nbytes = fk.fk_unfused_scratch_bytes(plan, arr, B)
+            scratch = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+            reps = 3 if P <= 100 else 1
+            r["unfused_ms"] = round(timeit(lambda: fk.fk_run_unfused(plan, arr, B, scratch.data_ptr(), nbytes,
+                                                                   stream), reps), 4)
+            r["unfused_launches"] = B * (1 + 2 * P)
+            r["speedup_vs_unfused"] = round(r["unfused_ms"] / r["fused_ms"], 1)
+            del scratch
+        r["tflops"] = round(flops / (r["fused_ms"] * 1e-3) / 1e12, 3)
+        r["alu_frac"] = round(r["tflops"] / ALU_PEAK_TFLOPS, 4)
+        r["gbps"] = round(alg_bytes / (r["fused_ms"] * 1e-3) / 1e9, 1)
+        r["speedup_hf_vs_per_image"] = round(r["per_image_ms"] / r["fused_ms"], 2)
+        fk.fk_plan_destroy(plan)
+        log(r)
+        rows.append(r)
+    top = rows[-1]
+    tot_flops = sum(2.0 * r["pairs"] * elems for r in rows)
+    tot_ms = sum(r["fused_ms"] for r in rows)
+    res = {"metric": "loop-chain fused TFLOP/s (2 flops per Mul+Add pair and element)",
+           "value": round(tot_flops / (tot_ms * 1e-3) / 1e12, 3), "unit": "TFLOP/s", "n_gpus": 1,
+           "higher_is_better": True, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "vf_hf_loop: 50 x 60x120 u8 images, cvt + P (mul, add) pairs via the loop op, "
+                                  "packed fp32", "pairs": LOOP_PAIRS, "batch": B,
+                      "fp_mode": "strict" if args.strict else "contracted", "seed": args.seed},
+           "roofline": {"bound": "alu", "achieved": top["tflops"], "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": top["alu_frac"], "traffic": None,
+                        "kernel": f"fused loop chain, {top['pairs']} pairs, 50 x 60x120 u8 -> packed fp32",
+                        "kernel_ms": top["fused_ms"]},
+           "rows": rows}
+    if not args.no_cpu_baseline:
+        import oracle
+        P, nimg = 10000, 4
+        cfg = datagen.loop_batch(P, seed=args.seed)
+        t0 = time.perf_counter()
+        oracle.run_chain(cfg["chain"], cfg["frames"], cfg["items"][:nimg], shadow=True)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": round(2.0 * P * nimg * h * w / dt / 1e12, 6), "unit": "TFLOP/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"{nimg} of the 50 images at {P} pairs, {dt:.2f} s single-threaded"}
+    return res
+
+
 def serve_workload(args):
     """Serving loop (config 4 sizes): open-loop Poisson arrivals, continuous
     batching vs per-request fused vs per-request unfused; p50/p99 latency."""
@@ -454,7 +551,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="vf", choices=["vf", "hf", "copy", "serve", "costmodel"])
+    ap.add_argument("--workload", default="vf", choices=["vf", "hf", "loop", "copy", "serve", "costmodel"])
     ap.add_argument("--data", nargs="+", default=[], help="cost-model label shards")
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--rates", type=float, nargs="+", default=[200, 500, 1000, 2000])
@@ -483,6 +580,9 @@ def main():
         return
     if args.workload == "costmodel":
         print(json.dumps(costmodel_workload(args)))
+        return
+    if args.workload == "loop":
+        print(json.dumps(loop_workload(args)))
         return
     if args.workload == "serve":
         print(json.dumps(serve_workload(args)))

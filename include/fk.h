@@ -72,13 +72,20 @@ typedef int32_t fk_status;
  *   fp32).  Arithmetic on a u8/f16 value promotes it to fp32 first.
  * MUL/ADD/SUB/DIV: one fp32 operation with a scalar (n_consts = 1) or
  *   per-channel (n_consts = channels) constant; per-channel constants index
- *   the channel position after earlier swaps.  DIV is an IEEE division. */
+ *   the channel position after earlier swaps.  DIV is an IEEE division.
+ * LOOP: the repeat op of Section VI-B (one op instance applied many times
+ *   without spending kernel parameters on each copy): the loop_span ops just
+ *   before it run loop_count times in all, in order (the first of those runs
+ *   is the one the chain reaches before the LOOP).  The body may hold
+ *   MUL/ADD/SUB/DIV only (no swap, no cvt, no other loop); n_consts = 0.
+ *   A loop is one entry of the op list whatever its count. */
 #define FK_OP_SWAP_RB 0
 #define FK_OP_CVT_F32 1
 #define FK_OP_MUL 2
 #define FK_OP_ADD 3
 #define FK_OP_SUB 4
 #define FK_OP_DIV 5
+#define FK_OP_LOOP 6
 
 #define FK_MAX_OPS 4096
 
@@ -90,8 +97,10 @@ typedef struct {
 
 typedef struct {
     int32_t kind;      /* FK_OP_* */
-    int32_t n_consts;  /* 0 for SWAP_RB/CVT_F32; 1 or `channels` otherwise */
+    int32_t n_consts;  /* 0 for SWAP_RB/CVT_F32/LOOP; 1 or `channels` otherwise */
     float consts[4];
+    int32_t loop_span;  /* LOOP: 1 .. (index of this op); ignored otherwise */
+    int32_t loop_count; /* LOOP: >= 1; ignored otherwise */
 } fk_op_desc;
 
 typedef struct {

@@ -32,7 +32,7 @@ FK_ERR_BUDGET = -6
 FK_U8, FK_F16, FK_F32 = 0, 1, 2
 FK_PACKED, FK_PLANAR = 0, 1
 FK_READ_PLAIN, FK_READ_CROP_RESIZE = 0, 1
-FK_OP_SWAP_RB, FK_OP_CVT_F32, FK_OP_MUL, FK_OP_ADD, FK_OP_SUB, FK_OP_DIV = range(6)
+FK_OP_SWAP_RB, FK_OP_CVT_F32, FK_OP_MUL, FK_OP_ADD, FK_OP_SUB, FK_OP_DIV, FK_OP_LOOP = range(7)
 FK_CONFIG_DEFAULT, FK_CONFIG_MANUAL, FK_CONFIG_AUTOTUNE, FK_CONFIG_MODEL = range(4)
 FK_TIER_AUTO, FK_TIER_RUNTIME = 0, 1
 
@@ -40,7 +40,7 @@ DTYPE = {"u8": FK_U8, "f16": FK_F16, "f32": FK_F32}
 LAYOUT = {"packed": FK_PACKED, "planar": FK_PLANAR}
 READ = {"plain": FK_READ_PLAIN, "crop_resize": FK_READ_CROP_RESIZE}
 OP = {"swap": FK_OP_SWAP_RB, "cvt": FK_OP_CVT_F32, "mul": FK_OP_MUL, "add": FK_OP_ADD,
-      "sub": FK_OP_SUB, "div": FK_OP_DIV}
+      "sub": FK_OP_SUB, "div": FK_OP_DIV, "loop": FK_OP_LOOP}
 TORCH_DTYPE = {"u8": torch.uint8, "f16": torch.float16, "f32": torch.float32}
 
 
@@ -49,7 +49,8 @@ class fk_read_desc(C.Structure):
 
 
 class fk_op_desc(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("n_consts", C.c_int32), ("consts", C.c_float * 4)]
+    _fields_ = [("kind", C.c_int32), ("n_consts", C.c_int32), ("consts", C.c_float * 4),
+                ("loop_span", C.c_int32), ("loop_count", C.c_int32)]
 
 
 class fk_write_desc(C.Structure):
@@ -232,6 +233,8 @@ def chain_desc(chain: dict):
         arr[i].n_consts = len(ks)
         for j, v in enumerate(ks[:4]):
             arr[i].consts[j] = v
+        arr[i].loop_span = op.get("span", 0)
+        arr[i].loop_count = op.get("count", 0)
     d = fk_chain_desc()
     d.read.kind = READ[chain["read"]["kind"]]
     d.read.in_dtype = DTYPE[chain["read"]["dtype"]]

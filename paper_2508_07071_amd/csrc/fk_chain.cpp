@@ -9,7 +9,10 @@
 // Run-time op list: swaps moved to the read (each later-crossed op's
 // per-channel constants permuted), CVT dropped, SUB -> ADD(-k), and unless
 // strict, MUL immediately followed by ADD -> FMA.  Every rewrite preserves
-// the per-element fp32 arithmetic exactly except the contraction.
+// the per-element fp32 arithmetic exactly except the contraction.  A loop
+// becomes a LOOP record after its body's records; contraction pairs only
+// records of one run: a loop body, or the stretch between two loop
+// boundaries (a MUL that repeats cannot absorb an ADD that does not).
 void fk::normalise_chain(const fk_chain_desc *ch, bool strict, std::vector<OpRec> &ops,
                          int32_t &swap)
 {
@@ -20,12 +23,26 @@ void fk::normalise_chain(const fk_chain_desc *ch, bool strict, std::vector<OpRec
         after[i] = after[i + 1] ^ (ch->ops[i].kind == FK_OP_SWAP_RB ? 1 : 0);
     swap = (C >= 3) ? after[0] : 0;
     std::vector<OpRec> lin;
+    std::vector<int> run;  // run id of each record in `lin`
+    int cur = 0;
     for (int i = 0; i < ch->n_ops; ++i) {
         const fk_op_desc &d = ch->ops[i];
         if (d.kind == FK_OP_SWAP_RB || d.kind == FK_OP_CVT_F32)
             continue;
         OpRec r;
         std::memset(&r, 0, sizeof r);
+        if (d.kind == FK_OP_LOOP) {
+            // the body's ops are arithmetic, one record each: the last loop_span
+            const int body = ++cur;
+            for (size_t j = lin.size() - (size_t)d.loop_span; j < lin.size(); ++j)
+                run[j] = body;
+            r.code = OPC_LOOP;
+            r.count = d.loop_count;
+            lin.push_back(r);
+            run.push_back(++cur);
+            ++cur;
+            continue;
+        }
         float k[4];
         for (int c = 0; c < 4; ++c)
             k[c] = d.n_consts == 1 ? d.consts[0] : (c < C ? d.consts[c] : 0.0f);
@@ -44,10 +61,13 @@ void fk::normalise_chain(const fk_chain_desc *ch, bool strict, std::vector<OpRec
         for (int c = 0; c < 4; ++c)
             r.a[c] = k[c];
         lin.push_back(r);
+        run.push_back(cur);
     }
     ops.clear();
+    std::vector<int> orun;
     for (size_t i = 0; i < lin.size(); ++i) {
-        if (!strict && lin[i].code == OPC_MUL && i + 1 < lin.size() && lin[i + 1].code == OPC_ADD) {
+        if (!strict && lin[i].code == OPC_MUL && i + 1 < lin.size() &&
+            lin[i + 1].code == OPC_ADD && run[i] == run[i + 1]) {
             OpRec f = lin[i];
             f.code = OPC_FMA;
             for (int c = 0; c < 4; ++c)
@@ -57,7 +77,33 @@ void fk::normalise_chain(const fk_chain_desc *ch, bool strict, std::vector<OpRec
         } else {
             ops.push_back(lin[i]);
         }
+        orun.push_back(run[i]);
     }
+    // a LOOP's span: the records of its body, the run just before it
+    for (size_t k = 0; k < ops.size(); ++k) {
+        if (ops[k].code != OPC_LOOP)
+            continue;
+        int n = 0;
+        for (size_t j = k; j > 0 && orun[j - 1] == orun[k - 1]; --j)
+            ++n;
+        ops[k].span = n;
+    }
+}
+
+// Runs of each record code when the list executes, loops unrolled
+// (cnt[OPC_MUL .. OPC_FMA]; LOOP records themselves are not counted).
+void fk::executed_counts(const std::vector<OpRec> &ops, double cnt[4])
+{
+    for (int c = 0; c < 4; ++c)
+        cnt[c] = 0.0;
+    std::vector<double> times(ops.size(), 1.0);
+    for (size_t k = 0; k < ops.size(); ++k)
+        if (ops[k].code == OPC_LOOP)
+            for (size_t j = k - (size_t)ops[k].span; j < k; ++j)
+                times[j] = ops[k].count;
+    for (size_t k = 0; k < ops.size(); ++k)
+        if (ops[k].code != OPC_LOOP)
+            cnt[ops[k].code] += times[k];
 }
 
 // Compile-time chains built into the library.
@@ -84,17 +130,30 @@ int fk::match_static(const fk_chain_desc *ch, std::vector<float> &consts, int &n
         ch->write.out_dtype == FK_F32 && ch->write.layout == FK_PACKED && ch->n_ops >= 2 &&
         o[0].kind == FK_OP_CVT_F32) {
         const int N = ch->n_ops - 1;
-        if (N != 1 && N != 4 && N != 16 && N != 64 && N != 256)
-            return FAM_RUNTIME;
-        consts.assign(N, 0.0f);
-        for (int k = 0; k < N; ++k) {
+        bool ok = N == 1 || N == 4 || N == 16 || N == 64 || N == 256;
+        for (int k = 0; ok && k < N; ++k) {
             const fk_op_desc &d = o[1 + k];
-            if (d.kind != (k % 2 == 0 ? FK_OP_MUL : FK_OP_ADD) || d.n_consts != 1)
-                return FAM_RUNTIME;
-            consts[k] = d.consts[0];
+            ok = d.kind == (k % 2 == 0 ? FK_OP_MUL : FK_OP_ADD) && d.n_consts == 1;
         }
-        n_ops = N;
-        return FAM_MULADD;
+        if (ok) {
+            consts.assign(N, 0.0f);
+            for (int k = 0; k < N; ++k)
+                consts[k] = o[1 + k].consts[0];
+            n_ops = N;
+            return FAM_MULADD;
+        }
+    }
+    // plain u8 (1 or 3 channels) -> cvt, mul, add (scalar), loop over both -> packed f32
+    if (ch->read.kind == FK_READ_PLAIN && ch->read.in_dtype == FK_U8 &&
+        (ch->read.channels == 1 || ch->read.channels == 3) && ch->write.out_dtype == FK_F32 &&
+        ch->write.layout == FK_PACKED && ch->n_ops == 4 && o[0].kind == FK_OP_CVT_F32 &&
+        o[1].kind == FK_OP_MUL && o[1].n_consts == 1 && o[2].kind == FK_OP_ADD &&
+        o[2].n_consts == 1 && o[3].kind == FK_OP_LOOP && o[3].loop_span == 2) {
+        consts.assign(2, 0.0f);
+        consts[0] = o[1].consts[0];
+        consts[1] = o[2].consts[0];
+        n_ops = o[3].loop_count;
+        return FAM_MULADD_LOOP;
     }
     return FAM_RUNTIME;
 }

@@ -14,8 +14,11 @@ namespace fk {
 // Run-time tier op list for a validated chain (see fk_chain.cpp); swap = 1
 // when the read must exchange channels 0 and 2.
 void normalise_chain(const fk_chain_desc *ch, bool strict, std::vector<OpRec> &ops, int32_t &swap);
-// FAM_NORMALIZE / FAM_MULADD with their constants when the chain is one of
-// the compile-time chains, else FAM_RUNTIME.
+// Executed records per code (loops unrolled) of a normalised list.
+void executed_counts(const std::vector<OpRec> &ops, double cnt[4]);
+// FAM_NORMALIZE / FAM_MULADD / FAM_MULADD_LOOP with their constants (and
+// op count, or the loop's count of pairs) when the chain is one of the
+// compile-time chains, else FAM_RUNTIME.
 int match_static(const fk_chain_desc *ch, std::vector<float> &consts, int &n_ops);
 
 }  // namespace fk

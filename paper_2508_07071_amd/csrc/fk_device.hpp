@@ -482,17 +482,60 @@ struct StaticCompute {
     }
 };
 
+// Compile-time loop chain: one Mul and one Add (scalar constants, loaded
+// once) applied loop_count times; the body is compiled, the trip count is
+// a kernel argument, so code size does not grow with the count.
+template <bool Strict>
+struct LoopMulAddCompute {
+    template <int K, int C>
+    __device__ __forceinline__ static void apply(const KArgs &a, float (&v)[K][kUnitPx][C])
+    {
+        const FK_CONST float *k = cptr(a.consts);
+        const float m = k[0];
+        const float ad = k[1];
+        const int n = a.loop_count;
+#pragma unroll 8
+        for (int p = 0; p < n; ++p) {
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+#pragma unroll
+                for (int i = 0; i < kUnitPx; ++i)
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        if constexpr (Strict) {
+                            const float t = v[j][i][c] * m;
+                            v[j][i][c] = t + ad;
+                        } else {
+                            v[j][i][c] = fmaf(v[j][i][c], m, ad);
+                        }
+                    }
+        }
+    }
+};
+
 // ------------------------------------------------------ run-time ops --
 // The op list is uniform across the grid: each op is one scalar branch and
 // its constants come through the scalar cache, then applied to all
-// K * 4 * C values of the thread's tile.
+// K * 4 * C values of the thread's tile.  A LOOP record jumps back over its
+// body until the body has run `count` times (bodies hold no loops, so one
+// counter serves every loop of the list).
 struct RuntimeCompute {
     template <int K, int C>
     __device__ __forceinline__ static void apply(const KArgs &a, float (&v)[K][kUnitPx][C])
     {
         const FK_CONST OpRec *ops = cptr(a.ops);
+        int runs = 1;  // runs of the current loop body so far
         for (int o = 0; o < a.n_ops; ++o) {
             const int code = ops[o].code;
+            if (code == OPC_LOOP) {
+                if (runs < ops[o].count) {
+                    ++runs;
+                    o -= ops[o].span + 1;  // the loop's ++o lands on the body's first record
+                } else {
+                    runs = 1;
+                }
+                continue;
+            }
             float ka[C], kb[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) {

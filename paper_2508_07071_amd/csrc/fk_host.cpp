@@ -83,9 +83,21 @@ fk_status fk::validate_chain(const fk_chain_desc *ch)
         return set_error(FK_ERR_INVALID_ARG, "ops is null");
     for (int32_t i = 0; i < ch->n_ops; ++i) {
         const fk_op_desc &op = ch->ops[i];
-        if (op.kind < FK_OP_SWAP_RB || op.kind > FK_OP_DIV)
+        if (op.kind < FK_OP_SWAP_RB || op.kind > FK_OP_LOOP)
             return set_error(FK_ERR_INVALID_ARG, "op %d: unknown kind %d", i, op.kind);
-        if (op.kind == FK_OP_SWAP_RB || op.kind == FK_OP_CVT_F32) {
+        if (op.kind == FK_OP_LOOP) {
+            if (op.n_consts != 0)
+                return set_error(FK_ERR_INVALID_ARG, "op %d: a loop takes no constants", i);
+            if (op.loop_span < 1 || op.loop_span > i)
+                return set_error(FK_ERR_INVALID_ARG, "op %d: loop span %d outside 1..%d", i,
+                                 op.loop_span, i);
+            if (op.loop_count < 1)
+                return set_error(FK_ERR_INVALID_ARG, "op %d: loop count %d < 1", i, op.loop_count);
+            for (int32_t j = i - op.loop_span; j < i; ++j)
+                if (ch->ops[j].kind < FK_OP_MUL || ch->ops[j].kind > FK_OP_DIV)
+                    return set_error(FK_ERR_INVALID_ARG,
+                                     "op %d: a loop body holds MUL/ADD/SUB/DIV only (op %d)", i, j);
+        } else if (op.kind == FK_OP_SWAP_RB || op.kind == FK_OP_CVT_F32) {
             if (op.n_consts != 0)
                 return set_error(FK_ERR_INVALID_ARG, "op %d: takes no constants", i);
         } else if (op.n_consts != 1 && op.n_consts != r.channels) {
@@ -166,11 +178,13 @@ extern "C" fk_status fk_items_validate(const fk_chain_desc *chain, const fk_item
 static const fk_launch_config kDefaultConfig = {256, 1};
 
 // Default launch configuration: 256 threads; long op lists get coarsening 4
-// so that each scalar constant load is amortised over more values.
+// so that each scalar constant load is amortised over more values.  The
+// compile-time loop chain loads its two constants once, so it keeps
+// coarsening 1 and with it the most waves for its arithmetic.
 static fk_launch_config default_config(const fk_plan *p)
 {
     fk_launch_config c = kDefaultConfig;
-    if (p->ops.size() > 32 || p->static_n > 64)
+    if (p->ops.size() > 32 || (p->family == FAM_MULADD && p->static_n > 64))
         c.coarsen = 4;
     return c;
 }
@@ -188,6 +202,8 @@ const void *fk::plan_kernel(const fk_plan *p, const fk_launch_config &cfg)
     switch (p->family) {
     case FAM_NORMALIZE: return kernel_normalize(cfg.coarsen, p->opts.strict_fp);
     case FAM_MULADD: return kernel_muladd(p->static_n, cfg.coarsen, p->opts.strict_fp);
+    case FAM_MULADD_LOOP:
+        return kernel_muladd_loop(p->chain.read.channels, cfg.coarsen, p->opts.strict_fp);
     default:
         return kernel_runtime(p->chain.read.kind, p->chain.read.in_dtype, p->chain.read.channels,
                               p->chain.write.out_dtype, p->chain.write.layout, cfg.coarsen);
@@ -436,6 +452,7 @@ KArgs fk::make_args(const fk_plan *p, void *d_table)
     a.n_ops = (int32_t)p->ops.size();
     a.swap = p->family == FAM_RUNTIME ? p->swap : 0;
     a.strict = p->opts.strict_fp;
+    a.loop_count = p->family == FAM_MULADD_LOOP ? p->static_n : 0;
     return a;
 }
 

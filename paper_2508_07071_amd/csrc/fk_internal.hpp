@@ -15,8 +15,9 @@ enum : int32_t { LY_PACKED = 0, LY_PLANAR = 1 };
 // Normalised compute op codes.  SUB becomes ADD of the negated constant
 // (IEEE x - y is x + (-y)), CVT disappears (fp32 from the read on), swaps
 // move to the read, and in the contracted mode a MUL followed by ADD/SUB
-// becomes FMA.
-enum : int32_t { OPC_MUL = 0, OPC_ADD = 1, OPC_DIV = 2, OPC_FMA = 3 };
+// becomes FMA.  LOOP sends execution back over the `span` records before
+// it until they have run `count` times.
+enum : int32_t { OPC_MUL = 0, OPC_ADD = 1, OPC_DIV = 2, OPC_FMA = 3, OPC_LOOP = 4 };
 
 constexpr int kUnitPx = 4;       // output pixels per unit: one 16-byte planar fp32 store
 constexpr int kMaxBlock = 1024;  // largest block the kernels accept
@@ -24,7 +25,9 @@ constexpr int kWave = 64;        // CDNA wavefront
 
 struct OpRec {          // 48 bytes
     int32_t code;
-    int32_t pad[3];
+    int32_t span;       // LOOP: body records just before this one
+    int32_t count;      // LOOP: runs of the body in all (>= 1)
+    int32_t pad;
     float a[4];         // MUL/ADD/DIV constant per channel, or FMA multiplier
     float b[4];         // FMA addend per channel
 };
@@ -85,11 +88,11 @@ struct KArgs {
     int32_t n_ops;
     int32_t swap;          // net BGR<->RGB swap applied at the read
     int32_t strict;        // compile-time tier: 1 = no contraction
+    int32_t loop_count;    // compile-time loop chain: pairs to run
     int32_t inl_n;         // > 0: the run's items are in `inl`
     int32_t inl_compact;   // 1: compact form
     uint32_t inl_total_tiles;
     uint32_t inl_tiles_per_item;  // compact form
-    int32_t pad;
     int64_t inl_dst_stride;       // compact form: bytes between item outputs
     alignas(16) uint8_t inl[kInlineBytes];
 };
@@ -99,6 +102,7 @@ enum : int32_t {
     FAM_RUNTIME = 0,       // any chain: run-time op list
     FAM_NORMALIZE = 1,     // crop+resize u8x3 -> swap,cvt,mul,sub,div -> planar f32
     FAM_MULADD = 2,        // plain u8x3 -> cvt, N x (mul, add) -> packed f32
+    FAM_MULADD_LOOP = 3,   // plain u8x1/u8x3 -> cvt, mul, add, loop(2, P) -> packed f32
 };
 
 // Kernel lookup (defined by the kernel translation units).  Returns the
@@ -108,5 +112,6 @@ const void *kernel_runtime(int read_kind, int in_dt, int channels, int out_dt, i
                            int coarsen);
 const void *kernel_normalize(int coarsen, int strict);
 const void *kernel_muladd(int n_ops, int coarsen, int strict);
+const void *kernel_muladd_loop(int channels, int coarsen, int strict);
 
 }  // namespace fk

@@ -346,14 +346,13 @@ extern "C" fk_status fk_model_features(const fk_plan *p, const fk_item *items, i
         f[17] = lg2(soh / n);
         f[18] = (float)std::log2(ssx / n);
         f[19] = (float)std::log2(ssy / n);
-        int cnt[4] = {0, 0, 0, 0};
-        for (const OpRec &o : p->ops)
-            cnt[o.code] += 1;
-        f[20] = (float)p->ops.size() / 64.0f;
-        f[21] = cnt[OPC_FMA] / 64.0f;
-        f[22] = cnt[OPC_MUL] / 64.0f;
-        f[23] = cnt[OPC_ADD] / 64.0f;
-        f[24] = cnt[OPC_DIV] / 64.0f;
+        double cnt[4];
+        executed_counts(p->ops, cnt);
+        f[20] = (float)((cnt[0] + cnt[1] + cnt[2] + cnt[3]) / 64.0);
+        f[21] = (float)(cnt[OPC_FMA] / 64.0);
+        f[22] = (float)(cnt[OPC_MUL] / 64.0);
+        f[23] = (float)(cnt[OPC_ADD] / 64.0);
+        f[24] = (float)(cnt[OPC_DIV] / 64.0);
         f[25] = (float)p->swap;
         f[26] = p->family != FAM_RUNTIME ? 1.0f : 0.0f;
         f[27] = (float)(vsrc / n);

@@ -277,15 +277,22 @@ static fk_status run_item_unfused(const fk_plan *p, const fk_item &it, uint8_t *
         cur_dt = DT_F32;
     }
     const bool direct = p->chain.write.layout == FK_PACKED && p->chain.write.out_dtype == FK_F32;
-    int last_op = -1;
-    for (int i = 0; i < p->chain.n_ops; ++i)
-        if (p->chain.ops[i].kind != FK_OP_SWAP_RB || C >= 3)
-            last_op = i;
+    // one kernel per op as the chain executes: a loop's body once per run
+    std::vector<int> seq;
     for (int i = 0; i < p->chain.n_ops; ++i) {
         const fk_op_desc &d = p->chain.ops[i];
-        if (d.kind == FK_OP_SWAP_RB && C < 3)
-            continue;  // a no-op: no kernel
-        float *o = (direct && i == last_op) ? (float *)it.dst : buf[nb];
+        if (d.kind == FK_OP_LOOP) {
+            for (int r = 1; r < d.loop_count; ++r)
+                for (int j = i - d.loop_span; j < i; ++j)
+                    seq.push_back(j);
+        } else if (d.kind != FK_OP_SWAP_RB || C >= 3) {  // a 1-channel swap is no kernel
+            seq.push_back(i);
+        }
+    }
+    for (size_t s = 0; s < seq.size(); ++s) {
+        const fk_op_desc &d = p->chain.ops[seq[s]];
+        const bool last = s + 1 == seq.size();
+        float *o = (direct && last) ? (float *)it.dst : buf[nb];
         if (o != (float *)it.dst)
             nb ^= 1;
         if (d.kind == FK_OP_SWAP_RB) {
@@ -311,7 +318,7 @@ static fk_status run_item_unfused(const fk_plan *p, const fk_item &it, uint8_t *
         cur = o;
         cur_dt = DT_F32;
     }
-    if (!(direct && last_op >= 0)) {
+    if (!(direct && !seq.empty())) {
         const int planar = p->chain.write.layout == FK_PLANAR;
         if (p->chain.write.out_dtype == FK_F16)
             write_out<DT_F16>(cur_dt, cur, it.dst, npix, C, planar, st);

@@ -128,3 +128,31 @@ def test_plan_create_without_gpu_fails_cleanly():
     with pytest.raises(fk.FKError) as e:
         fk.fk_plan_create(d, 4)
     assert e.value.status == fk.FK_ERR_HIP
+
+
+LOOP_CASES = [
+    ([{"kind": "mul", "k": [2.0]}, {"kind": "add", "k": [1.0]}, {"kind": "loop", "span": 2, "count": 9}], True),
+    ([{"kind": "mul", "k": [2.0]}, {"kind": "loop", "span": 1, "count": 1}], True),
+    ([{"kind": "cvt", "k": []}, {"kind": "div", "k": [3.0]}, {"kind": "loop", "span": 1, "count": 1 << 30},
+      {"kind": "swap", "k": []}], True),
+    ([{"kind": "loop", "span": 1, "count": 2}], False),
+    ([{"kind": "mul", "k": [2.0]}, {"kind": "loop", "span": 2, "count": 2}], False),
+    ([{"kind": "mul", "k": [2.0]}, {"kind": "loop", "span": 1, "count": 0}], False),
+    ([{"kind": "swap", "k": []}, {"kind": "mul", "k": [2.0]}, {"kind": "loop", "span": 2, "count": 2}], False),
+    ([{"kind": "cvt", "k": []}, {"kind": "loop", "span": 1, "count": 2}], False),
+    ([{"kind": "mul", "k": [2.0]}, {"kind": "loop", "span": 1, "count": 2}, {"kind": "loop", "span": 2, "count": 2}],
+     False),
+    ([{"kind": "mul", "k": [2.0]}, {"kind": "loop", "span": 1, "count": 2, "k": [1.0]}], False),
+]
+
+
+@pytest.mark.parametrize("ops,ok", LOOP_CASES)
+def test_loop_validation_agrees_with_oracle(ops, ok):
+    import numpy as np
+    import oracle
+    ch = {"read": {"kind": "plain", "dtype": "u8", "channels": 3, "out_w": 0, "out_h": 0},
+          "ops": ops, "write": {"dtype": "f32", "layout": "packed"}}
+    lib_ok = fk.fk_chain_validate(fk.chain_desc(ch)) == fk.FK_OK
+    fr = np.zeros((4, 4, 3), np.uint8)
+    orc_ok = oracle.validate(ch, [fr], [{"frame": 0, "x": 0, "y": 0, "w": 4, "h": 4}]) == 0
+    assert lib_ok == orc_ok == ok

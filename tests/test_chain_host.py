@@ -26,8 +26,8 @@ int main() {
     while (std::scanf("%d %d %d %d %d %d %d", &C, &n, &strict, &rk, &dt, &odt, &lay) == 7) {
         std::vector<fk_op_desc> ops(n);
         for (auto &o : ops)
-            std::scanf("%d %d %a %a %a %a", &o.kind, &o.n_consts, &o.consts[0], &o.consts[1],
-                       &o.consts[2], &o.consts[3]);
+            std::scanf("%d %d %a %a %a %a %d %d", &o.kind, &o.n_consts, &o.consts[0], &o.consts[1],
+                       &o.consts[2], &o.consts[3], &o.loop_span, &o.loop_count);
         fk_chain_desc ch{};
         ch.read.kind = rk; ch.read.in_dtype = dt; ch.read.channels = C;
         ch.ops = ops.data(); ch.n_ops = n;
@@ -40,16 +40,16 @@ int main() {
         int fam = fk::match_static(&ch, k, sn);
         std::printf("%d %zu %d %d %zu\n", swap, rec.size(), fam, sn, k.size());
         for (auto &r : rec)
-            std::printf("%d %a %a %a %a %a %a %a %a\n", r.code, r.a[0], r.a[1], r.a[2], r.a[3],
-                        r.b[0], r.b[1], r.b[2], r.b[3]);
+            std::printf("%d %a %a %a %a %a %a %a %a %d %d\n", r.code, r.a[0], r.a[1], r.a[2], r.a[3],
+                        r.b[0], r.b[1], r.b[2], r.b[3], r.span, r.count);
         for (float v : k) std::printf("%a\n", v);
     }
     return 0;
 }
 """
 
-OPC_MUL, OPC_ADD, OPC_DIV, OPC_FMA = 0, 1, 2, 3
-FAM_RUNTIME, FAM_NORMALIZE, FAM_MULADD = 0, 1, 2
+OPC_MUL, OPC_ADD, OPC_DIV, OPC_FMA, OPC_LOOP = 0, 1, 2, 3, 4
+FAM_RUNTIME, FAM_NORMALIZE, FAM_MULADD, FAM_MULADD_LOOP = 0, 1, 2, 3
 
 
 @pytest.fixture(scope="module")
@@ -69,8 +69,9 @@ def driver():
                              f"{int(r['kind'] == 'crop_resize')} {['u8', 'f16', 'f32'].index(r['dtype'])} "
                              f"{['u8', 'f16', 'f32'].index(w['dtype'])} {int(w['layout'] == 'planar')}")
                 for o in ch["ops"]:
-                    k = list(o["k"]) + [0.0] * (4 - len(o["k"]))
-                    lines.append(f"{KINDS[o['kind']]} {len(o['k'])} " + " ".join(float(v).hex() for v in k))
+                    k = list(o.get("k", [])) + [0.0] * (4 - len(o.get("k", [])))
+                    lines.append(f"{KINDS.get(o['kind'], 6)} {len(o.get('k', []))} " + " ".join(float(v).hex() for v in k)
+                                 + f" {o.get('span', 0)} {o.get('count', 0)}")
             out = subprocess.run([exe], input="\n".join(lines) + "\n", capture_output=True, text=True,
                                  check=True).stdout.split("\n")
             res, i = [], 0
@@ -81,7 +82,8 @@ def driver():
                 for _ in range(n):
                     f = out[i].split()
                     ops.append((int(f[0]), np.array([float.fromhex(v) for v in f[1:5]], np.float32),
-                                np.array([float.fromhex(v) for v in f[5:9]], np.float32)))
+                                np.array([float.fromhex(v) for v in f[5:9]], np.float32),
+                                int(f[9]), int(f[10])))
                     i += 1
                 ks = [float.fromhex(out[i + j]) for j in range(nk)]
                 i += nk
@@ -91,11 +93,23 @@ def driver():
 
 
 def evaluate(frame, C, swap, ops):
-    """The normalised list applied to a packed frame, fp32 per operation."""
+    """The normalised list applied to a packed frame, fp32 per operation; a
+    LOOP record sends execution back over its `span` records until they
+    have run `count` times."""
     x = frame.astype(np.float32).reshape(-1, C)
     if swap:
         x = x[:, [2, 1, 0] + list(range(3, C))]
-    for code, a, b in ops:
+    o, runs = 0, 1
+    while o < len(ops):
+        code, a, b, span, count = ops[o]
+        o += 1
+        if code == OPC_LOOP:
+            if runs < count:
+                runs += 1
+                o -= span + 1
+            else:
+                runs = 1
+            continue
         a, b = a[:C], b[:C]
         if code == OPC_MUL:
             x = x * a
@@ -120,6 +134,18 @@ def random_chain(g, C, dtype, max_ops=24):
     return ch
 
 
+def add_loops(g, ops):
+    """Insert loop ops after random runs of arithmetic ops."""
+    out, run = [], 0
+    for o in ops:
+        out.append(o)
+        run = run + 1 if o["kind"] in ("mul", "add", "sub", "div") else 0
+        if run and g.uniform() < 0.3:
+            out.append({"kind": "loop", "span": int(g.integers(1, run + 1)), "count": int(g.integers(1, 5))})
+            run = 0
+    return out
+
+
 @pytest.mark.parametrize("strict", [True, False])
 def test_normalised_list_matches_oracle(driver, strict):
     g = datagen.rng(11 + strict)
@@ -128,6 +154,8 @@ def test_normalised_list_matches_oracle(driver, strict):
         C = [1, 3, 4][t % 3]
         dtype = ["u8", "f32"][(t // 3) % 2]
         ch = random_chain(g, C, dtype)
+        if t % 5 == 1:  # loops over runs of arithmetic ops
+            ch["ops"] = add_loops(g, ch["ops"])
         if t % 7 == 0:  # swaps around per-channel constants
             ch["ops"] = [{"kind": "mul", "k": [1.5, 0.75, 0.625, 1.25][:C]}, {"kind": "swap", "k": []},
                          {"kind": "sub", "k": [0.25, -0.5, 0.125, 1.0][:C]}, {"kind": "swap", "k": []},
@@ -141,8 +169,9 @@ def test_normalised_list_matches_oracle(driver, strict):
     for (ch, fr), (swap, ops, _, _, _) in zip(cases, outs):
         C = ch["read"]["channels"]
         n_arith = sum(o["kind"] in ("mul", "add", "sub", "div") for o in ch["ops"])
-        assert len(ops) <= n_arith and (not strict or len(ops) == n_arith)
-        assert all(code != OPC_FMA for code, _, _ in ops) or not strict
+        n_loops = sum(o["kind"] == "loop" for o in ch["ops"])
+        assert len(ops) <= n_arith + n_loops and (not strict or len(ops) == n_arith + n_loops)
+        assert all(op[0] != OPC_FMA for op in ops) or not strict
         n_swaps = sum(o["kind"] == "swap" for o in ch["ops"])
         assert swap == (n_swaps % 2 if C >= 3 else 0)
         got = evaluate(fr, C, swap, ops)
@@ -162,7 +191,7 @@ def test_contraction_pairs_mul_then_add_only(driver):
                   {"kind": "cvt", "k": []}, {"kind": "add", "k": [0.5]},
                   {"kind": "mul", "k": [5.0]}, {"kind": "div", "k": [2.0]}]}
     (swap, ops, fam, _, _), = driver([(ch, False)])
-    codes = [c for c, _, _ in ops]
+    codes = [op[0] for op in ops]
     # mul,sub -> fma(2,-k); add stays; mul,(cvt),add -> fma; mul; div
     assert codes == [OPC_FMA, OPC_ADD, OPC_FMA, OPC_MUL, OPC_DIV]
     np.testing.assert_array_equal(ops[0][1][:3], [2, 2, 2])
@@ -179,7 +208,21 @@ def test_static_chain_match(driver):
     g = datagen.rng(0)
     for n in (1, 2, 4, 16, 64, 256, 257):
         cases.append((datagen.muladd_chain(n, g), True))
+    loop3 = datagen.loop_chain(1000, g, channels=3)
+    loop4 = datagen.loop_chain(7, g, channels=1)
+    loop4["ops"][3]["span"] = 1
+    cases += [(datagen.loop_chain(10000, g), False), (loop3, True), (loop4, True)]
     res = driver(cases)
+    r1, r3, r4 = res[-3:]
+    assert r1[2] == FAM_MULADD_LOOP and r1[3] == 10000 and r3[2] == FAM_MULADD_LOOP and r3[3] == 1000
+    assert r1[4] == [np.float32(cases[-3][0]["ops"][1]["k"][0]), np.float32(cases[-3][0]["ops"][2]["k"][0])]
+    assert r4[2] == FAM_RUNTIME
+    # contracted loop body: one FMA record, then LOOP(span 1, count P)
+    assert [op[0] for op in r1[1]] == [OPC_FMA, OPC_LOOP] and r1[1][1][3:] == (1, 10000)
+    assert [op[0] for op in r3[1]] == [OPC_MUL, OPC_ADD, OPC_LOOP] and r3[1][2][3:] == (2, 1000)
+    # a loop over the add only: mul must not absorb it
+    assert [op[0] for op in r4[1]] == [OPC_MUL, OPC_ADD, OPC_LOOP] and r4[1][2][3:] == (1, 7)
+    res, cases = res[:-3], cases[:-3]
     assert res[0][2] == FAM_NORMALIZE and res[0][3] == 5
     k = res[0][4]
     assert k[0] == np.float32(norm["ops"][2]["k"][0])
