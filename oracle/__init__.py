@@ -23,11 +23,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "fk_oracle.c")
 LIB = os.path.join(HERE, "libfkoracle.so")
 
-_DT = {"u8": 0, "f16": 1, "f32": 2}
+_DT = {"u8": 0, "f16": 1, "f32": 2, "f64": 3}
 _READ = {"plain": 0, "crop_resize": 1}
 _OP = {"swap": 0, "cvt": 1, "mul": 2, "add": 3, "sub": 4, "div": 5, "loop": 6}
-_LAYOUT = {"packed": 0, "planar": 1}
-_NP_OUT = {"f32": np.float32, "f16": np.float16}
+_LAYOUT = {"packed": 0, "planar": 1, "stats": 2}
+_NP_OUT = {"f32": np.float32, "f16": np.float16, "f64": np.float64}
 
 
 class _Op(C.Structure):
@@ -102,6 +102,8 @@ def _chain_struct(chain: dict):
 
 def out_shape(chain: dict, item: dict) -> tuple:
     C_ = chain["read"]["channels"]
+    if chain["write"]["layout"] == "stats":
+        return (C_, 4)  # per channel: min, max, sum, mean
     if chain["read"]["kind"] == "crop_resize":
         oh, ow = item["out_h"], item["out_w"]
     else:
@@ -113,8 +115,11 @@ def run_chain(chain: dict, frames: list, items: list, shadow: bool = True) -> li
     """Run `chain` on each item.  Returns one dict per item with ``out`` (the
     chain's output dtype and layout), and, if `shadow`, ``v64`` (fp64 shadow)
     and ``smax`` (largest |value| the element took), same shape as ``out``.
-    Raises ValueError if the oracle rejects the chain or an item."""
+    A stats write gives ``out`` of shape (C, 4) = per channel min, max, sum,
+    mean, and no shadow.  Raises ValueError if the oracle rejects the chain
+    or an item."""
     L = lib()
+    shadow = shadow and chain["write"]["layout"] != "stats"
     ch, _keep = _chain_struct(chain)
     frames = [np.ascontiguousarray(f) for f in frames]
     results = []

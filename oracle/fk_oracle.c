@@ -38,6 +38,13 @@
  *    no contraction; Div is a true division.
  *  - Write: packed out[(y*W + x)*C + c] or planar out[(c*H + y)*W + x];
  *    fp16 outputs round to nearest even.
+ *  - Stats write (the reduction pattern of Section IV-C: several reductions
+ *    of one matrix from a single read): instead of an image, each item's
+ *    output is, per channel c, {min, max, sum, mean} of the chain's fp32
+ *    values, as four doubles at dst[4c .. 4c+3].  min and max are IEEE
+ *    minNum/maxNum over the values in row-major order (a NaN value is
+ *    skipped); sum adds the values converted to fp64 in row-major order;
+ *    mean = sum / (number of pixels), in fp64.
  *  - Loop (the repeat op of Section VI-B, which applies one op many times
  *    without spending kernel parameters on each copy): the `span` ops just
  *    before it run `count` times in all, in order, before the chain goes
@@ -51,10 +58,10 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { ORC_U8 = 0, ORC_F16 = 1, ORC_F32 = 2 };
+enum { ORC_U8 = 0, ORC_F16 = 1, ORC_F32 = 2, ORC_F64 = 3 };
 enum { ORC_READ_PLAIN = 0, ORC_READ_CROP_RESIZE = 1 };
 enum { ORC_SWAP = 0, ORC_CVT = 1, ORC_MUL = 2, ORC_ADD = 3, ORC_SUB = 4, ORC_DIV = 5, ORC_LOOP = 6 };
-enum { ORC_PACKED = 0, ORC_PLANAR = 1 };
+enum { ORC_PACKED = 0, ORC_PLANAR = 1, ORC_STATS = 2 };
 
 enum {
     ORC_OK = 0,
@@ -76,8 +83,8 @@ typedef struct {
     int32_t channels;
     const orc_op *ops;
     int32_t n_ops;
-    int32_t out_dtype; /* ORC_F32 or ORC_F16 */
-    int32_t layout;    /* ORC_PACKED or ORC_PLANAR */
+    int32_t out_dtype; /* ORC_F32 or ORC_F16; ORC_F64 with ORC_STATS */
+    int32_t layout;    /* ORC_PACKED, ORC_PLANAR or ORC_STATS */
 } orc_chain;
 
 typedef struct {
@@ -86,9 +93,10 @@ typedef struct {
     int64_t pitch;       /* bytes between frame rows */
     int32_t x, y, w, h;  /* region of interest */
     int32_t ow, oh;      /* output size (crop+resize); plain read uses w, h */
-    void *dst;           /* output image in the chain's output dtype/layout */
-    double *v64;         /* optional: fp64 shadow, same layout as dst */
-    float *smax;         /* optional: largest |value| along the chain */
+    void *dst;           /* output image in the chain's output dtype/layout,
+                            or 4 * channels doubles for ORC_STATS */
+    double *v64;         /* optional: fp64 shadow, same layout as dst (images only) */
+    float *smax;         /* optional: largest |value| along the chain (images only) */
 } orc_item;
 
 /* ---------------------------------------------------------------- fp16 -- */
@@ -354,6 +362,28 @@ static void step_write(const orc_chain *ch, const img *m, const orc_item *it)
             }
 }
 
+/* Per-channel statistics of the final image (the stats write). */
+static void step_stats(const img *m, const orc_item *it)
+{
+    int32_t C = m->C;
+    size_t npix = (size_t)m->w * (size_t)m->h;
+    double *out = (double *)it->dst;
+    for (int32_t c = 0; c < C; ++c) {
+        float mn = INFINITY, mx = -INFINITY;
+        double sum = 0.0;
+        for (size_t p = 0; p < npix; ++p) {
+            float v = m->v[p * (size_t)C + (size_t)c];
+            mn = fminf(mn, v);
+            mx = fmaxf(mx, v);
+            sum += (double)v;
+        }
+        out[4 * c + 0] = (double)mn;
+        out[4 * c + 1] = (double)mx;
+        out[4 * c + 2] = sum;
+        out[4 * c + 3] = sum / (double)npix;
+    }
+}
+
 /* ---------------------------------------------------------- validate -- */
 
 static int chain_ok(const orc_chain *ch)
@@ -366,10 +396,15 @@ static int chain_ok(const orc_chain *ch)
         return 0;
     if (ch->channels != 1 && ch->channels != 3 && ch->channels != 4)
         return 0;
-    if (ch->out_dtype != ORC_F32 && ch->out_dtype != ORC_F16)
-        return 0;
-    if (ch->layout != ORC_PACKED && ch->layout != ORC_PLANAR)
-        return 0;
+    if (ch->layout == ORC_STATS) {
+        if (ch->out_dtype != ORC_F64)
+            return 0;
+    } else {
+        if (ch->out_dtype != ORC_F32 && ch->out_dtype != ORC_F16)
+            return 0;
+        if (ch->layout != ORC_PACKED && ch->layout != ORC_PLANAR)
+            return 0;
+    }
     for (int32_t i = 0; i < ch->n_ops; ++i) {
         const orc_op *op = &ch->ops[i];
         if (op->kind < ORC_SWAP || op->kind > ORC_LOOP)
@@ -446,7 +481,9 @@ int orc_run(const orc_chain *ch, const orc_item *items, int32_t n)
             else
                 step_arith(&cur, op);
         }
-        if (!rc)
+        if (!rc && ch->layout == ORC_STATS)
+            step_stats(&cur, it);
+        else if (!rc)
             step_write(ch, &cur, it);
         img_free(&cur);
         if (rc)
