@@ -20,7 +20,7 @@ Printed JSON line:
 
 Other workloads (--workload), for the design notes, not the headline line:
 "hf" (batched uneven crops), "loop" (long Mul+Add chains through the loop
-op on a batch of small images), "serve" (the serving loop), "costmodel"
+op on a batch of small images), "stats" (the reduction write), "serve" (the serving loop), "costmodel"
 (training and evaluating the launch-configuration model) and "copy" (a
 plain device copy, the bandwidth reference).
 """
@@ -445,6 +445,98 @@ def loop_workload(args):
     return res
 
 
+def stats_workload(args):
+    """The stats write (Section IV-C's reduction pattern: min, max, sum and
+    mean per channel from one read).  Workload: 16 distinct 3840x2160x3 u8
+    frames (398 MB, beyond the 256 MB MALL), cvt then the stats write, one
+    item per frame.  Compared with: the fused transform writing the fp32
+    image followed by four torch reductions (amin, amax, sum, mean) over it,
+    and the unfused baseline (one kernel per op, then one reduction pass per
+    statistic).  Algorithmic bytes = the frames read once (the 16 x 3 x 4
+    doubles written are negligible)."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2508_07071_amd as fk
+
+    dev = torch.device("cuda:0")
+    stream = fk.stream_handle()
+    F, (H, W) = 16, FRAME_HW
+    g = datagen.rng(args.seed)
+    frames = [torch.from_numpy(datagen.frame(g, H, W, 3)).to(dev) for _ in range(F)]
+    chain = {"read": {"kind": "plain", "dtype": "u8", "channels": 3, "out_w": 0, "out_h": 0},
+             "ops": [{"kind": "cvt", "k": []}], "write": {"dtype": "f64", "layout": "stats"}}
+    items = [{"frame": f, "x": 0, "y": 0, "w": W, "h": H, "out_w": W, "out_h": H} for f in range(F)]
+    stats = torch.empty((F, 3, 4), dtype=torch.float64, device=dev)
+    arr = fk.make_items(chain, frames, items, [stats[f] for f in range(F)])
+    alg = F * H * W * 3
+
+    def timeit(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    plan = fk.fk_plan_create(fk.chain_desc(chain), F, fk.plan_opts())
+    res = {"frames": F, "alg_bytes": alg}
+    if args.autotune:
+        best, _ = fk.fk_autotune(plan, arr, F, 5)
+        res["autotuned"] = [best.block_threads, best.coarsen]
+    c = fk.fk_plan_get_config(plan)
+    res["launch_config"] = [c.block_threads, c.coarsen]
+    res["fused_ms"] = round(timeit(lambda: fk.fk_run(plan, arr, F, stream), 50), 5)
+    res["fused_gbps"] = round(alg / (res["fused_ms"] * 1e-3) / 1e9, 1)
+    res["hbm_frac"] = round(res["fused_gbps"] / HBM_PEAK_GBPS, 4)
+    # fused transform to fp32, then four library reductions over the image
+    img_chain = dict(chain, write={"dtype": "f32", "layout": "packed"})
+    img = torch.empty((F, H, W, 3), dtype=torch.float32, device=dev)
+    iplan = fk.fk_plan_create(fk.chain_desc(img_chain), F, fk.plan_opts())
+    iarr = fk.make_items(img_chain, frames, items, [img[f] for f in range(F)])
+
+    def transform_then_reduce():
+        fk.fk_run(iplan, iarr, F, stream)
+        v = img.view(F, -1, 3)
+        return torch.amin(v, 1), torch.amax(v, 1), torch.sum(v, 1, dtype=torch.float64), torch.mean(v, 1)
+    res["transform_then_torch_ms"] = round(timeit(transform_then_reduce, 10), 4)
+    fk.fk_plan_destroy(iplan)
+    del img
+    if not args.no_unfused:
+        nbytes = fk.fk_unfused_scratch_bytes(plan, arr, F)
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        res["unfused_ms"] = round(timeit(lambda: fk.fk_run_unfused(plan, arr, F, scratch.data_ptr(), nbytes,
+                                                                 stream), 3), 4)
+        res["speedup_vs_unfused"] = round(res["unfused_ms"] / res["fused_ms"], 1)
+        del scratch
+    res["speedup_vs_transform_then_torch"] = round(res["transform_then_torch_ms"] / res["fused_ms"], 1)
+    fk.fk_plan_destroy(plan)
+    log(res)
+    out = {"metric": "stats-write GB/s (min, max, sum, mean per channel from one read)",
+           "value": res["fused_gbps"], "unit": "GB/s", "n_gpus": 1, "higher_is_better": True,
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "stats: 16 x 3840x2160x3 u8 frames, cvt, per-channel min/max/sum/mean",
+                      "seed": args.seed},
+           "roofline": {"bound": "hbm", "achieved": res["fused_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                        "frac": res["hbm_frac"], "traffic": None,
+                        "kernel": "k_stats plain u8x3, 16 frames per launch", "kernel_ms": res["fused_ms"]},
+           "result": res}
+    if not args.no_cpu_baseline:
+        import oracle
+        fr = datagen.frame(datagen.rng(args.seed), H // 8, W, 3)
+        t0 = time.perf_counter()
+        oracle.run_chain(chain, [fr], [datagen.whole_frame_item(fr)])
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(fr.nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": 1,
+                               "kind": "oracle", "sample": f"one 3840x270x3 band, {dt:.2f} s single-threaded"}
+    return out
+
+
 def serve_workload(args):
     """Serving loop (config 4 sizes): open-loop Poisson arrivals, continuous
     batching vs per-request fused vs per-request unfused; p50/p99 latency."""
@@ -551,7 +643,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="vf", choices=["vf", "hf", "loop", "copy", "serve", "costmodel"])
+    ap.add_argument("--workload", default="vf", choices=["vf", "hf", "loop", "stats", "copy", "serve", "costmodel"])
     ap.add_argument("--data", nargs="+", default=[], help="cost-model label shards")
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--rates", type=float, nargs="+", default=[200, 500, 1000, 2000])
@@ -583,6 +675,9 @@ def main():
         return
     if args.workload == "loop":
         print(json.dumps(loop_workload(args)))
+        return
+    if args.workload == "stats":
+        print(json.dumps(stats_workload(args)))
         return
     if args.workload == "serve":
         print(json.dumps(serve_workload(args)))

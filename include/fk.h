@@ -45,16 +45,31 @@ typedef int32_t fk_status;
 #define FK_ERR_BAD_STATE (-5)    /* call not allowed in the object's current state */
 #define FK_ERR_BUDGET (-6)       /* request exceeds a memory budget */
 
-/* Element types. */
+/* Element types.  FK_F64 is the output type of the stats write only. */
 #define FK_U8 0
 #define FK_F16 1
 #define FK_F32 2
+#define FK_F64 3
 
 /* Image layouts: packed HWC (out[(y*W + x)*C + c]) or planar CHW
  * (out[(c*H + y)*W + x]); Split is the packed-to-planar write op
  * (Section IV-B, the memory-ops figure). */
 #define FK_PACKED 0
 #define FK_PLANAR 1
+
+/* Stats write: the reduction pattern of Section IV-C, several reductions of
+ * one matrix from a single read.  Instead of an image, an item's output is,
+ * for each channel c, four doubles at dst[4c .. 4c+3]: the minimum, the
+ * maximum, the sum and the mean of the chain's fp32 values over the item's
+ * output pixels.  Min and max are IEEE minNum/maxNum (a NaN value is
+ * skipped; all NaN gives +inf / -inf); the sum accumulates the values in
+ * fp64 (in an order that depends on the launch configuration, within
+ * 2 (n - 1) 2^-53 sum|x| of any other order); mean = sum / n in fp64.
+ * Requires out_dtype = FK_F64; dst must be 8-byte aligned.  One plan runs
+ * one stats launch at a time (per-item completion counters live in the
+ * plan); launches of one plan on one stream are ordered, so that holds
+ * unless the caller overlaps streams. */
+#define FK_STATS 2
 
 /* Read operations (Section IV-B).
  * FK_READ_PLAIN: the item's region of interest read 1:1 (a crop when the
@@ -104,8 +119,8 @@ typedef struct {
 } fk_op_desc;
 
 typedef struct {
-    int32_t out_dtype; /* FK_F32 or FK_F16 (round to nearest even) */
-    int32_t layout;    /* FK_PACKED or FK_PLANAR */
+    int32_t out_dtype; /* FK_F32 or FK_F16 (round to nearest even); FK_F64 with FK_STATS */
+    int32_t layout;    /* FK_PACKED, FK_PLANAR or FK_STATS */
 } fk_write_desc;
 
 /* A chain: read -> ops[0..n_ops) -> write.  `ops` is copied at plan

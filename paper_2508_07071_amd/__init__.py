@@ -29,19 +29,19 @@ FK_ERR_HIP = -4
 FK_ERR_BAD_STATE = -5
 FK_ERR_BUDGET = -6
 
-FK_U8, FK_F16, FK_F32 = 0, 1, 2
-FK_PACKED, FK_PLANAR = 0, 1
+FK_U8, FK_F16, FK_F32, FK_F64 = 0, 1, 2, 3
+FK_PACKED, FK_PLANAR, FK_STATS = 0, 1, 2
 FK_READ_PLAIN, FK_READ_CROP_RESIZE = 0, 1
 FK_OP_SWAP_RB, FK_OP_CVT_F32, FK_OP_MUL, FK_OP_ADD, FK_OP_SUB, FK_OP_DIV, FK_OP_LOOP = range(7)
 FK_CONFIG_DEFAULT, FK_CONFIG_MANUAL, FK_CONFIG_AUTOTUNE, FK_CONFIG_MODEL = range(4)
 FK_TIER_AUTO, FK_TIER_RUNTIME = 0, 1
 
-DTYPE = {"u8": FK_U8, "f16": FK_F16, "f32": FK_F32}
-LAYOUT = {"packed": FK_PACKED, "planar": FK_PLANAR}
+DTYPE = {"u8": FK_U8, "f16": FK_F16, "f32": FK_F32, "f64": FK_F64}
+LAYOUT = {"packed": FK_PACKED, "planar": FK_PLANAR, "stats": FK_STATS}
 READ = {"plain": FK_READ_PLAIN, "crop_resize": FK_READ_CROP_RESIZE}
 OP = {"swap": FK_OP_SWAP_RB, "cvt": FK_OP_CVT_F32, "mul": FK_OP_MUL, "add": FK_OP_ADD,
       "sub": FK_OP_SUB, "div": FK_OP_DIV, "loop": FK_OP_LOOP}
-TORCH_DTYPE = {"u8": torch.uint8, "f16": torch.float16, "f32": torch.float32}
+TORCH_DTYPE = {"u8": torch.uint8, "f16": torch.float16, "f32": torch.float32, "f64": torch.float64}
 
 
 class fk_read_desc(C.Structure):
@@ -268,6 +268,8 @@ def make_items(chain: dict, frames: list, items: list, outs: list):
 
 def out_shape(chain: dict, item: dict) -> tuple:
     c = chain["read"]["channels"]
+    if chain["write"]["layout"] == "stats":
+        return (c, 4)  # per channel: min, max, sum, mean (fp64)
     if chain["read"]["kind"] == "crop_resize":
         oh, ow = item["out_h"], item["out_w"]
     else:

@@ -833,4 +833,214 @@ __global__ __launch_bounds__(kMaxBlock) void k_transform(const KArgs a)
     }
 }
 
+// ------------------------------------------------------------- stats --
+// The reduction pattern (Section IV-C's second data-parallel pattern): the
+// same read and compute ops as the transform, then per channel min, max and
+// an fp64 sum of the item's values, from one read of the source.
+//
+// A batch slot (item) is covered by `nslots` blocks; block slot s strides
+// over the item's tiles s, s + nslots, ...  Each block reduces its values
+// in a fixed order (lane order within a wave by xor-shuffles, then waves in
+// order), stores one StatPartial per channel, and takes a ticket on the
+// item's counter; the block drawing the last ticket combines the item's
+// partials in slot order, writes {min, max, sum, mean} and resets the
+// counter to zero for the next launch.  No block waits for another, so
+// every block finishes whatever the scheduling.
+
+template <int C>
+struct StatAcc {
+    float mn[C], mx[C];
+    double sum[C];
+    __device__ __forceinline__ void init()
+    {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            mn[c] = __builtin_inff();
+            mx[c] = -__builtin_inff();
+            sum[c] = 0.0;
+        }
+    }
+    __device__ __forceinline__ void add(const StatAcc &o)
+    {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            mn[c] = fminf(mn[c], o.mn[c]);
+            mx[c] = fmaxf(mx[c], o.mx[c]);
+            sum[c] += o.sum[c];
+        }
+    }
+    // lane 0 of the wave ends up with the wave's reduction (fixed xor tree)
+    __device__ __forceinline__ void wave_reduce()
+    {
+#pragma unroll
+        for (int m = kWave / 2; m >= 1; m >>= 1) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                mn[c] = fminf(mn[c], __shfl_xor(mn[c], m, kWave));
+                mx[c] = fmaxf(mx[c], __shfl_xor(mx[c], m, kWave));
+                sum[c] += __shfl_xor(sum[c], m, kWave);
+            }
+        }
+    }
+};
+
+// Block-wide reduction into thread 0 (waves combined in wave order).
+template <int C>
+__device__ __forceinline__ void block_reduce(StatAcc<C> &acc, StatPartial (*lds)[C], int tid,
+                                             int T)
+{
+    acc.wave_reduce();
+    const int wave = tid / kWave;
+    if ((tid % kWave) == 0) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            lds[wave][c] = StatPartial{acc.mn[c], acc.mx[c], acc.sum[c]};
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < T / kWave; ++w) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                acc.mn[c] = fminf(acc.mn[c], lds[w][c].mn);
+                acc.mx[c] = fmaxf(acc.mx[c], lds[w][c].mx);
+                acc.sum[c] += lds[w][c].sum;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <class Read, class Compute, int C, int K>
+__global__ __launch_bounds__(kMaxBlock) void k_stats(const KArgs a)
+{
+    __shared__ StatPartial red[kMaxBlock / kWave][C];
+    __shared__ uint32_t ticket;
+    const FK_CONST KArgs *ka = (const FK_CONST KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    const bool inl = a.inl_n > 0;
+    const bool compact = inl && a.inl_compact;
+    const FK_CONST uint32_t *tb =
+        inl ? (const FK_CONST uint32_t *)(ka->inl + kInlineTileBegin) : cptr(a.tile_begin);
+    const FK_CONST ItemRec *items = inl ? (const FK_CONST ItemRec *)ka->inl : cptr(a.items);
+    const int n_items = inl ? a.inl_n : cptr(a.hdr)->n_items;
+    const uint32_t total = inl ? a.inl_total_tiles : cptr(a.hdr)->total_tiles;
+    const int T = blockDim.x;
+    const int tid = threadIdx.x;
+    const uint32_t tile_units = (uint32_t)T * K;
+    const bool swap = a.swap != 0;
+
+    for (uint32_t slot = blockIdx.x; slot < total; slot += gridDim.x) {
+        int b;
+        ItemRec it;
+        uint32_t first, nslots;
+        if (compact) {
+            b = (int)(slot / a.inl_tiles_per_item);
+            first = (uint32_t)b * a.inl_tiles_per_item;
+            nslots = a.inl_tiles_per_item;
+            it = load_item(items);
+            const FK_CONST Roi16 *roi = (const FK_CONST Roi16 *)(ka->inl + 64) + b;
+            it.x = roi->x;
+            it.y = roi->y;
+            it.w = roi->w;
+            it.h = roi->h;
+            it.dst += (uint64_t)b * (uint64_t)a.inl_dst_stride;
+            if constexpr (Read::kind == RD_CROP_RESIZE) {
+                it.sx = (float)it.w / (float)it.ow;
+                it.sy = (float)it.h / (float)it.oh;
+            }
+            if ((it.x * C * Read::elem_size) % 4 != 0)
+                it.flags &= ~IF_SRC_VEC;
+        } else {
+            b = find_item(tb, n_items, slot);
+            it = load_item(items + b);
+            first = tb[b];
+            nslots = tb[b + 1] - first;
+        }
+        const uint32_t upr = (uint32_t)(it.ow + kUnitPx - 1) / kUnitPx;
+        const uint32_t units = upr * (uint32_t)it.oh;
+        const uint32_t item_tiles = (units + tile_units - 1) / tile_units;
+
+        StatAcc<C> acc;
+        acc.init();
+        // the K units of a thread run one at a time (read, ops, accumulate):
+        // only one unit's values are live, whatever K
+        for (uint32_t t = slot - first; t < item_tiles; t += nslots) {
+            const uint32_t ubase = t * tile_units;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const uint32_t u = ubase + (uint32_t)(j * T + tid);
+                if (u >= units)
+                    continue;
+                const uint32_t row = u / upr;
+                const int ox0 = (int)(u - row * upr) * kUnitPx;
+                const int left = it.ow - ox0;
+                const int nv = left < kUnitPx ? left : kUnitPx;
+                float v[1][kUnitPx][C];
+                Read::load(it, (int)row, ox0, nv, v[0]);
+                if constexpr (C >= 3) {
+                    if (swap) {
+#pragma unroll
+                        for (int i = 0; i < kUnitPx; ++i) {
+                            const float s = v[0][i][0];
+                            v[0][i][0] = v[0][i][2];
+                            v[0][i][2] = s;
+                        }
+                    }
+                }
+                Compute::template apply<1, C>(a, v);
+#pragma unroll
+                for (int i = 0; i < kUnitPx; ++i)
+                    if (i < nv) {
+#pragma unroll
+                        for (int c = 0; c < C; ++c) {
+                            acc.mn[c] = fminf(acc.mn[c], v[0][i][c]);
+                            acc.mx[c] = fmaxf(acc.mx[c], v[0][i][c]);
+                            acc.sum[c] += (double)v[0][i][c];
+                        }
+                    }
+            }
+        }
+        block_reduce<C>(acc, red, tid, T);
+        if (tid == 0) {
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                a.st_part[(size_t)slot * C + c] = StatPartial{acc.mn[c], acc.mx[c], acc.sum[c]};
+            __threadfence();  // release the partial before the ticket
+            ticket = atomicAdd(&a.st_done[b], 1u);
+        }
+        __syncthreads();
+        if (ticket == nslots - 1) {  // block-uniform: this block finishes the item
+            __threadfence();          // acquire every other block's partial
+            StatAcc<C> fin;
+            fin.init();
+            for (uint32_t s = (uint32_t)tid; s < nslots; s += (uint32_t)T) {
+                const StatPartial *q = a.st_part + (size_t)(first + s) * C;
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    // atomic loads: vector memory at device scope, never the scalar cache
+                    const float mn = __hip_atomic_load(&q[c].mn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const float mx = __hip_atomic_load(&q[c].mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const double sm = __hip_atomic_load(&q[c].sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    fin.mn[c] = fminf(fin.mn[c], mn);
+                    fin.mx[c] = fmaxf(fin.mx[c], mx);
+                    fin.sum[c] += sm;
+                }
+            }
+            block_reduce<C>(fin, red, tid, T);
+            if (tid == 0) {
+                double *out = (double *)(uintptr_t)it.dst;
+                const double n = (double)it.ow * (double)it.oh;
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    out[4 * c + 0] = (double)fin.mn[c];
+                    out[4 * c + 1] = (double)fin.mx[c];
+                    out[4 * c + 2] = fin.sum[c];
+                    out[4 * c + 3] = fin.sum[c] / n;
+                }
+                __hip_atomic_store(&a.st_done[b], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        __syncthreads();  // `ticket` and `red` are reused by the next slot
+    }
+}
+
 }  // namespace fk

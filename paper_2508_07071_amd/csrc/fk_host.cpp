@@ -60,7 +60,7 @@ extern "C" const char *fk_version(void) { return "fk-mi355x 0.1 (gfx950)"; }
 
 // ------------------------------------------------------------ validation --
 
-int fk::dtype_size(int32_t dt) { return dt == FK_U8 ? 1 : dt == FK_F16 ? 2 : 4; }
+int fk::dtype_size(int32_t dt) { return dt == FK_U8 ? 1 : dt == FK_F16 ? 2 : dt == FK_F64 ? 8 : 4; }
 
 fk_status fk::validate_chain(const fk_chain_desc *ch)
 {
@@ -73,10 +73,15 @@ fk_status fk::validate_chain(const fk_chain_desc *ch)
         return set_error(FK_ERR_INVALID_ARG, "unknown input dtype %d", r.in_dtype);
     if (r.channels != 1 && r.channels != 3 && r.channels != 4)
         return set_error(FK_ERR_UNSUPPORTED, "channels must be 1, 3 or 4 (got %d)", r.channels);
-    if (ch->write.out_dtype != FK_F32 && ch->write.out_dtype != FK_F16)
-        return set_error(FK_ERR_UNSUPPORTED, "output dtype must be FK_F32 or FK_F16");
-    if (ch->write.layout != FK_PACKED && ch->write.layout != FK_PLANAR)
-        return set_error(FK_ERR_INVALID_ARG, "unknown layout %d", ch->write.layout);
+    if (ch->write.layout == FK_STATS) {
+        if (ch->write.out_dtype != FK_F64)
+            return set_error(FK_ERR_UNSUPPORTED, "the stats write produces FK_F64 only");
+    } else {
+        if (ch->write.out_dtype != FK_F32 && ch->write.out_dtype != FK_F16)
+            return set_error(FK_ERR_UNSUPPORTED, "output dtype must be FK_F32 or FK_F16");
+        if (ch->write.layout != FK_PACKED && ch->write.layout != FK_PLANAR)
+            return set_error(FK_ERR_INVALID_ARG, "unknown layout %d", ch->write.layout);
+    }
     if (ch->n_ops < 0 || ch->n_ops > FK_MAX_OPS)
         return set_error(FK_ERR_INVALID_ARG, "n_ops %d outside 0..%d", ch->n_ops, FK_MAX_OPS);
     if (ch->n_ops > 0 && !ch->ops)
@@ -199,6 +204,9 @@ bool fk::config_valid(const fk_launch_config &c)
 
 const void *fk::plan_kernel(const fk_plan *p, const fk_launch_config &cfg)
 {
+    if (p->chain.write.layout == FK_STATS)
+        return kernel_stats(p->chain.read.kind, p->chain.read.in_dtype, p->chain.read.channels,
+                            cfg.coarsen);
     switch (p->family) {
     case FAM_NORMALIZE: return kernel_normalize(cfg.coarsen, p->opts.strict_fp);
     case FAM_MULADD: return kernel_muladd(p->static_n, cfg.coarsen, p->opts.strict_fp);
@@ -243,6 +251,10 @@ static void plan_free(fk_plan *p)
         (void)hipFree(p->d_ops);
     if (p->d_consts)
         (void)hipFree(p->d_consts);
+    if (p->d_st_part)
+        (void)hipFree(p->d_st_part);
+    if (p->d_st_done)
+        (void)hipFree(p->d_st_done);
     if (p->capture_stream)
         (void)hipStreamDestroy(p->capture_stream);
     if (p->tune_stream)
@@ -262,6 +274,9 @@ extern "C" fk_status fk_plan_create(const fk_chain_desc *chain, int32_t max_batc
             return s;
         if (max_batch < 1 || max_batch > (1 << 20))
             return set_error(FK_ERR_INVALID_ARG, "max_batch %d outside 1..2^20", max_batch);
+        const bool stats = chain->write.layout == FK_STATS;
+        if (stats && max_batch > kStatCapacity)
+            return set_error(FK_ERR_UNSUPPORTED, "stats write: max_batch above %d", kStatCapacity);
         fk_plan_opts o = {FK_CONFIG_DEFAULT, kDefaultConfig, 0, 0, FK_TIER_AUTO};
         if (opts)
             o = *opts;
@@ -293,7 +308,8 @@ extern "C" fk_status fk_plan_create(const fk_chain_desc *chain, int32_t max_batc
 
         std::vector<float> consts;
         int sn = 0;
-        p->family = o.tier == FK_TIER_AUTO ? match_static(&p->chain, consts, sn) : FAM_RUNTIME;
+        p->family = o.tier == FK_TIER_AUTO && !stats ? match_static(&p->chain, consts, sn)
+                                                     : FAM_RUNTIME;
         p->static_n = sn;
         normalise_chain(&p->chain, o.strict_fp != 0, p->ops, p->swap);
         p->cfg = o.config_source == FK_CONFIG_MANUAL ? o.manual : default_config(p);
@@ -308,6 +324,17 @@ extern "C" fk_status fk_plan_create(const fk_chain_desc *chain, int32_t max_batc
             if (e == hipSuccess && !p->ops.empty())
                 e = hipMemcpy(p->d_ops, p->ops.data(), p->ops.size() * sizeof(OpRec),
                               hipMemcpyHostToDevice);
+        }
+        if (e == hipSuccess && stats) {
+            // partials for every slot of a full batch, and counters that the
+            // kernel returns to zero after each item
+            p->st_capacity = (uint32_t)std::min<int64_t>((int64_t)max_batch * kStatSlots, kStatCapacity);
+            e = hipMalloc(&p->d_st_part, (size_t)p->st_capacity * chain->read.channels *
+                                             sizeof(StatPartial));
+            if (e == hipSuccess)
+                e = hipMalloc(&p->d_st_done, sizeof(uint32_t) * (size_t)max_batch);
+            if (e == hipSuccess)
+                e = hipMemset(p->d_st_done, 0, sizeof(uint32_t) * (size_t)max_batch);
         }
         p->table_bytes = sizeof(RunHeader) + sizeof(ItemRec) * (size_t)max_batch +
                          sizeof(uint32_t) * ((size_t)max_batch + 1);
@@ -380,11 +407,17 @@ extern "C" fk_status fk_plan_get_tier(const fk_plan *plan, int32_t *is_static)
 // Fill the item records and tile prefix sums of a run; returns the number
 // of tiles.
 uint32_t fk::build_items(const fk_plan *p, const fk_item *items, int32_t n,
-                         const fk_launch_config &cfg, ItemRec *recs, uint32_t *tb)
+                         const fk_launch_config &cfg, ItemRec *recs, uint32_t *tb,
+                         int32_t batch_n)
 {
     const int C = p->chain.read.channels;
     const int es_in = dtype_size(p->chain.read.in_dtype);
     const uint64_t tile_units = (uint64_t)cfg.block_threads * cfg.coarsen;
+    // stats write: an item's "tiles" are its blocks, at most slot_cap each
+    const bool stats = p->chain.write.layout == FK_STATS;
+    const uint64_t slot_cap =
+        stats ? std::min<uint64_t>(kStatSlots, p->st_capacity / (uint64_t)(batch_n > 0 ? batch_n : n))
+              : ~0ull;
     uint64_t tiles = 0;
     for (int32_t b = 0; b < n; ++b) {
         const fk_item &it = items[b];
@@ -420,7 +453,7 @@ uint32_t fk::build_items(const fk_plan *p, const fk_item *items, int32_t n,
         r.flags = flags;
         tb[b] = (uint32_t)tiles;
         const uint64_t units = (uint64_t)upr * (uint64_t)r.oh;
-        tiles += (units + tile_units - 1) / tile_units;
+        tiles += std::min<uint64_t>((units + tile_units - 1) / tile_units, slot_cap);
     }
     tb[n] = (uint32_t)tiles;
     return (uint32_t)tiles;
@@ -453,6 +486,8 @@ KArgs fk::make_args(const fk_plan *p, void *d_table)
     a.swap = p->family == FAM_RUNTIME ? p->swap : 0;
     a.strict = p->opts.strict_fp;
     a.loop_count = p->family == FAM_MULADD_LOOP ? p->static_n : 0;
+    a.st_part = p->d_st_part;
+    a.st_done = p->d_st_done;
     return a;
 }
 
@@ -533,7 +568,7 @@ fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_la
         a.inl_compact = 1;
         uint32_t tb[2];
         ItemRec &t = *(ItemRec *)a.inl;
-        a.inl_tiles_per_item = build_items(p, items, 1, cfg, &t, tb);
+        a.inl_tiles_per_item = build_items(p, items, 1, cfg, &t, tb, n);
         a.inl_total_tiles = a.inl_tiles_per_item * (uint32_t)n;
         a.inl_dst_stride = (int64_t)((uintptr_t)items[1].dst - (uintptr_t)items[0].dst);
         // template flags: frame base and pitch dword-aligned; outputs aligned

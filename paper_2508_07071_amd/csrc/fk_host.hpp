@@ -31,6 +31,9 @@ struct fk_plan {
     int32_t swap = 0;                      // net channel swap (run-time tier)
     void *d_ops = nullptr;
     void *d_consts = nullptr;
+    fk::StatPartial *d_st_part = nullptr;  // stats write: block partials
+    uint32_t *d_st_done = nullptr;         // stats write: per-slot counters (zero at rest)
+    uint32_t st_capacity = 0;              // stats write: partial slots held
     size_t table_bytes = 0;
     Slot slots[kRing];
     int next_slot = 0;
@@ -51,7 +54,7 @@ bool config_valid(const fk_launch_config &c);
 const void *plan_kernel(const fk_plan *p, const fk_launch_config &cfg);
 size_t lds_bytes(const fk_plan *p, const fk_launch_config &cfg);
 uint32_t build_items(const fk_plan *p, const fk_item *items, int32_t n, const fk_launch_config &cfg,
-                     ItemRec *recs, uint32_t *tb);
+                     ItemRec *recs, uint32_t *tb, int32_t batch_n = 0);
 uint32_t build_table(const fk_plan *p, const fk_item *items, int32_t n, const fk_launch_config &cfg,
                      void *stage);
 KArgs make_args(const fk_plan *p, void *d_table);

@@ -10,7 +10,7 @@ namespace fk {
 
 enum : int32_t { RD_PLAIN = 0, RD_CROP_RESIZE = 1 };
 enum : int32_t { DT_U8 = 0, DT_F16 = 1, DT_F32 = 2 };
-enum : int32_t { LY_PACKED = 0, LY_PLANAR = 1 };
+enum : int32_t { LY_PACKED = 0, LY_PLANAR = 1, LY_STATS = 2 };
 
 // Normalised compute op codes.  SUB becomes ADD of the negated constant
 // (IEEE x - y is x + (-y)), CVT disappears (fp32 from the read on), swaps
@@ -76,6 +76,20 @@ struct Roi16 {
     uint16_t x, y, w, h;
 };
 
+// Stats write: a block's partial result for one channel.
+struct StatPartial {    // 16 bytes
+    float mn, mx;
+    double sum;
+};
+
+// Stats write: a batch slot's output is covered by at most kStatSlots
+// blocks (each striding over the item's tiles); each leaves one partial per
+// channel, and the last block to finish combines them.
+constexpr int kStatSlots = 512;
+// Partials a stats plan holds (slots over a whole batch); a batch of n
+// items gives each at most kStatCapacity / n slots.
+constexpr int kStatCapacity = 65536;
+
 // Kernel arguments (by value, the only kernel argument, so it starts the
 // kernarg segment).  Device table layout of one run:
 //   RunHeader | ItemRec[max_batch] | uint32 tile_begin[max_batch + 1]
@@ -94,6 +108,8 @@ struct KArgs {
     uint32_t inl_total_tiles;
     uint32_t inl_tiles_per_item;  // compact form
     int64_t inl_dst_stride;       // compact form: bytes between item outputs
+    StatPartial *st_part;  // stats write: one partial per (slot, channel)
+    uint32_t *st_done;     // stats write: finished slots per batch slot
     alignas(16) uint8_t inl[kInlineBytes];
 };
 
@@ -113,5 +129,6 @@ const void *kernel_runtime(int read_kind, int in_dt, int channels, int out_dt, i
 const void *kernel_normalize(int coarsen, int strict);
 const void *kernel_muladd(int n_ops, int coarsen, int strict);
 const void *kernel_muladd_loop(int channels, int coarsen, int strict);
+const void *kernel_stats(int read_kind, int in_dt, int channels, int coarsen);
 
 }  // namespace fk

@@ -360,8 +360,8 @@ extern "C" fk_status fk_server_create(const fk_server_opts *opts, fk_server **ou
         fk_status st = validate_chain(opts->chain);
         if (st)
             return st;
-        if (opts->chain->read.kind != FK_READ_CROP_RESIZE)
-            return set_error(FK_ERR_UNSUPPORTED, "the server runs crop+resize chains");
+        if (opts->chain->read.kind != FK_READ_CROP_RESIZE || opts->chain->write.layout == FK_STATS)
+            return set_error(FK_ERR_UNSUPPORTED, "the server runs crop+resize chains with an image write");
         if (!opts->arena || opts->arena_bytes < 4096)
             return set_error(FK_ERR_INVALID_ARG, "arena missing or too small");
         if (opts->budget_bytes < 0 || opts->budget_bytes > opts->arena_bytes)

@@ -12,6 +12,18 @@ const void *kernel_runtime_resize_u8(int, int, int, int);
 const void *kernel_runtime_resize_f16(int, int, int, int);
 const void *kernel_runtime_resize_f32(int, int, int, int);
 
+const void *kernel_stats_plain(int, int, int);
+const void *kernel_stats_resize(int, int, int);
+
+const void *kernel_stats(int read_kind, int in_dt, int channels, int coarsen)
+{
+    if (read_kind == RD_PLAIN)
+        return kernel_stats_plain(in_dt, channels, coarsen);
+    if (read_kind == RD_CROP_RESIZE)
+        return kernel_stats_resize(in_dt, channels, coarsen);
+    return nullptr;
+}
+
 const void *kernel_runtime(int read_kind, int in_dt, int channels, int out_dt, int layout,
                            int coarsen)
 {

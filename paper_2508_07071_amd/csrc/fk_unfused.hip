@@ -7,7 +7,10 @@
 // Per item: [crop: 2-D copy of the ROI] -> [resize: bilinear to fp32] ->
 // one elementwise kernel per compute op (swap, cvt, mul, add, sub, div) ->
 // [write: packed or planar, fp32/fp16].  The last compute op writes the
-// output directly when the write is packed fp32 (no extra copy).
+// output directly when the write is packed fp32 (no extra copy).  A stats
+// write instead runs one reduction per statistic over the fp32 image (min,
+// max, sum, and mean as its own pass), as separate library calls would:
+// each pass reads the whole image again.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -156,6 +159,107 @@ __global__ __launch_bounds__(kUnfusedBlock) void k_write(const uint8_t *src, uin
     }
 }
 
+// One statistic over a packed fp32 image, stage 1: block g reduces the
+// pixels g*T + t, g*T + t + G*T, ... (fixed order) into part[g][c].
+enum : int { RED_MIN = 0, RED_MAX = 1, RED_SUM = 2, RED_MEAN = 3 };
+constexpr int kRedBlocks = 256;
+
+template <int OP>
+__device__ __forceinline__ double red_op(double a, double b)
+{
+    if constexpr (OP == RED_MIN)
+        return fmin(a, b);
+    else if constexpr (OP == RED_MAX)
+        return fmax(a, b);
+    else
+        return a + b;
+}
+
+template <int OP>
+__device__ __forceinline__ double red_init()
+{
+    if constexpr (OP == RED_MIN)
+        return __builtin_inf();
+    else if constexpr (OP == RED_MAX)
+        return -__builtin_inf();
+    else
+        return 0.0;
+}
+
+// Block-wide reduction of one value per channel in a fixed tree; thread 0
+// gets the result.
+template <int OP>
+__device__ __forceinline__ void red_block(double (&acc)[4], int C, double (*lds)[4])
+{
+    const int tid = threadIdx.x;
+    for (int c = 0; c < C; ++c)
+        lds[tid][c] = acc[c];
+    __syncthreads();
+    for (int s = kUnfusedBlock / 2; s >= 1; s >>= 1) {
+        if (tid < s)
+            for (int c = 0; c < C; ++c)
+                lds[tid][c] = red_op<OP>(lds[tid][c], lds[tid + s][c]);
+        __syncthreads();
+    }
+    for (int c = 0; c < C; ++c)
+        acc[c] = lds[0][c];
+}
+
+template <int OP>
+__global__ __launch_bounds__(kUnfusedBlock) void k_red_partial(const float *src, int64_t npix,
+                                                              int C, double *part)
+{
+    __shared__ double lds[kUnfusedBlock][4];
+    double acc[4];
+    for (int c = 0; c < 4; ++c)
+        acc[c] = red_init<OP>();
+    const FK_GLOBAL float *s = (const FK_GLOBAL float *)src;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npix;
+         p += (int64_t)gridDim.x * blockDim.x)
+        for (int c = 0; c < C; ++c) {
+            const float v = s[p * C + c];
+            if constexpr (OP == RED_MIN)
+                acc[c] = (double)fminf((float)acc[c], v);
+            else if constexpr (OP == RED_MAX)
+                acc[c] = (double)fmaxf((float)acc[c], v);
+            else
+                acc[c] += (double)v;
+        }
+    red_block<OP>(acc, C, lds);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < C; ++c)
+            part[(int64_t)blockIdx.x * 4 + c] = acc[c];
+}
+
+// Stage 2: one block combines the G partials; dst[4c + OP] = the statistic.
+template <int OP>
+__global__ __launch_bounds__(kUnfusedBlock) void k_red_final(const double *part, int G, int C,
+                                                            double *dst, double npix)
+{
+    __shared__ double lds[kUnfusedBlock][4];
+    double acc[4];
+    for (int c = 0; c < 4; ++c)
+        acc[c] = red_init<OP>();
+    for (int g = threadIdx.x; g < G; g += blockDim.x)
+        for (int c = 0; c < C; ++c)
+            acc[c] = red_op<OP>(acc[c], part[(int64_t)g * 4 + c]);
+    red_block<OP>(acc, C, lds);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < C; ++c)
+            dst[4 * c + OP] = OP == RED_MEAN ? acc[c] / npix : acc[c];
+}
+
+template <int OP>
+static void stat_pass(const float *img, int64_t npix, int C, double *part, double *dst,
+                      hipStream_t st)
+{
+    constexpr int K = OP == RED_MEAN ? RED_SUM : OP;
+    const int G = (int)std::max<int64_t>(
+        1, std::min<int64_t>(kRedBlocks, (npix + kUnfusedBlock - 1) / kUnfusedBlock));
+    k_red_partial<K><<<G, kUnfusedBlock, 0, st>>>(img, npix, C, part);
+    k_red_final<OP><<<1, kUnfusedBlock, 0, st>>>(part, G, C, dst, (double)npix);
+}
+
 static unsigned grid_for(int64_t n)
 {
     const int64_t g = (n + kUnfusedBlock - 1) / kUnfusedBlock;
@@ -165,8 +269,8 @@ static unsigned grid_for(int64_t n)
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct ScratchPlan {
-    size_t crop = 0, buf = 0;
-    size_t total() const { return align_up(crop) + 2 * align_up(buf); }
+    size_t crop = 0, buf = 0, part = 0;
+    size_t total() const { return align_up(crop) + 2 * align_up(buf) + align_up(part); }
 };
 
 static ScratchPlan scratch_for(const fk_plan *p, const fk_item &it)
@@ -179,6 +283,8 @@ static ScratchPlan scratch_for(const fk_plan *p, const fk_item &it)
     if (p->chain.read.kind == FK_READ_CROP_RESIZE)
         npix = std::max(npix, (size_t)it.out_w * it.out_h);
     s.buf = npix * C * sizeof(float);
+    if (p->chain.write.layout == FK_STATS)
+        s.part = (size_t)kRedBlocks * 4 * sizeof(double);
     return s;
 }
 
@@ -318,7 +424,20 @@ static fk_status run_item_unfused(const fk_plan *p, const fk_item &it, uint8_t *
         cur = o;
         cur_dt = DT_F32;
     }
-    if (!(direct && !seq.empty())) {
+    if (p->chain.write.layout == FK_STATS) {
+        if (cur_dt != DT_F32) {  // no arithmetic op ran: make the fp32 image
+            float *o = buf[nb];
+            write_out<DT_F32>(cur_dt, cur, o, npix, C, 0, st);
+            cur = o;
+        }
+        const float *img = (const float *)cur;
+        double *part = (double *)(scratch + align_up(sp.crop) + 2 * align_up(sp.buf));
+        double *out = (double *)it.dst;
+        stat_pass<RED_MIN>(img, npix, C, part, out, st);
+        stat_pass<RED_MAX>(img, npix, C, part, out, st);
+        stat_pass<RED_SUM>(img, npix, C, part, out, st);
+        stat_pass<RED_MEAN>(img, npix, C, part, out, st);
+    } else if (!(direct && !seq.empty())) {
         const int planar = p->chain.write.layout == FK_PLANAR;
         if (p->chain.write.out_dtype == FK_F16)
             write_out<DT_F16>(cur_dt, cur, it.dst, npix, C, planar, st);

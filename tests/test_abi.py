@@ -156,3 +156,13 @@ def test_loop_validation_agrees_with_oracle(ops, ok):
     fr = np.zeros((4, 4, 3), np.uint8)
     orc_ok = oracle.validate(ch, [fr], [{"frame": 0, "x": 0, "y": 0, "w": 4, "h": 4}]) == 0
     assert lib_ok == orc_ok == ok
+
+
+@pytest.mark.parametrize("dtype,layout,ok", [
+    ("f64", "stats", fk.FK_OK), ("f32", "stats", fk.FK_ERR_UNSUPPORTED),
+    ("f64", "planar", fk.FK_ERR_UNSUPPORTED), ("f64", "packed", fk.FK_ERR_UNSUPPORTED),
+])
+def test_stats_write_validation(dtype, layout, ok):
+    c = norm_chain()
+    c["write"] = {"dtype": dtype, "layout": layout}
+    assert fk.fk_chain_validate(fk.chain_desc(c)) == ok
