@@ -20,7 +20,8 @@ Printed JSON line:
 
 Other workloads (--workload), for the design notes, not the headline line:
 "hf" (batched uneven crops), "loop" (long Mul+Add chains through the loop
-op on a batch of small images), "stats" (the reduction write), "serve" (the serving loop), "costmodel"
+op on a batch of small images), "stats" (the reduction write), "sweeps"
+(the paper's data-size, plain-read batch and data-type sweeps), "serve" (the serving loop), "costmodel"
 (training and evaluating the launch-configuration model) and "copy" (a
 plain device copy, the bandwidth reference).
 """
@@ -537,6 +538,108 @@ def stats_workload(args):
     return out
 
 
+DATA_SIZES = [100, 1000, 10000, 100000, 282370, 1000000, 4000000, 9032740, 16654030]
+HF_PLAIN_BATCHES = [1, 10, 50, 100, 300, 600, 1191]
+DTYPE_PAIRS = [("u8", "f32"), ("u8", "f16"), ("f16", "f32"), ("f16", "f16"), ("f32", "f32"), ("f32", "f16")]
+
+
+def sweeps_workload(args):
+    """The paper's parameter sweeps on this library (Sections VI-C, VI-G,
+    VI-I), fused vs the unfused one-kernel-per-op baseline:
+      data_size: 1-D fp32 arrays of N values (rows of 4096 above 4096), 100
+                 Mul+Add pairs through the loop op, no batch;
+      hf_plain:  B single-channel 60x120 u8 images, Read -> Cast -> Mul ->
+                 Sub -> Div -> Write, one batched launch vs one launch per
+                 image vs unfused;
+      dtypes:    the same chain at B = 50 for six input -> output types."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2508_07071_amd as fk
+
+    dev = torch.device("cuda:0")
+    stream = fk.stream_handle()
+
+    def timeit(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def setup(cfg):
+        ch = cfg["chain"]
+        frame = torch.from_numpy(cfg["frames"][0]).to(dev)
+        outs = [torch.empty(fk.out_shape(ch, it), dtype=fk.TORCH_DTYPE[ch["write"]["dtype"]], device=dev)
+                for it in cfg["items"]]
+        arr = fk.make_items(ch, [frame], cfg["items"], outs)
+        plan = fk.fk_plan_create(fk.chain_desc(ch), len(cfg["items"]), fk.plan_opts())
+        return ch, frame, outs, arr, plan
+
+    def unfused_ms(plan, arr, n, reps):
+        nbytes = fk.fk_unfused_scratch_bytes(plan, arr, n)
+        scratch = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+        return timeit(lambda: fk.fk_run_unfused(plan, arr, n, scratch.data_ptr(), nbytes, stream), reps)
+
+    data_size = []
+    for n in DATA_SIZES:
+        cfg = datagen.data_size_case(n, seed=args.seed)
+        ch, frame, outs, arr, plan = setup(cfg)
+        r = {"n": int(cfg["frames"][0].size), "compile_time_chain": bool(fk.fk_plan_get_tier(plan))}
+        r["fused_ms"] = round(timeit(lambda: fk.fk_run(plan, arr, 1, stream), 50), 5)
+        if not args.no_unfused:
+            r["unfused_ms"] = round(unfused_ms(plan, arr, 1, 3), 4)
+            r["speedup"] = round(r["unfused_ms"] / r["fused_ms"], 1)
+        fk.fk_plan_destroy(plan)
+        log("data_size", r)
+        data_size.append(r)
+
+    hf_plain = []
+    for B in HF_PLAIN_BATCHES:
+        cfg = datagen.cast_chain_batch(B, seed=args.seed)
+        ch, frame, outs, arr, plan = setup(cfg)
+        r = {"batch": B, "fused_ms": round(timeit(lambda: fk.fk_run(plan, arr, B, stream), 50), 5)}
+        singles = [fk.make_items(ch, [frame], [it], [outs[b]]) for b, it in enumerate(cfg["items"])]
+        r["per_image_ms"] = round(timeit(lambda: [fk.fk_run(plan, s1, 1, stream) for s1 in singles], 5), 4)
+        r["speedup_vs_per_image"] = round(r["per_image_ms"] / r["fused_ms"], 1)
+        if not args.no_unfused:
+            r["unfused_ms"] = round(unfused_ms(plan, arr, B, 3), 4)
+            r["speedup_vs_unfused"] = round(r["unfused_ms"] / r["fused_ms"], 1)
+        fk.fk_plan_destroy(plan)
+        log("hf_plain", r)
+        hf_plain.append(r)
+
+    dtypes = []
+    for din, dout in DTYPE_PAIRS:
+        cfg = datagen.cast_chain_batch(50, din, dout, seed=args.seed)
+        ch, frame, outs, arr, plan = setup(cfg)
+        r = {"in": din, "out": dout, "fused_ms": round(timeit(lambda: fk.fk_run(plan, arr, 50, stream), 50), 5)}
+        if not args.no_unfused:
+            r["unfused_ms"] = round(unfused_ms(plan, arr, 50, 3), 4)
+            r["speedup"] = round(r["unfused_ms"] / r["fused_ms"], 1)
+        fk.fk_plan_destroy(plan)
+        log("dtypes", r)
+        dtypes.append(r)
+    top = data_size[-1]
+    n = top["n"]
+    flops = 2.0 * 100 * n
+    tf = flops / (top["fused_ms"] * 1e-3) / 1e12
+    return {"metric": "paper sweeps: fused vs unfused times", "value": round(tf, 3), "unit": "TFLOP/s",
+            "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "sweeps: data size (VI-G), plain-read HF (VI-C), data types (VI-I)",
+                       "seed": args.seed},
+            "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tf / ALU_PEAK_TFLOPS, 4), "traffic": None,
+                         "kernel": f"fused 100 mul+add pairs over {n} fp32 values", "kernel_ms": top["fused_ms"]},
+            "data_size": data_size, "hf_plain": hf_plain, "dtypes": dtypes}
+
+
 def serve_workload(args):
     """Serving loop (config 4 sizes): open-loop Poisson arrivals, continuous
     batching vs per-request fused vs per-request unfused; p50/p99 latency."""
@@ -643,7 +746,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="vf", choices=["vf", "hf", "loop", "stats", "copy", "serve", "costmodel"])
+    ap.add_argument("--workload", default="vf", choices=["vf", "hf", "loop", "stats", "sweeps", "copy", "serve", "costmodel"])
     ap.add_argument("--data", nargs="+", default=[], help="cost-model label shards")
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--rates", type=float, nargs="+", default=[200, 500, 1000, 2000])
@@ -678,6 +781,9 @@ def main():
         return
     if args.workload == "stats":
         print(json.dumps(stats_workload(args)))
+        return
+    if args.workload == "sweeps":
+        print(json.dumps(sweeps_workload(args)))
         return
     if args.workload == "serve":
         print(json.dumps(serve_workload(args)))

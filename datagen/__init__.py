@@ -142,6 +142,42 @@ def loop_batch(pairs: int, seed: int = 0, batch: int = 50, hw=(120, 60), channel
     return {"frames": [fr], "items": items, "chain": loop_chain(pairs, g, channels), "seed": seed}
 
 
+def data_size_case(n_elems: int, pairs: int = 100, seed: int = 0, row: int = 4096) -> dict:
+    """Section VI-G: a 1-D fp32 array of about n_elems values (uniform in
+    [0, 255)), no batch, then `pairs` Mul+Add pairs through a loop op.  The
+    array is held as one row when n_elems <= row, else as n_elems // row rows
+    of `row` values (n rounded down to whole rows)."""
+    g = rng(seed)
+    w = min(n_elems, row)
+    h = max(1, n_elems // row) if n_elems > row else 1
+    fr = frame(g, h, w, 1, dtype="f32")
+    m = f32(g.uniform(0.5, 0.95))
+    a = f32(g.uniform(-1.0, 1.0))
+    chain = {"read": {"kind": "plain", "dtype": "f32", "channels": 1, "out_w": 0, "out_h": 0},
+             "ops": [{"kind": "mul", "k": [m]}, {"kind": "add", "k": [a]},
+                     {"kind": "loop", "span": 2, "count": int(pairs)}],
+             "write": {"dtype": "f32", "layout": "packed"}}
+    return {"frames": [fr], "items": [whole_frame_item(fr)], "chain": chain, "seed": seed}
+
+
+def cast_chain_batch(batch: int = 50, in_dtype: str = "u8", out_dtype: str = "f32", seed: int = 0,
+                     hw=(120, 60)) -> dict:
+    """Sections VI-C and VI-I: `batch` single-channel images of hw (height,
+    width) stacked in one frame (image b in rows [b*h, (b+1)*h)), chain
+    Read -> Cast -> Multiply -> Subtract -> Divide -> Write.  Constants:
+    mul uniform in [0.5, 1.5), sub in [-1, 1), div in [0.5, 1.5), drawn after
+    the frame values."""
+    g = rng(seed)
+    h, w = hw
+    fr = frame(g, batch * h, w, 1, dtype=in_dtype)
+    ops = [{"kind": "cvt", "k": []}, {"kind": "mul", "k": [f32(g.uniform(0.5, 1.5))]},
+           {"kind": "sub", "k": [f32(g.uniform(-1.0, 1.0))]}, {"kind": "div", "k": [f32(g.uniform(0.5, 1.5))]}]
+    chain = {"read": {"kind": "plain", "dtype": in_dtype, "channels": 1, "out_w": 0, "out_h": 0},
+             "ops": ops, "write": {"dtype": out_dtype, "layout": "packed"}}
+    items = [{"frame": 0, "x": 0, "y": b * h, "w": w, "h": h, "out_w": w, "out_h": h} for b in range(batch)]
+    return {"frames": [fr], "items": items, "chain": chain, "seed": seed}
+
+
 def whole_frame_item(fr: np.ndarray, frame_index: int = 0) -> dict:
     h, w = fr.shape[:2]
     return {"frame": frame_index, "x": 0, "y": 0, "w": w, "h": h, "out_w": w, "out_h": h}

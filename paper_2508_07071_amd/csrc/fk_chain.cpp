@@ -143,17 +143,22 @@ int fk::match_static(const fk_chain_desc *ch, std::vector<float> &consts, int &n
             return FAM_MULADD;
         }
     }
-    // plain u8 (1 or 3 channels) -> cvt, mul, add (scalar), loop over both -> packed f32
-    if (ch->read.kind == FK_READ_PLAIN && ch->read.in_dtype == FK_U8 &&
+    // plain u8 or fp32 (1 or 3 channels) -> [cvt,] mul, add (scalar), loop over
+    // both -> packed f32
+    if (ch->read.kind == FK_READ_PLAIN &&
+        (ch->read.in_dtype == FK_U8 || ch->read.in_dtype == FK_F32) &&
         (ch->read.channels == 1 || ch->read.channels == 3) && ch->write.out_dtype == FK_F32 &&
-        ch->write.layout == FK_PACKED && ch->n_ops == 4 && o[0].kind == FK_OP_CVT_F32 &&
-        o[1].kind == FK_OP_MUL && o[1].n_consts == 1 && o[2].kind == FK_OP_ADD &&
-        o[2].n_consts == 1 && o[3].kind == FK_OP_LOOP && o[3].loop_span == 2) {
-        consts.assign(2, 0.0f);
-        consts[0] = o[1].consts[0];
-        consts[1] = o[2].consts[0];
-        n_ops = o[3].loop_count;
-        return FAM_MULADD_LOOP;
+        ch->write.layout == FK_PACKED && ch->n_ops >= 3) {
+        const fk_op_desc *q = o[0].kind == FK_OP_CVT_F32 ? o + 1 : o;
+        if (ch->n_ops == (int)(q - o) + 3 && q[0].kind == FK_OP_MUL && q[0].n_consts == 1 &&
+            q[1].kind == FK_OP_ADD && q[1].n_consts == 1 && q[2].kind == FK_OP_LOOP &&
+            q[2].loop_span == 2) {
+            consts.assign(2, 0.0f);
+            consts[0] = q[0].consts[0];
+            consts[1] = q[1].consts[0];
+            n_ops = q[2].loop_count;
+            return FAM_MULADD_LOOP;
+        }
     }
     return FAM_RUNTIME;
 }

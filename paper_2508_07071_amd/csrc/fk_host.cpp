@@ -211,7 +211,8 @@ const void *fk::plan_kernel(const fk_plan *p, const fk_launch_config &cfg)
     case FAM_NORMALIZE: return kernel_normalize(cfg.coarsen, p->opts.strict_fp);
     case FAM_MULADD: return kernel_muladd(p->static_n, cfg.coarsen, p->opts.strict_fp);
     case FAM_MULADD_LOOP:
-        return kernel_muladd_loop(p->chain.read.channels, cfg.coarsen, p->opts.strict_fp);
+        return kernel_muladd_loop(p->chain.read.in_dtype, p->chain.read.channels, cfg.coarsen,
+                                  p->opts.strict_fp);
     default:
         return kernel_runtime(p->chain.read.kind, p->chain.read.in_dtype, p->chain.read.channels,
                               p->chain.write.out_dtype, p->chain.write.layout, cfg.coarsen);

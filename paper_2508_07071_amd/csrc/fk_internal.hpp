@@ -118,7 +118,7 @@ enum : int32_t {
     FAM_RUNTIME = 0,       // any chain: run-time op list
     FAM_NORMALIZE = 1,     // crop+resize u8x3 -> swap,cvt,mul,sub,div -> planar f32
     FAM_MULADD = 2,        // plain u8x3 -> cvt, N x (mul, add) -> packed f32
-    FAM_MULADD_LOOP = 3,   // plain u8x1/u8x3 -> cvt, mul, add, loop(2, P) -> packed f32
+    FAM_MULADD_LOOP = 3,   // plain u8/f32 x1/x3 -> [cvt,] mul, add, loop(2, P) -> packed f32
 };
 
 // Kernel lookup (defined by the kernel translation units).  Returns the
@@ -128,7 +128,7 @@ const void *kernel_runtime(int read_kind, int in_dt, int channels, int out_dt, i
                            int coarsen);
 const void *kernel_normalize(int coarsen, int strict);
 const void *kernel_muladd(int n_ops, int coarsen, int strict);
-const void *kernel_muladd_loop(int channels, int coarsen, int strict);
+const void *kernel_muladd_loop(int in_dt, int channels, int coarsen, int strict);
 const void *kernel_stats(int read_kind, int in_dt, int channels, int coarsen);
 
 }  // namespace fk

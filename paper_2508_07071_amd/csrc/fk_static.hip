@@ -94,32 +94,34 @@ const void *kernel_muladd(int n_ops, int coarsen, int strict)
     return nullptr;
 }
 
-// Plain u8 (1 or 3 channels) -> cvt, then (mul, add) looped -> packed fp32.
-template <int C, bool Strict, int K>
+// Plain u8 or fp32 (1 or 3 channels) -> (mul, add) looped -> packed fp32.
+template <int DI, int C, bool Strict, int K>
 static const void *loop_ptr()
 {
-    return (const void *)&k_transform<ReadPlain<DT_U8, C>, LoopMulAddCompute<Strict>,
+    return (const void *)&k_transform<ReadPlain<DI, C>, LoopMulAddCompute<Strict>,
                                       WritePacked<DT_F32, C>, C, K>;
 }
 
-template <int C>
+template <int DI, int C>
 static const void *loop_k(int coarsen, int strict)
 {
     switch (coarsen) {
-    case 1: return strict ? loop_ptr<C, true, 1>() : loop_ptr<C, false, 1>();
-    case 2: return strict ? loop_ptr<C, true, 2>() : loop_ptr<C, false, 2>();
-    case 4: return strict ? loop_ptr<C, true, 4>() : loop_ptr<C, false, 4>();
-    case 8: return strict ? loop_ptr<C, true, 8>() : loop_ptr<C, false, 8>();
+    case 1: return strict ? loop_ptr<DI, C, true, 1>() : loop_ptr<DI, C, false, 1>();
+    case 2: return strict ? loop_ptr<DI, C, true, 2>() : loop_ptr<DI, C, false, 2>();
+    case 4: return strict ? loop_ptr<DI, C, true, 4>() : loop_ptr<DI, C, false, 4>();
+    case 8: return strict ? loop_ptr<DI, C, true, 8>() : loop_ptr<DI, C, false, 8>();
     }
     return nullptr;
 }
 
-const void *kernel_muladd_loop(int channels, int coarsen, int strict)
+const void *kernel_muladd_loop(int in_dt, int channels, int coarsen, int strict)
 {
-    switch (channels) {
-    case 1: return loop_k<1>(coarsen, strict);
-    case 3: return loop_k<3>(coarsen, strict);
-    }
+    if (in_dt == DT_U8)
+        return channels == 1 ? loop_k<DT_U8, 1>(coarsen, strict)
+               : channels == 3 ? loop_k<DT_U8, 3>(coarsen, strict) : nullptr;
+    if (in_dt == DT_F32)
+        return channels == 1 ? loop_k<DT_F32, 1>(coarsen, strict)
+               : channels == 3 ? loop_k<DT_F32, 3>(coarsen, strict) : nullptr;
     return nullptr;
 }
 

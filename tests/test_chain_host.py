@@ -211,9 +211,13 @@ def test_static_chain_match(driver):
     loop3 = datagen.loop_chain(1000, g, channels=3)
     loop4 = datagen.loop_chain(7, g, channels=1)
     loop4["ops"][3]["span"] = 1
+    f32loop = datagen.data_size_case(10, pairs=100)["chain"]
+    f16loop = dict(f32loop, read=dict(f32loop["read"], dtype="f16"))
+    cases += [(f32loop, True), (f16loop, True)]
     cases += [(datagen.loop_chain(10000, g), False), (loop3, True), (loop4, True)]
     res = driver(cases)
     r1, r3, r4 = res[-3:]
+    assert res[-5][2] == FAM_MULADD_LOOP and res[-5][3] == 100 and res[-4][2] == FAM_RUNTIME
     assert r1[2] == FAM_MULADD_LOOP and r1[3] == 10000 and r3[2] == FAM_MULADD_LOOP and r3[3] == 1000
     assert r1[4] == [np.float32(cases[-3][0]["ops"][1]["k"][0]), np.float32(cases[-3][0]["ops"][2]["k"][0])]
     assert r4[2] == FAM_RUNTIME
@@ -222,7 +226,7 @@ def test_static_chain_match(driver):
     assert [op[0] for op in r3[1]] == [OPC_MUL, OPC_ADD, OPC_LOOP] and r3[1][2][3:] == (2, 1000)
     # a loop over the add only: mul must not absorb it
     assert [op[0] for op in r4[1]] == [OPC_MUL, OPC_ADD, OPC_LOOP] and r4[1][2][3:] == (1, 7)
-    res, cases = res[:-3], cases[:-3]
+    res, cases = res[:-5], cases[:-5]
     assert res[0][2] == FAM_NORMALIZE and res[0][3] == 5
     k = res[0][4]
     assert k[0] == np.float32(norm["ops"][2]["k"][0])

@@ -1,0 +1,54 @@
+"""Parity with the oracle at the shapes of the paper's parameter sweeps:
+1-D fp32 arrays with 100 Mul+Add pairs through the loop op (data size),
+batches of 60x120 single-channel images through Read -> Cast -> Mul -> Sub
+-> Div -> Write for six input/output types (data type) and up to 1191
+images (plain-read horizontal fusion)."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+import paper_2508_07071_amd as fk
+from fkhelpers import Plan, assert_bitexact, assert_close, host, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def both_modes(cfg, what, sample=None, static=None):
+    items = cfg["items"]
+    idx = list(range(len(items))) if sample is None else sample
+    refs = oracle.run_chain(cfg["chain"], cfg["frames"], [items[i] for i in idx])
+    dframes = to_dev(cfg["frames"])
+    for strict in (True, False):
+        with Plan(cfg["chain"], len(items), strict=strict) as p:
+            if static is not None:
+                assert fk.fk_plan_get_tier(p.h) == int(static)
+            outs = host(p.run(dframes, items))
+        for i, r in zip(idx, refs):
+            if strict:
+                assert_bitexact(outs[i], r["out"], f"{what} strict item {i}")
+            else:
+                assert_close(outs[i], r, what=f"{what} item {i}")
+
+
+@pytest.mark.parametrize("n", [100, 4096, 282370])
+def test_data_size_fp32_loop_chain(n):
+    say("data size", n)
+    both_modes(datagen.data_size_case(n, seed=n % 97), f"n={n}", static=True)
+
+
+@pytest.mark.parametrize("din,dout", [("u8", "f32"), ("u8", "f16"), ("f16", "f32"), ("f16", "f16"),
+                                      ("f32", "f32"), ("f32", "f16")])
+def test_cast_chain_data_types_batch50(din, dout):
+    say("data types", din, "->", dout)
+    both_modes(datagen.cast_chain_batch(50, din, dout, seed=3), f"{din}->{dout}")
+
+
+def test_plain_batch_1191_images_sampled():
+    say("plain-read batch 1191")
+    cfg = datagen.cast_chain_batch(1191, seed=4)
+    both_modes(cfg, "B=1191", sample=[0, 1, 500, 1189, 1190])
