@@ -11,7 +11,8 @@ workload whatever the consumer.
 
 A chain is a dict::
 
-    {"read":  {"kind": "plain" | "crop_resize", "dtype": "u8"|"f16"|"f32",
+    {"read":  {"kind": "plain" | "crop_resize" | "crop_nearest" | "nv12" | "nv12_resize",
+               "dtype": "u8"|"f16"|"f32",
                "channels": 1|3|4, "out_w": int, "out_h": int},
      "ops":   [{"kind": "swap"|"cvt"|"mul"|"add"|"sub"|"div", "k": [floats]}
                | {"kind": "loop", "span": s, "count": n}],
@@ -176,6 +177,14 @@ def cast_chain_batch(batch: int = 50, in_dtype: str = "u8", out_dtype: str = "f3
              "ops": ops, "write": {"dtype": out_dtype, "layout": "packed"}}
     items = [{"frame": 0, "x": 0, "y": b * h, "w": w, "h": h, "out_w": w, "out_h": h} for b in range(batch)]
     return {"frames": [fr], "items": items, "chain": chain, "seed": seed}
+
+
+def nv12_frame(g: np.random.Generator, h: int, w: int) -> np.ndarray:
+    """An NV12 frame of h x w luma pixels (h, w even) as (3h/2, w) bytes:
+    h luma rows, then h/2 rows of w/2 (U, V) pairs; every byte uniform in
+    0..255."""
+    assert h % 2 == 0 and w % 2 == 0
+    return g.integers(0, 256, size=(h * 3 // 2, w), dtype=np.uint8)
 
 
 def whole_frame_item(fr: np.ndarray, frame_index: int = 0) -> dict:

@@ -24,7 +24,9 @@ SRC = os.path.join(HERE, "fk_oracle.c")
 LIB = os.path.join(HERE, "libfkoracle.so")
 
 _DT = {"u8": 0, "f16": 1, "f32": 2, "f64": 3}
-_READ = {"plain": 0, "crop_resize": 1}
+_READ = {"plain": 0, "crop_resize": 1, "crop_nearest": 2, "nv12": 3, "nv12_resize": 4}
+_RESIZING = ("crop_resize", "crop_nearest", "nv12_resize")
+_NV12 = ("nv12", "nv12_resize")
 _OP = {"swap": 0, "cvt": 1, "mul": 2, "add": 3, "sub": 4, "div": 5, "loop": 6}
 _LAYOUT = {"packed": 0, "planar": 1, "stats": 2}
 _NP_OUT = {"f32": np.float32, "f16": np.float16, "f64": np.float64}
@@ -100,11 +102,19 @@ def _chain_struct(chain: dict):
     return ch, arr
 
 
+def _frame_hw(chain: dict, fr: np.ndarray) -> tuple:
+    """Image height and width of a frame array; an NV12 frame is held as
+    (3H/2, W) bytes (luma rows, then chroma rows)."""
+    if chain["read"]["kind"] in _NV12:
+        return fr.shape[0] * 2 // 3, fr.shape[1]
+    return fr.shape[0], fr.shape[1]
+
+
 def out_shape(chain: dict, item: dict) -> tuple:
     C_ = chain["read"]["channels"]
     if chain["write"]["layout"] == "stats":
         return (C_, 4)  # per channel: min, max, sum, mean
-    if chain["read"]["kind"] == "crop_resize":
+    if chain["read"]["kind"] in _RESIZING:
         oh, ow = item["out_h"], item["out_w"]
     else:
         oh, ow = item["h"], item["w"]
@@ -133,7 +143,7 @@ def run_chain(chain: dict, frames: list, items: list, shadow: bool = True) -> li
             res["smax"] = np.zeros(shape, dtype=np.float32)
         s = structs[b]
         s.src = fr.ctypes.data
-        s.H, s.W = fr.shape[0], fr.shape[1]
+        s.H, s.W = _frame_hw(chain, fr)
         s.pitch = fr.strides[0]
         s.x, s.y, s.w, s.h = it["x"], it["y"], it["w"], it["h"]
         s.ow, s.oh = it.get("out_w", it["w"]), it.get("out_h", it["h"])
@@ -157,7 +167,7 @@ def validate(chain: dict, frames: list, items: list) -> int:
         fr = frames[it["frame"]]
         s = structs[b]
         s.src = fr.ctypes.data
-        s.H, s.W = fr.shape[0], fr.shape[1]
+        s.H, s.W = _frame_hw(chain, fr)
         s.pitch = fr.strides[0]
         s.x, s.y, s.w, s.h = it["x"], it["y"], it["w"], it["h"]
         s.ow, s.oh = it.get("out_w", it["w"]), it.get("out_h", it["h"])

@@ -31,6 +31,19 @@
  *  - Values: u8 and fp16 sources convert to fp32 exactly, and every
  *    arithmetic op runs in fp32, so the running value is held as fp32 from
  *    the read onwards; "cvt" is then numerically the identity.
+ *  - Nearest resize (the other interpolation): output index o takes source
+ *    index floor((2o + 1) * in / (2 * out)) in exact integer arithmetic, the
+ *    source pixel whose extent holds the output pixel's centre (a centre on
+ *    a pixel boundary goes to the higher index).
+ *  - NV12 read: the frame is a W x H luma plane followed, at the same pitch,
+ *    by H/2 rows of W/2 interleaved (U, V) pairs (W and H even).  Pixel
+ *    (x, y) takes Y[y][x] and the chroma pair of (x/2, y/2) (each pair
+ *    serves a 2 x 2 block) and becomes three fp32 values in B, G, R order by
+ *    the ITU-R BT.601 limited-range matrix: with y' = Y - 16, u = U - 128,
+ *    v = V - 128 and c = 1.164 y', B = c + 2.018 u, G = (c - 0.813 v) -
+ *    0.391 u, R = c + 1.596 v, every product and sum one fp32 operation in
+ *    that order.  The ROI is in luma pixels; the NV12 resize read applies
+ *    the bilinear resize above to the converted crop.
  *  - Swap (ColorConvert BGR->RGB): exchanges channels 0 and 2; channel 3 is
  *    kept; a no-op for one channel.  Per-channel constants index channels by
  *    their position after earlier swaps.
@@ -59,7 +72,13 @@
 #include <string.h>
 
 enum { ORC_U8 = 0, ORC_F16 = 1, ORC_F32 = 2, ORC_F64 = 3 };
-enum { ORC_READ_PLAIN = 0, ORC_READ_CROP_RESIZE = 1 };
+enum {
+    ORC_READ_PLAIN = 0,
+    ORC_READ_CROP_RESIZE = 1,
+    ORC_READ_CROP_NEAREST = 2,
+    ORC_READ_NV12 = 3,
+    ORC_READ_NV12_RESIZE = 4,
+};
 enum { ORC_SWAP = 0, ORC_CVT = 1, ORC_MUL = 2, ORC_ADD = 3, ORC_SUB = 4, ORC_DIV = 5, ORC_LOOP = 6 };
 enum { ORC_PACKED = 0, ORC_PLANAR = 1, ORC_STATS = 2 };
 
@@ -234,6 +253,63 @@ static int step_crop(const orc_chain *ch, const orc_item *it, img *out)
     return ORC_OK;
 }
 
+/* NV12 pixel (x, y) of the frame -> B, G, R (BT.601 limited range). */
+static void nv12_bgr(const orc_item *it, int32_t x, int32_t y, float out[3])
+{
+    const uint8_t *base = (const uint8_t *)it->src;
+    float Y = (float)base[(int64_t)y * it->pitch + x];
+    const uint8_t *uv = base + ((int64_t)it->H + y / 2) * it->pitch + (int64_t)(x / 2) * 2;
+    float u = (float)uv[0] - 128.0f;
+    float v = (float)uv[1] - 128.0f;
+    float c = 1.164f * (Y - 16.0f);
+    out[0] = c + 2.018f * u;
+    out[1] = (c - 0.813f * v) - 0.391f * u;
+    out[2] = c + 1.596f * v;
+}
+
+/* NV12 crop: the region of interest, converted, becomes its own image. */
+static int step_crop_nv12(const orc_item *it, img *out)
+{
+    int rc = img_alloc(out, it->w, it->h, 3);
+    if (rc)
+        return rc;
+    for (int32_t j = 0; j < it->h; ++j)
+        for (int32_t i = 0; i < it->w; ++i) {
+            float bgr[3];
+            nv12_bgr(it, it->x + i, it->y + j, bgr);
+            for (int32_t c = 0; c < 3; ++c) {
+                size_t o = ((size_t)j * (size_t)it->w + (size_t)i) * 3u + (size_t)c;
+                out->v[o] = bgr[c];
+                out->d[o] = (double)bgr[c];
+                out->s[o] = fabsf(bgr[c]);
+            }
+        }
+    return ORC_OK;
+}
+
+/* Nearest resize of a whole image to ow x oh. */
+static int step_nearest(const img *in, int32_t ow, int32_t oh, img *out)
+{
+    int32_t C = in->C;
+    int rc = img_alloc(out, ow, oh, C);
+    if (rc)
+        return rc;
+    for (int32_t oy = 0; oy < oh; ++oy) {
+        int64_t sy = ((int64_t)2 * oy + 1) * in->h / ((int64_t)2 * oh);
+        for (int32_t ox = 0; ox < ow; ++ox) {
+            int64_t sx = ((int64_t)2 * ox + 1) * in->w / ((int64_t)2 * ow);
+            for (int32_t c = 0; c < C; ++c) {
+                size_t i = ((size_t)sy * (size_t)in->w + (size_t)sx) * (size_t)C + (size_t)c;
+                size_t o = ((size_t)oy * (size_t)ow + (size_t)ox) * (size_t)C + (size_t)c;
+                out->v[o] = in->v[i];
+                out->d[o] = in->d[i];
+                out->s[o] = in->s[i];
+            }
+        }
+    }
+    return ORC_OK;
+}
+
 /* Source coordinate of output index o for a scale of in/out (half-pixel
  * centres), clamped below at 0; returns the two tap indices and weight. */
 static void bilinear_coord(int32_t o, float scale, int32_t in_size, int32_t *i0, int32_t *i1,
@@ -390,7 +466,10 @@ static int chain_ok(const orc_chain *ch)
 {
     if (!ch || (ch->n_ops > 0 && !ch->ops) || ch->n_ops < 0)
         return 0;
-    if (ch->read_kind != ORC_READ_PLAIN && ch->read_kind != ORC_READ_CROP_RESIZE)
+    if (ch->read_kind < ORC_READ_PLAIN || ch->read_kind > ORC_READ_NV12_RESIZE)
+        return 0;
+    if ((ch->read_kind == ORC_READ_NV12 || ch->read_kind == ORC_READ_NV12_RESIZE) &&
+        (ch->in_dtype != ORC_U8 || ch->channels != 3))
         return 0;
     if (ch->in_dtype < ORC_U8 || ch->in_dtype > ORC_F32)
         return 0;
@@ -427,15 +506,18 @@ static int chain_ok(const orc_chain *ch)
 
 static int item_ok(const orc_chain *ch, const orc_item *it)
 {
+    const int nv12 = ch->read_kind == ORC_READ_NV12 || ch->read_kind == ORC_READ_NV12_RESIZE;
     if (!it->src || !it->dst || it->W < 1 || it->H < 1)
         return 0;
-    if (it->pitch < (int64_t)it->W * ch->channels * (int64_t)dtype_size(ch->in_dtype))
+    if (nv12 ? (it->pitch < it->W || it->W % 2 || it->H % 2)
+             : it->pitch < (int64_t)it->W * ch->channels * (int64_t)dtype_size(ch->in_dtype))
         return 0;
     if (it->w < 1 || it->h < 1 || it->x < 0 || it->y < 0)
         return 0;
     if ((int64_t)it->x + it->w > it->W || (int64_t)it->y + it->h > it->H)
         return 0;
-    if (ch->read_kind == ORC_READ_CROP_RESIZE && (it->ow < 1 || it->oh < 1))
+    if ((ch->read_kind == ORC_READ_CROP_RESIZE || ch->read_kind == ORC_READ_CROP_NEAREST ||
+         ch->read_kind == ORC_READ_NV12_RESIZE) && (it->ow < 1 || it->oh < 1))
         return 0;
     return 1;
 }
@@ -461,9 +543,16 @@ int orc_run(const orc_chain *ch, const orc_item *items, int32_t n)
     for (int32_t b = 0; b < n; ++b) {
         const orc_item *it = &items[b];
         img cur = {0}, nxt = {0};
-        rc = step_crop(ch, it, &cur);
-        if (!rc && ch->read_kind == ORC_READ_CROP_RESIZE) {
+        if (ch->read_kind == ORC_READ_NV12 || ch->read_kind == ORC_READ_NV12_RESIZE)
+            rc = step_crop_nv12(it, &cur);
+        else
+            rc = step_crop(ch, it, &cur);
+        if (!rc && (ch->read_kind == ORC_READ_CROP_RESIZE || ch->read_kind == ORC_READ_NV12_RESIZE)) {
             rc = step_resize(&cur, it->ow, it->oh, &nxt);
+            img_free(&cur);
+            cur = nxt;
+        } else if (!rc && ch->read_kind == ORC_READ_CROP_NEAREST) {
+            rc = step_nearest(&cur, it->ow, it->oh, &nxt);
             img_free(&cur);
             cur = nxt;
         }

@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 import test_oracle_pins as pins
+import test_oracle_read_pins as rpins
 import test_oracle_stats_pins as spins
 
 SRC = open(oracle.SRC).read()
@@ -33,6 +34,11 @@ MUTATIONS = [
     ("mul and add exchanged", "case ORC_MUL: r = v * k;", "case ORC_MUL: r = v + k;"),
     ("loop runs its body once too often", "for (int32_t r = 1; r < op->count; ++r)",
      "for (int32_t r = 0; r < op->count; ++r)"),
+    ("nearest drops the half-pixel centre", "int64_t sx = ((int64_t)2 * ox + 1) * in->w",
+     "int64_t sx = ((int64_t)2 * ox) * in->w"),
+    ("NV12 chroma row from y/4", "((int64_t)it->H + y / 2) * it->pitch", "((int64_t)it->H + y / 4) * it->pitch"),
+    ("NV12 green takes +v", "out[1] = (c - 0.813f * v) - 0.391f * u;", "out[1] = (c + 0.813f * v) - 0.391f * u;"),
+    ("NV12 U and V exchanged", "float u = (float)uv[0] - 128.0f;", "float u = (float)uv[1] - 128.0f;"),
     ("stats min takes the maximum", "mn = fminf(mn, v);", "mn = fmaxf(mn, v);"),
     ("stats read channel 0 only", "float v = m->v[p * (size_t)C + (size_t)c];", "float v = m->v[p * (size_t)C];"),
     ("stats mean over one row", "out[4 * c + 3] = sum / (double)npix;", "out[4 * c + 3] = sum / (double)m->w;"),
@@ -57,6 +63,10 @@ PINS = [
     ("test_loop_equals_unrolled_body", {"span": 3, "count": 4}),
     ("test_loop_chain_matches_affine_closed_form", {"pairs": 7}),
     ("test_stats_of_coordinate_ramps_are_closed_forms", {"roi": (3, 5, 17, 9)}),
+    ("test_nearest_integer_downscale_takes_centre_pixel", {"f": 3}),
+    ("test_nv12_bt601_colour_table", {"yuv": (81, 90, 240), "rgb": (255, 0, 0)}),
+    ("test_nv12_bt601_colour_table", {"yuv": (145, 54, 34), "rgb": (0, 255, 0)}),
+    ("test_nv12_chroma_pair_serves_a_2x2_block", {}),
     ("test_division_is_true_division_not_reciprocal", {}),
     ("test_float_to_half_round_to_nearest_even_matches_numpy", {}),
 ]
@@ -83,7 +93,7 @@ def load_as_oracle(path, monkeypatch):
 def caught_by_pins():
     for name, kw in PINS:
         try:
-            (getattr(pins, name, None) or getattr(spins, name))(**kw)
+            (getattr(pins, name, None) or getattr(spins, name, None) or getattr(rpins, name))(**kw)
         except AssertionError:
             return name
     return None
