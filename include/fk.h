@@ -80,6 +80,23 @@ typedef int32_t fk_status;
  *   written as fma(a, p1 - p0, p0); the resized value stays fp32. */
 #define FK_READ_PLAIN 0
 #define FK_READ_CROP_RESIZE 1
+/* FK_READ_CROP_NEAREST: the ROI is resized to the output size by nearest
+ *   neighbour: output index o takes ROI index floor((2o + 1) * in / (2 out))
+ *   in exact integer arithmetic (the pixel holding the output pixel's
+ *   centre; a centre on a boundary takes the higher index).
+ * FK_READ_NV12 / FK_READ_NV12_RESIZE: the frame is NV12 (in_dtype FK_U8,
+ *   channels 3): a width x height luma plane at src.ptr, then height/2 rows
+ *   of width/2 interleaved (U, V) byte pairs at src.ptr + height *
+ *   pitch_bytes, same pitch; width and height even; 3 * height / 2 rows
+ *   readable.  Pixel (x, y) takes Y[y][x] and the pair of (x/2, y/2) and
+ *   becomes B, G, R in fp32 by the ITU-R BT.601 limited-range matrix: with
+ *   y' = Y - 16, u = U - 128, v = V - 128, c = 1.164 y', B = c + 2.018 u,
+ *   G = (c - 0.813 v) - 0.391 u, R = c + 1.596 v, one fp32 operation each
+ *   in that order.  The ROI is in luma pixels; FK_READ_NV12 reads it 1:1,
+ *   FK_READ_NV12_RESIZE resizes the converted ROI bilinearly as above. */
+#define FK_READ_CROP_NEAREST 2
+#define FK_READ_NV12 3
+#define FK_READ_NV12_RESIZE 4
 
 /* Compute operations (Section IV-A; the hot chain of Sections VI-F/VI-J).
  * SWAP_RB: exchange channels 0 and 2 (BGR<->RGB), channel 3 kept, no-op for

@@ -31,14 +31,17 @@ FK_ERR_BUDGET = -6
 
 FK_U8, FK_F16, FK_F32, FK_F64 = 0, 1, 2, 3
 FK_PACKED, FK_PLANAR, FK_STATS = 0, 1, 2
-FK_READ_PLAIN, FK_READ_CROP_RESIZE = 0, 1
+FK_READ_PLAIN, FK_READ_CROP_RESIZE, FK_READ_CROP_NEAREST, FK_READ_NV12, FK_READ_NV12_RESIZE = range(5)
 FK_OP_SWAP_RB, FK_OP_CVT_F32, FK_OP_MUL, FK_OP_ADD, FK_OP_SUB, FK_OP_DIV, FK_OP_LOOP = range(7)
 FK_CONFIG_DEFAULT, FK_CONFIG_MANUAL, FK_CONFIG_AUTOTUNE, FK_CONFIG_MODEL = range(4)
 FK_TIER_AUTO, FK_TIER_RUNTIME = 0, 1
 
 DTYPE = {"u8": FK_U8, "f16": FK_F16, "f32": FK_F32, "f64": FK_F64}
 LAYOUT = {"packed": FK_PACKED, "planar": FK_PLANAR, "stats": FK_STATS}
-READ = {"plain": FK_READ_PLAIN, "crop_resize": FK_READ_CROP_RESIZE}
+READ = {"plain": FK_READ_PLAIN, "crop_resize": FK_READ_CROP_RESIZE, "crop_nearest": FK_READ_CROP_NEAREST,
+        "nv12": FK_READ_NV12, "nv12_resize": FK_READ_NV12_RESIZE}
+RESIZING = ("crop_resize", "crop_nearest", "nv12_resize")
+NV12 = ("nv12", "nv12_resize")
 OP = {"swap": FK_OP_SWAP_RB, "cvt": FK_OP_CVT_F32, "mul": FK_OP_MUL, "add": FK_OP_ADD,
       "sub": FK_OP_SUB, "div": FK_OP_DIV, "loop": FK_OP_LOOP}
 TORCH_DTYPE = {"u8": torch.uint8, "f16": torch.float16, "f32": torch.float32, "f64": torch.float64}
@@ -249,17 +252,20 @@ def chain_desc(chain: dict):
 
 def make_items(chain: dict, frames: list, items: list, outs: list):
     """fk_item array: `frames` are device tensors (H, W, C) (any row pitch in
-    their stride), `outs` device tensors receiving each item's output."""
+    their stride; NV12 frames are (3H/2, W) bytes), `outs` device tensors
+    receiving each item's output."""
     arr = (fk_item * max(1, len(items)))()
+    nv12 = chain["read"]["kind"] in NV12
     for b, it in enumerate(items):
         fr = frames[it["frame"]]
         a = arr[b]
         a.src.ptr = fr.data_ptr()
-        a.src.height, a.src.width = int(fr.shape[0]), int(fr.shape[1])
+        a.src.height = int(fr.shape[0]) * 2 // 3 if nv12 else int(fr.shape[0])
+        a.src.width = int(fr.shape[1])
         a.src.pitch_bytes = int(fr.stride(0)) * fr.element_size()
         a.x, a.y, a.w, a.h = it["x"], it["y"], it["w"], it["h"]
         a.dst = outs[b].data_ptr()
-        if chain["read"]["kind"] == "crop_resize":
+        if chain["read"]["kind"] in RESIZING:
             a.out_w, a.out_h = it["out_w"], it["out_h"]
         else:
             a.out_w, a.out_h = 0, 0
@@ -270,7 +276,7 @@ def out_shape(chain: dict, item: dict) -> tuple:
     c = chain["read"]["channels"]
     if chain["write"]["layout"] == "stats":
         return (c, 4)  # per channel: min, max, sum, mean (fp64)
-    if chain["read"]["kind"] == "crop_resize":
+    if chain["read"]["kind"] in RESIZING:
         oh, ow = item["out_h"], item["out_w"]
     else:
         oh, ow = item["h"], item["w"]

@@ -271,6 +271,135 @@ struct ReadCropResize {
     }
 };
 
+// Nearest-neighbour crop+resize: output index o takes ROI index
+// floor((2o + 1) * in / (2 out)).  The quotient comes from an fp32
+// estimate (off by at most one: the quotient is below 2^16 and the estimate
+// carries three roundings of 2^-24) corrected by exact integer products.
+__device__ __forceinline__ int nearest_index(int o, int in, int out)
+{
+    const uint64_t num = (uint64_t)(2 * o + 1) * (uint64_t)in;
+    const uint64_t den = 2ull * (uint64_t)out;
+    int q = (int)((float)num * (1.0f / (float)den));
+    if ((uint64_t)q * den > num)
+        --q;
+    else if ((uint64_t)(q + 1) * den <= num)
+        ++q;
+    return q;
+}
+
+template <int DT, int C>
+struct ReadCropNearest {
+    static constexpr int kind = RD_CROP_NEAREST;
+    static constexpr int elem_size = DSize<DT>::v;
+
+    __device__ __forceinline__ static void load(const ItemRec &it, int oy, int ox0, int n,
+                                                float (&r)[kUnitPx][C])
+    {
+        constexpr int ES = DSize<DT>::v;
+        const int sy = nearest_index(oy, it.h, it.oh);
+        gsrc_t row = (gsrc_t)it.src + (int64_t)(it.y + sy) * it.pitch + (int64_t)it.x * (C * ES);
+#pragma unroll
+        for (int i = 0; i < kUnitPx; ++i) {
+            if (i < n) {
+                const int sx = nearest_index(ox0 + i, it.w, it.ow);
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    r[i][c] = load_elem<DT>(row + (sx * C + c) * ES);
+            } else {
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    r[i][c] = 0.0f;
+            }
+        }
+    }
+};
+
+// NV12 (BT.601 limited range) -> B, G, R in fp32, one IEEE operation per
+// product and sum in a fixed order (compiled without contraction).
+__device__ __forceinline__ void nv12_to_bgr(float Y, float U, float V, float (&o)[3])
+{
+    const float u = U - 128.0f;
+    const float v = V - 128.0f;
+    const float c = 1.164f * (Y - 16.0f);
+    o[0] = c + 2.018f * u;
+    o[1] = (c - 0.813f * v) - 0.391f * u;
+    o[2] = c + 1.596f * v;
+}
+
+// Pixel (x, y) of an NV12 frame (absolute luma coordinates): the luma byte
+// and the chroma pair serving its 2x2 block; the chroma plane starts
+// `fh` rows (the luma height) below the frame base, at the same pitch.
+__device__ __forceinline__ void nv12_pixel(const ItemRec &it, int x, int y, float (&o)[3])
+{
+    gsrc_t base = (gsrc_t)it.src;
+    const float Y = load_elem<DT_U8>(base + (int64_t)y * it.pitch + x);
+    gsrc_t uv = base + ((int64_t)it.fh + (y >> 1)) * it.pitch + (x & ~1);
+    nv12_to_bgr(Y, load_elem<DT_U8>(uv), load_elem<DT_U8>(uv + 1), o);
+}
+
+// NV12 crop read 1:1 (three output channels).
+template <int C>
+struct ReadNV12 {
+    static_assert(C == 3, "NV12 reads give three channels");
+    static constexpr int kind = RD_NV12;
+    static constexpr int elem_size = 1;
+
+    __device__ __forceinline__ static void load(const ItemRec &it, int oy, int ox0, int n,
+                                                float (&r)[kUnitPx][C])
+    {
+#pragma unroll
+        for (int i = 0; i < kUnitPx; ++i) {
+            if (i < n) {
+                nv12_pixel(it, it.x + ox0 + i, it.y + oy, r[i]);
+            } else {
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    r[i][c] = 0.0f;
+            }
+        }
+    }
+};
+
+// NV12 crop + bilinear resize of the converted values (taps converted,
+// then the same lerps as the u8/f16/f32 resize).
+template <int C>
+struct ReadNV12Resize {
+    static_assert(C == 3, "NV12 reads give three channels");
+    static constexpr int kind = RD_NV12_RESIZE;
+    static constexpr int elem_size = 1;
+
+    __device__ __forceinline__ static void load(const ItemRec &it, int oy, int ox0, int n,
+                                                float (&r)[kUnitPx][C])
+    {
+        int y0, y1;
+        float ay;
+        bilinear_coord(oy, it.sy, it.h, y0, y1, ay);
+#pragma unroll
+        for (int i = 0; i < kUnitPx; ++i) {
+            if (i < n) {
+                int x0, x1;
+                float ax;
+                bilinear_coord(ox0 + i, it.sx, it.w, x0, x1, ax);
+                float p00[3], p01[3], p10[3], p11[3];
+                nv12_pixel(it, it.x + x0, it.y + y0, p00);
+                nv12_pixel(it, it.x + x1, it.y + y0, p01);
+                nv12_pixel(it, it.x + x0, it.y + y1, p10);
+                nv12_pixel(it, it.x + x1, it.y + y1, p11);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const float top = fmaf(ax, p01[c] - p00[c], p00[c]);
+                    const float bot = fmaf(ax, p11[c] - p10[c], p10[c]);
+                    r[i][c] = fmaf(ay, bot - top, top);
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    r[i][c] = 0.0f;
+            }
+        }
+    }
+};
+
 // ------------------------------------------------- compile-time ops --
 // Storage-less op types with a static exec on one pixel (a C-vector in
 // registers); binary ops take their constants from the plan's constant
@@ -766,7 +895,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_transform(const KArgs a)
             it.w = roi->w;
             it.h = roi->h;
             it.dst += (uint64_t)b * (uint64_t)a.inl_dst_stride;
-            if constexpr (Read::kind == RD_CROP_RESIZE) {
+            if constexpr (rd_bilinear(Read::kind)) {
                 // the same IEEE fp32 divisions the host performs for the table forms
                 it.sx = (float)it.w / (float)it.ow;
                 it.sy = (float)it.h / (float)it.oh;
@@ -943,7 +1072,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_stats(const KArgs a)
             it.w = roi->w;
             it.h = roi->h;
             it.dst += (uint64_t)b * (uint64_t)a.inl_dst_stride;
-            if constexpr (Read::kind == RD_CROP_RESIZE) {
+            if constexpr (rd_bilinear(Read::kind)) {
                 it.sx = (float)it.w / (float)it.ow;
                 it.sy = (float)it.h / (float)it.oh;
             }

@@ -67,8 +67,11 @@ fk_status fk::validate_chain(const fk_chain_desc *ch)
     if (!ch)
         return set_error(FK_ERR_INVALID_ARG, "chain is null");
     const fk_read_desc &r = ch->read;
-    if (r.kind != FK_READ_PLAIN && r.kind != FK_READ_CROP_RESIZE)
+    if (r.kind < FK_READ_PLAIN || r.kind > FK_READ_NV12_RESIZE)
         return set_error(FK_ERR_INVALID_ARG, "unknown read kind %d", r.kind);
+    if ((r.kind == FK_READ_NV12 || r.kind == FK_READ_NV12_RESIZE) &&
+        (r.in_dtype != FK_U8 || r.channels != 3))
+        return set_error(FK_ERR_INVALID_ARG, "NV12 reads take FK_U8 frames and give 3 channels");
     if (r.in_dtype != FK_U8 && r.in_dtype != FK_F16 && r.in_dtype != FK_F32)
         return set_error(FK_ERR_INVALID_ARG, "unknown input dtype %d", r.in_dtype);
     if (r.channels != 1 && r.channels != 3 && r.channels != 4)
@@ -120,6 +123,7 @@ fk_status fk::validate_items(const fk_chain_desc *ch, const fk_item *items, int3
         return set_error(FK_ERR_INVALID_ARG, "items is null");
     const int64_t es = dtype_size(ch->read.in_dtype);
     const int64_t C = ch->read.channels;
+    const bool nv12 = ch->read.kind == FK_READ_NV12 || ch->read.kind == FK_READ_NV12_RESIZE;
     for (int32_t b = 0; b < n; ++b) {
         const fk_item &it = items[b];
         if (!it.src.ptr || !it.dst)
@@ -128,9 +132,14 @@ fk_status fk::validate_items(const fk_chain_desc *ch, const fk_item *items, int3
             return set_error(FK_ERR_INVALID_ARG, "item %d: empty frame", b);
         if (it.src.width > 65535 || it.src.height > 65535)
             return set_error(FK_ERR_UNSUPPORTED, "item %d: frame sides above 65535", b);
-        if (it.src.pitch_bytes < it.src.width * C * es || it.src.pitch_bytes % es != 0)
+        if (nv12) {
+            if (it.src.width % 2 || it.src.height % 2 || it.src.pitch_bytes < it.src.width)
+                return set_error(FK_ERR_INVALID_ARG,
+                                 "item %d: NV12 frames need even sides and pitch >= width", b);
+        } else if (it.src.pitch_bytes < it.src.width * C * es || it.src.pitch_bytes % es != 0) {
             return set_error(FK_ERR_INVALID_ARG, "item %d: bad pitch %lld", b,
                              (long long)it.src.pitch_bytes);
+        }
         if ((uintptr_t)it.src.ptr % es != 0)
             return set_error(FK_ERR_INVALID_ARG, "item %d: src not element aligned", b);
         if ((uintptr_t)it.dst % dtype_size(ch->write.out_dtype) != 0)
@@ -140,7 +149,7 @@ fk_status fk::validate_items(const fk_chain_desc *ch, const fk_item *items, int3
             return set_error(FK_ERR_INVALID_ARG,
                              "item %d: ROI (%d,%d,%d,%d) not inside the %dx%d frame", b, it.x,
                              it.y, it.w, it.h, it.src.width, it.src.height);
-        if (ch->read.kind == FK_READ_CROP_RESIZE) {
+        if (rd_resizes(ch->read.kind)) {
             if (it.out_w < 1 || it.out_h < 1)
                 return set_error(FK_ERR_INVALID_ARG, "item %d: output size must be positive", b);
             if ((int64_t)it.out_w * it.out_h > (1LL << 28))
@@ -431,7 +440,7 @@ uint32_t fk::build_items(const fk_plan *p, const fk_item *items, int32_t n,
         r.y = it.y;
         r.w = it.w;
         r.h = it.h;
-        if (p->chain.read.kind == FK_READ_CROP_RESIZE) {
+        if (rd_resizes(p->chain.read.kind)) {
             r.ow = it.out_w;
             r.oh = it.out_h;
             r.sx = (float)it.w / (float)it.out_w;
@@ -528,7 +537,7 @@ bool fk::compact_batch(const fk_plan *p, const fk_item *items, int32_t n)
     if (n < 2)
         return false;
     const fk_item &f = items[0];
-    const bool rs = p->chain.read.kind == FK_READ_CROP_RESIZE;
+    const bool rs = rd_resizes(p->chain.read.kind);
     const intptr_t stride = (intptr_t)items[1].dst - (intptr_t)items[0].dst;
     if (stride < 0 || f.src.width > 65535 || f.src.height > 65535)
         return false;

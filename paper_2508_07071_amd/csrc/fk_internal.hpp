@@ -8,7 +8,17 @@
 
 namespace fk {
 
-enum : int32_t { RD_PLAIN = 0, RD_CROP_RESIZE = 1 };
+enum : int32_t {
+    RD_PLAIN = 0,
+    RD_CROP_RESIZE = 1,
+    RD_CROP_NEAREST = 2,
+    RD_NV12 = 3,
+    RD_NV12_RESIZE = 4,
+};
+// read kinds with an output size of their own (not the ROI's)
+constexpr bool rd_resizes(int rk) { return rk == RD_CROP_RESIZE || rk == RD_CROP_NEAREST || rk == RD_NV12_RESIZE; }
+// read kinds whose kernels use the fp32 scales w/ow and h/oh
+constexpr bool rd_bilinear(int rk) { return rk == RD_CROP_RESIZE || rk == RD_NV12_RESIZE; }
 enum : int32_t { DT_U8 = 0, DT_F16 = 1, DT_F32 = 2 };
 enum : int32_t { LY_PACKED = 0, LY_PLANAR = 1, LY_STATS = 2 };
 

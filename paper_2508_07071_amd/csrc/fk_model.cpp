@@ -304,7 +304,7 @@ extern "C" fk_status fk_model_features(const fk_plan *p, const fk_item *items, i
         const int es_in = dtype_size(ch.read.in_dtype), es_out = dtype_size(ch.write.out_dtype);
         float f[F];
         std::fill(f, f + F, 0.0f);
-        f[0] = ch.read.kind == FK_READ_CROP_RESIZE ? 1.0f : 0.0f;
+        f[0] = rd_resizes(ch.read.kind) ? 1.0f : 0.0f;
         f[1 + ch.read.in_dtype] = 1.0f;
         f[4 + (C == 1 ? 0 : C == 3 ? 1 : 2)] = 1.0f;
         f[7] = ch.write.out_dtype == FK_F16 ? 1.0f : 0.0f;
@@ -314,7 +314,7 @@ extern "C" fk_status fk_model_features(const fk_plan *p, const fk_item *items, i
                max_px = 0, vsrc = 0, vdst = 0, ragged = 0;
         for (int32_t b = 0; b < n; ++b) {
             const fk_item &it = items[b];
-            const bool rs = ch.read.kind == FK_READ_CROP_RESIZE;
+            const bool rs = rd_resizes(ch.read.kind);
             const double ow = rs ? it.out_w : it.w, oh = rs ? it.out_h : it.h;
             const double px = ow * oh;
             out_px += px;

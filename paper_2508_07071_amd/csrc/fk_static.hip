@@ -14,6 +14,11 @@ const void *kernel_runtime_resize_f32(int, int, int, int);
 
 const void *kernel_stats_plain(int, int, int);
 const void *kernel_stats_resize(int, int, int);
+const void *kernel_stats_other(int, int, int, int);
+const void *kernel_runtime_nearest_u8(int, int, int, int);
+const void *kernel_runtime_nearest_f16(int, int, int, int);
+const void *kernel_runtime_nearest_f32(int, int, int, int);
+const void *kernel_runtime_nv12(int, int, int, int, int);
 
 const void *kernel_stats(int read_kind, int in_dt, int channels, int coarsen)
 {
@@ -21,7 +26,7 @@ const void *kernel_stats(int read_kind, int in_dt, int channels, int coarsen)
         return kernel_stats_plain(in_dt, channels, coarsen);
     if (read_kind == RD_CROP_RESIZE)
         return kernel_stats_resize(in_dt, channels, coarsen);
-    return nullptr;
+    return kernel_stats_other(read_kind, in_dt, channels, coarsen);
 }
 
 const void *kernel_runtime(int read_kind, int in_dt, int channels, int out_dt, int layout,
@@ -39,6 +44,14 @@ const void *kernel_runtime(int read_kind, int in_dt, int channels, int out_dt, i
         case DT_F16: return kernel_runtime_resize_f16(channels, out_dt, layout, coarsen);
         case DT_F32: return kernel_runtime_resize_f32(channels, out_dt, layout, coarsen);
         }
+    } else if (read_kind == RD_CROP_NEAREST) {
+        switch (in_dt) {
+        case DT_U8: return kernel_runtime_nearest_u8(channels, out_dt, layout, coarsen);
+        case DT_F16: return kernel_runtime_nearest_f16(channels, out_dt, layout, coarsen);
+        case DT_F32: return kernel_runtime_nearest_f32(channels, out_dt, layout, coarsen);
+        }
+    } else if ((read_kind == RD_NV12 || read_kind == RD_NV12_RESIZE) && in_dt == DT_U8) {
+        return kernel_runtime_nv12(read_kind, channels, out_dt, layout, coarsen);
     }
     return nullptr;
 }

@@ -56,6 +56,45 @@ __global__ __launch_bounds__(kUnfusedBlock) void k_resize(const uint8_t *src, in
     }
 }
 
+// Packed TIn image (contiguous w*h*C) -> packed fp32 nearest-resized image:
+// output o takes source floor((2o + 1) * in / (2 out)), exact in 64 bits.
+template <int DT>
+__global__ __launch_bounds__(kUnfusedBlock) void k_nearest(const uint8_t *src, int w, int h, int C,
+                                                          float *dst, int ow, int oh)
+{
+    const int64_t npix = (int64_t)ow * oh;
+    gsrc_t s = (gsrc_t)src;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npix;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int oy = (int)(p / ow), ox = (int)(p - (int64_t)oy * ow);
+        const int64_t sy = (2 * (int64_t)oy + 1) * h / (2 * (int64_t)oh);
+        const int64_t sx = (2 * (int64_t)ox + 1) * w / (2 * (int64_t)ow);
+        for (int c = 0; c < C; ++c)
+            ((FK_GLOBAL float *)dst)[p * C + c] = uload<DT>(s, (sy * w + sx) * C + c);
+    }
+}
+
+// NV12 ROI -> packed fp32 B, G, R (the colour-conversion op of the
+// unfused pipeline; the ROI's rows are read in place).
+__global__ __launch_bounds__(kUnfusedBlock) void k_nv12(const uint8_t *frame, int64_t pitch,
+                                                       int fh, int x, int y, int w, int h,
+                                                       float *dst)
+{
+    const int64_t npix = (int64_t)w * h;
+    gsrc_t base = (gsrc_t)frame;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npix;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(p / w), i = (int)(p - (int64_t)j * w);
+        const int ax = x + i, ay = y + j;
+        const float Y = load_elem<DT_U8>(base + (int64_t)ay * pitch + ax);
+        gsrc_t uv = base + ((int64_t)fh + (ay >> 1)) * pitch + (ax & ~1);
+        float o[3];
+        nv12_to_bgr(Y, load_elem<DT_U8>(uv), load_elem<DT_U8>(uv + 1), o);
+        for (int c = 0; c < 3; ++c)
+            ((FK_GLOBAL float *)dst)[p * 3 + c] = o[c];
+    }
+}
+
 // One elementwise op over a packed image of n elements: TIn -> fp32.
 // code: -1 cvt (copy), OPC_MUL, OPC_ADD (SUB arrives as ADD of -k), OPC_DIV.
 template <int DT>
@@ -280,7 +319,7 @@ static ScratchPlan scratch_for(const fk_plan *p, const fk_item &it)
     ScratchPlan s;
     s.crop = (size_t)it.w * it.h * C * es;
     size_t npix = (size_t)it.w * it.h;
-    if (p->chain.read.kind == FK_READ_CROP_RESIZE)
+    if (rd_resizes(p->chain.read.kind))
         npix = std::max(npix, (size_t)it.out_w * it.out_h);
     s.buf = npix * C * sizeof(float);
     if (p->chain.write.layout == FK_STATS)
@@ -358,7 +397,17 @@ static fk_status run_item_unfused(const fk_plan *p, const fk_item &it, uint8_t *
 
     const bool contiguous = (size_t)it.src.pitch_bytes == row_bytes ||
                             (it.h == 1);
-    if (p->chain.read.kind == FK_READ_PLAIN && contiguous) {
+    const int rk = p->chain.read.kind;
+    if (rk == FK_READ_NV12 || rk == FK_READ_NV12_RESIZE) {
+        // crop + colour conversion to fp32 BGR in one pass
+        float *o = buf[nb];
+        nb ^= 1;
+        k_nv12<<<grid_for(npix), kUnfusedBlock, 0, st>>>((const uint8_t *)it.src.ptr,
+                                                         it.src.pitch_bytes, it.src.height, it.x,
+                                                         it.y, it.w, it.h, o);
+        cur = o;
+        cur_dt = DT_F32;
+    } else if (rk == FK_READ_PLAIN && contiguous) {
         cur = roi;  // the ROI already is a dense image: no crop kernel
     } else {
         e = hipMemcpy2DAsync(crop, row_bytes, roi, it.src.pitch_bytes, row_bytes, it.h,
@@ -367,15 +416,29 @@ static fk_status run_item_unfused(const fk_plan *p, const fk_item &it, uint8_t *
             return hip_error(e, "crop copy");
         cur = crop;
     }
-    if (p->chain.read.kind == FK_READ_CROP_RESIZE) {
-        const float sx = (float)it.w / (float)it.out_w, sy = (float)it.h / (float)it.out_h;
+    if (rk == FK_READ_CROP_NEAREST) {
         npix = (int64_t)it.out_w * it.out_h;
         float *o = buf[nb];
         nb ^= 1;
         const unsigned g = grid_for(npix);
         if (din == DT_U8)
-            k_resize<DT_U8><<<g, kUnfusedBlock, 0, st>>>((const uint8_t *)cur, it.w, it.h, C, o, it.out_w, it.out_h, sx, sy);
+            k_nearest<DT_U8><<<g, kUnfusedBlock, 0, st>>>((const uint8_t *)cur, it.w, it.h, C, o, it.out_w, it.out_h);
         else if (din == DT_F16)
+            k_nearest<DT_F16><<<g, kUnfusedBlock, 0, st>>>((const uint8_t *)cur, it.w, it.h, C, o, it.out_w, it.out_h);
+        else
+            k_nearest<DT_F32><<<g, kUnfusedBlock, 0, st>>>((const uint8_t *)cur, it.w, it.h, C, o, it.out_w, it.out_h);
+        cur = o;
+        cur_dt = DT_F32;
+    }
+    if (rk == FK_READ_CROP_RESIZE || rk == FK_READ_NV12_RESIZE) {
+        const float sx = (float)it.w / (float)it.out_w, sy = (float)it.h / (float)it.out_h;
+        npix = (int64_t)it.out_w * it.out_h;
+        float *o = buf[nb];
+        nb ^= 1;
+        const unsigned g = grid_for(npix);
+        if (cur_dt == DT_U8)
+            k_resize<DT_U8><<<g, kUnfusedBlock, 0, st>>>((const uint8_t *)cur, it.w, it.h, C, o, it.out_w, it.out_h, sx, sy);
+        else if (cur_dt == DT_F16)
             k_resize<DT_F16><<<g, kUnfusedBlock, 0, st>>>((const uint8_t *)cur, it.w, it.h, C, o, it.out_w, it.out_h, sx, sy);
         else
             k_resize<DT_F32><<<g, kUnfusedBlock, 0, st>>>((const uint8_t *)cur, it.w, it.h, C, o, it.out_w, it.out_h, sx, sy);

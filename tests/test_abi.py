@@ -166,3 +166,25 @@ def test_stats_write_validation(dtype, layout, ok):
     c = norm_chain()
     c["write"] = {"dtype": dtype, "layout": layout}
     assert fk.fk_chain_validate(fk.chain_desc(c)) == ok
+
+
+@pytest.mark.parametrize("kind,dtype,C,ok", [
+    ("nv12", "u8", 3, fk.FK_OK), ("nv12_resize", "u8", 3, fk.FK_OK), ("crop_nearest", "f16", 4, fk.FK_OK),
+    ("nv12", "u8", 1, fk.FK_ERR_INVALID_ARG), ("nv12_resize", "f32", 3, fk.FK_ERR_INVALID_ARG),
+])
+def test_read_kind_validation(kind, dtype, C, ok):
+    c = {"read": {"kind": kind, "dtype": dtype, "channels": C, "out_w": 0, "out_h": 0},
+         "ops": [{"kind": "cvt", "k": []}], "write": {"dtype": "f32", "layout": "planar"}}
+    assert fk.fk_chain_validate(fk.chain_desc(c)) == ok
+
+
+def test_nv12_items_need_even_frames():
+    c = {"read": {"kind": "nv12", "dtype": "u8", "channels": 3, "out_w": 0, "out_h": 0},
+         "ops": [], "write": {"dtype": "f32", "layout": "packed"}}
+    d = fk.chain_desc(c)
+    it = (fk.fk_item * 1)()
+    it[0].src.ptr, it[0].src.width, it[0].src.height, it[0].src.pitch_bytes = 4096, 64, 48, 64
+    it[0].x, it[0].y, it[0].w, it[0].h, it[0].dst = 0, 0, 8, 8, 8192
+    assert fk.lib().fk_items_validate(C.byref(d), it, 1) == fk.FK_OK
+    it[0].src.width = 63
+    assert fk.lib().fk_items_validate(C.byref(d), it, 1) == fk.FK_ERR_INVALID_ARG

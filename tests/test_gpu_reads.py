@@ -1,0 +1,115 @@
+"""The other read ops on the GPU, through the C ABI, against the oracle:
+nearest-neighbour crop+resize (u8/fp16/fp32 frames, 1/3/4 channels) and
+NV12 reads (BT.601 limited range to BGR) with and without a bilinear
+resize.  Strict plans are bit-exact; default plans within
+|g - r| <= 1e-5 * max(|r|, s)."""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+import paper_2508_07071_amd as fk
+from fkhelpers import Plan, assert_bitexact, assert_close, host, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def norm_ops(C):
+    return [{"kind": "swap", "k": []}, {"kind": "cvt", "k": []},
+            {"kind": "mul", "k": [datagen.NORM_SCALE]},
+            {"kind": "sub", "k": (datagen.NORM_MEAN + [0.5])[:C] if C > 1 else [0.45]},
+            {"kind": "div", "k": (datagen.NORM_STD + [0.25])[:C] if C > 1 else [0.226]}]
+
+
+def both_modes(chain, frames, items, what, unfused=False):
+    refs = oracle.run_chain(chain, frames, items)
+    dframes = to_dev(frames)
+    for strict in (True, False):
+        with Plan(chain, len(items), strict=strict) as p:
+            outs = host(p.run(dframes, items))
+            uouts = host(p.run_unfused(dframes, items)) if (unfused and strict) else None
+        for b, (g, r) in enumerate(zip(outs, refs)):
+            if strict:
+                assert_bitexact(g, r["out"], f"{what} strict item {b}")
+                if uouts is not None:
+                    assert_bitexact(uouts[b], r["out"], f"{what} unfused item {b}")
+            else:
+                assert_close(g, r, what=f"{what} item {b}")
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f16", "f32"])
+@pytest.mark.parametrize("C", [1, 3, 4])
+def test_nearest_crops_match_oracle(dtype, C):
+    say("nearest", dtype, C)
+    g = datagen.rng(C * 7 + len(dtype))
+    fr = datagen.frame(g, 300, 410, C, dtype=dtype)
+    items = datagen.random_crops(g, 9, 410, 300, lo=3, hi=290, out=(61, 37))
+    items += [{"frame": 0, "x": 5, "y": 6, "w": 20, "h": 10, "out_w": 160, "out_h": 30},   # upscale
+              {"frame": 0, "x": 0, "y": 0, "w": 410, "h": 300, "out_w": 7, "out_h": 5},  # strong downscale
+              {"frame": 0, "x": 100, "y": 100, "w": 1, "h": 1, "out_w": 9, "out_h": 3}]  # one pixel
+    for layout in ("packed", "planar"):
+        ch = {"read": {"kind": "crop_nearest", "dtype": dtype, "channels": C, "out_w": 0, "out_h": 0},
+              "ops": norm_ops(C), "write": {"dtype": "f32", "layout": layout}}
+        both_modes(ch, [fr], items, f"nearest {dtype}x{C} {layout}", unfused=layout == "planar")
+
+
+@pytest.mark.parametrize("kind", ["nv12", "nv12_resize"])
+@pytest.mark.parametrize("out_dtype,layout", [("f32", "planar"), ("f16", "packed"), ("f32", "packed")])
+def test_nv12_reads_match_oracle(kind, out_dtype, layout):
+    say(kind, out_dtype, layout)
+    g = datagen.rng(11 if kind == "nv12" else 12)
+    fr = datagen.nv12_frame(g, 480, 640)
+    if kind == "nv12":
+        items = [{"frame": 0, "x": x, "y": y, "w": w, "h": h, "out_w": w, "out_h": h}
+                 for x, y, w, h in ((0, 0, 640, 480), (3, 5, 17, 11), (101, 77, 254, 133), (639, 479, 1, 1))]
+    else:
+        items = datagen.random_crops(g, 6, 640, 480, lo=2, hi=400, out=(64, 128))
+        items.append({"frame": 0, "x": 1, "y": 1, "w": 9, "h": 7, "out_w": 224, "out_h": 224})
+    ch = {"read": {"kind": kind, "dtype": "u8", "channels": 3, "out_w": 0, "out_h": 0},
+          "ops": norm_ops(3), "write": {"dtype": out_dtype, "layout": layout}}
+    both_modes(ch, [fr], items, f"{kind} {out_dtype} {layout}", unfused=out_dtype == "f32")
+
+
+def test_nv12_frame_with_row_padding():
+    """An NV12 frame whose rows are padded (pitch 704 for 640 pixels): both
+    planes follow the pitch."""
+    say("nv12 padded rows")
+    g = datagen.rng(13)
+    dense = datagen.nv12_frame(g, 96, 640)
+    padded = np.zeros((144, 704), np.uint8)
+    padded[:, :640] = dense
+    items = [{"frame": 0, "x": 13, "y": 9, "w": 300, "h": 70, "out_w": 64, "out_h": 128}]
+    ch = {"read": {"kind": "nv12_resize", "dtype": "u8", "channels": 3, "out_w": 0, "out_h": 0},
+          "ops": norm_ops(3), "write": {"dtype": "f32", "layout": "planar"}}
+    ref = oracle.run_chain(ch, [dense], items)[0]
+    dfr = torch.from_numpy(padded).cuda()[:, :640]  # a strided view: pitch 704 bytes
+    with Plan(ch, 1, strict=True) as p:
+        out = host(p.run([dfr], items))[0]
+    assert_bitexact(out, ref["out"], "padded nv12")
+
+
+def test_stats_over_nearest_and_nv12_reads():
+    say("stats over nearest / nv12")
+    g = datagen.rng(14)
+    cases = [({"kind": "crop_nearest", "dtype": "u8", "channels": 3}, datagen.frame(g, 200, 300, 3)),
+             ({"kind": "nv12_resize", "dtype": "u8", "channels": 3}, datagen.nv12_frame(g, 200, 300))]
+    for read, fr in cases:
+        read = dict(read, out_w=0, out_h=0)
+        items = datagen.random_crops(g, 5, 300, 200, lo=10, hi=180, out=(50, 70))
+        img = {"read": read, "ops": norm_ops(3), "write": {"dtype": "f32", "layout": "packed"}}
+        st = dict(img, write={"dtype": "f64", "layout": "stats"})
+        imgs = oracle.run_chain(img, [fr], items)
+        sts = oracle.run_chain(st, [fr], items)
+        with Plan(st, len(items), strict=True) as p:
+            outs = host(p.run(to_dev([fr]), items))
+        for b, (o, s_, im) in enumerate(zip(outs, sts, imgs)):
+            v = im["out"].reshape(-1, 3).astype(np.float64)
+            n = v.shape[0]
+            np.testing.assert_array_equal(o[:, :2], s_["out"][:, :2])
+            bound = 2 * (n - 1) * 2.0 ** -53 * np.abs(v).sum(0)
+            assert np.all(np.abs(o[:, 2] - s_["out"][:, 2]) <= bound), (read["kind"], b)
