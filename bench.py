@@ -21,7 +21,8 @@ Printed JSON line:
 Other workloads (--workload), for the design notes, not the headline line:
 "hf" (batched uneven crops), "loop" (long Mul+Add chains through the loop
 op on a batch of small images), "stats" (the reduction write), "sweeps"
-(the paper's data-size, plain-read batch and data-type sweeps), "serve" (the serving loop), "costmodel"
+(the paper's data-size, plain-read batch and data-type sweeps), "reads"
+(nearest-neighbour and NV12 reads), "serve" (the serving loop), "costmodel"
 (training and evaluating the launch-configuration model) and "copy" (a
 plain device copy, the bandwidth reference).
 """
@@ -640,6 +641,85 @@ def sweeps_workload(args):
             "data_size": data_size, "hf_plain": hf_plain, "dtypes": dtypes}
 
 
+def reads_workload(args):
+    """The other read ops (nearest-neighbour and NV12), fused vs the unfused
+    baseline:
+      nv12_full:   a 3840x2160 NV12 frame (12.4 MB) converted to planar fp32
+                   B, G, R (99.5 MB written): HBM-bound, algorithmic bytes =
+                   frame + output;
+      nv12_crops:  256 uneven crops of the same frame, resized bilinearly to
+                   64x128 and normalised (the hot chain on NV12 input);
+      nearest_crops: the same 256 crops of a 3840x2160x3 u8 frame with a
+                   nearest-neighbour resize."""
+    import torch
+
+    import datagen
+    import paper_2508_07071_amd as fk
+
+    dev = torch.device("cuda:0")
+    stream = fk.stream_handle()
+    H, W = FRAME_HW
+    g = datagen.rng(args.seed)
+
+    def timeit(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def measure(ch, frame, items, alg, name, reps=50):
+        outs = [torch.empty(fk.out_shape(ch, it), dtype=fk.TORCH_DTYPE[ch["write"]["dtype"]], device=dev)
+                for it in items]
+        arr = fk.make_items(ch, [frame], items, outs)
+        n = len(items)
+        plan = fk.fk_plan_create(fk.chain_desc(ch), n, fk.plan_opts())
+        best, _ = fk.fk_autotune(plan, arr, n, 5)
+        r = {"case": name, "items": n, "alg_bytes": alg, "autotuned": [best.block_threads, best.coarsen]}
+        r["fused_ms"] = round(timeit(lambda: fk.fk_run(plan, arr, n, stream), reps), 5)
+        r["gbps"] = round(alg / (r["fused_ms"] * 1e-3) / 1e9, 1)
+        r["hbm_frac"] = round(r["gbps"] / HBM_PEAK_GBPS, 4)
+        if not args.no_unfused:
+            nbytes = fk.fk_unfused_scratch_bytes(plan, arr, n)
+            scratch = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+            r["unfused_ms"] = round(timeit(lambda: fk.fk_run_unfused(plan, arr, n, scratch.data_ptr(), nbytes,
+                                                                   stream), 3), 4)
+            r["speedup_vs_unfused"] = round(r["unfused_ms"] / r["fused_ms"], 1)
+        fk.fk_plan_destroy(plan)
+        log(r)
+        return r
+
+    nv12 = torch.from_numpy(datagen.nv12_frame(g, H, W)).to(dev)
+    rows = []
+    full = {"read": {"kind": "nv12", "dtype": "u8", "channels": 3, "out_w": 0, "out_h": 0},
+            "ops": [], "write": {"dtype": "f32", "layout": "planar"}}
+    rows.append(measure(full, nv12, [{"frame": 0, "x": 0, "y": 0, "w": W, "h": H}],
+                        H * W * 3 // 2 + H * W * 3 * 4, "nv12_full"))
+    crops = datagen.random_crops(g, 256, W, H)
+    norm = datagen.normalize_chain(64, 128)
+    taps = sum(min(it["w"], 128) * min(it["h"], 256) * 3 // 2 for it in crops)
+    rows.append(measure(dict(norm, read=dict(norm["read"], kind="nv12_resize")), nv12, crops,
+                        taps + 256 * 3 * 128 * 64 * 4, "nv12_crops"))
+    bgr = torch.from_numpy(datagen.frame(g, H, W, 3)).to(dev)
+    taps = sum(min(it["w"], 64) * min(it["h"], 128) * 3 for it in crops)
+    rows.append(measure(dict(norm, read=dict(norm["read"], kind="crop_nearest")), bgr, crops,
+                        taps + 256 * 3 * 128 * 64 * 4, "nearest_crops"))
+    top = rows[0]
+    return {"metric": "other read ops: fused GB/s vs unfused", "value": top["gbps"], "unit": "GB/s",
+            "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "reads: NV12 4K frame to planar fp32; 256 NV12 / nearest crops -> 64x128",
+                       "seed": args.seed},
+            "roofline": {"bound": "hbm", "achieved": top["gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": top["hbm_frac"], "traffic": None,
+                         "kernel": "NV12 3840x2160 -> planar fp32 BGR", "kernel_ms": top["fused_ms"]},
+            "rows": rows}
+
+
 def serve_workload(args):
     """Serving loop (config 4 sizes): open-loop Poisson arrivals, continuous
     batching vs per-request fused vs per-request unfused; p50/p99 latency."""
@@ -746,7 +826,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="vf", choices=["vf", "hf", "loop", "stats", "sweeps", "copy", "serve", "costmodel"])
+    ap.add_argument("--workload", default="vf", choices=["vf", "hf", "loop", "stats", "sweeps", "reads", "copy", "serve", "costmodel"])
     ap.add_argument("--data", nargs="+", default=[], help="cost-model label shards")
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--rates", type=float, nargs="+", default=[200, 500, 1000, 2000])
@@ -784,6 +864,9 @@ def main():
         return
     if args.workload == "sweeps":
         print(json.dumps(sweeps_workload(args)))
+        return
+    if args.workload == "reads":
+        print(json.dumps(reads_workload(args)))
         return
     if args.workload == "serve":
         print(json.dumps(serve_workload(args)))
