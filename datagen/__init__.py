@@ -164,18 +164,22 @@ def data_size_case(n_elems: int, pairs: int = 100, seed: int = 0, row: int = 409
 def cast_chain_batch(batch: int = 50, in_dtype: str = "u8", out_dtype: str = "f32", seed: int = 0,
                      hw=(120, 60)) -> dict:
     """Sections VI-C and VI-I: `batch` single-channel images of hw (height,
-    width) stacked in one frame (image b in rows [b*h, (b+1)*h)), chain
+    width) in one frame: columns of up to 512 images stacked vertically
+    (image b at column b // 512, rows [(b % 512) h, (b % 512 + 1) h)), chain
     Read -> Cast -> Multiply -> Subtract -> Divide -> Write.  Constants:
     mul uniform in [0.5, 1.5), sub in [-1, 1), div in [0.5, 1.5), drawn after
     the frame values."""
     g = rng(seed)
     h, w = hw
-    fr = frame(g, batch * h, w, 1, dtype=in_dtype)
+    per_col = 512
+    cols = (batch + per_col - 1) // per_col
+    fr = frame(g, min(batch, per_col) * h, cols * w, 1, dtype=in_dtype)
     ops = [{"kind": "cvt", "k": []}, {"kind": "mul", "k": [f32(g.uniform(0.5, 1.5))]},
            {"kind": "sub", "k": [f32(g.uniform(-1.0, 1.0))]}, {"kind": "div", "k": [f32(g.uniform(0.5, 1.5))]}]
     chain = {"read": {"kind": "plain", "dtype": in_dtype, "channels": 1, "out_w": 0, "out_h": 0},
              "ops": ops, "write": {"dtype": out_dtype, "layout": "packed"}}
-    items = [{"frame": 0, "x": 0, "y": b * h, "w": w, "h": h, "out_w": w, "out_h": h} for b in range(batch)]
+    items = [{"frame": 0, "x": (b // per_col) * w, "y": (b % per_col) * h, "w": w, "h": h, "out_w": w, "out_h": h}
+             for b in range(batch)]
     return {"frames": [fr], "items": items, "chain": chain, "seed": seed}
 
 
