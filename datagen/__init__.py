@@ -132,14 +132,17 @@ def loop_chain(pairs: int, g: np.random.Generator, channels: int = 1,
 
 
 def loop_batch(pairs: int, seed: int = 0, batch: int = 50, hw=(120, 60), channels: int = 1) -> dict:
-    """`batch` u8 images of hw (height, width) stacked in one frame, image b
-    in rows [b*h, (b+1)*h); one item per image; loop_chain(pairs)
+    """`batch` u8 images of hw (height, width) in one frame: columns of up
+    to 512 images stacked vertically (image b at column b // 512, rows
+    [(b % 512) h, (b % 512 + 1) h)); one item per image; loop_chain(pairs)
     (Section VI-D: batch 50 of 60 x 120 uchar images, Mul+Add pairs)."""
     g = rng(seed)
     h, w = hw
-    fr = frame(g, batch * h, w, channels)
-    items = [{"frame": 0, "x": 0, "y": b * h, "w": w, "h": h, "out_w": w, "out_h": h}
-             for b in range(batch)]
+    per_col = 512
+    cols = (batch + per_col - 1) // per_col
+    fr = frame(g, min(batch, per_col) * h, cols * w, channels)
+    items = [{"frame": 0, "x": (b // per_col) * w, "y": (b % per_col) * h, "w": w, "h": h,
+              "out_w": w, "out_h": h} for b in range(batch)]
     return {"frames": [fr], "items": items, "chain": loop_chain(pairs, g, channels), "seed": seed}
 
 

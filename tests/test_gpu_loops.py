@@ -68,7 +68,8 @@ def test_loop_batch_10000_pairs_sampled_items():
     fr = cfg["frames"][0].astype(np.float64)
     mp = m ** pairs
     for b, o in enumerate(outs):
-        x = fr[items[b]["y"]:items[b]["y"] + 120]
+        it = items[b]
+        x = fr[it["y"]:it["y"] + it["h"], it["x"]:it["x"] + it["w"]]
         exact = mp * x + a * (1 - mp) / (1 - m)
         assert np.all(np.abs(o - exact) <= 1e-5 * max(255.0, 1.0 / (1 - m)))
 
