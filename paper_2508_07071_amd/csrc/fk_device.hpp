@@ -962,6 +962,103 @@ __global__ __launch_bounds__(kMaxBlock) void k_transform(const KArgs a)
     }
 }
 
+// ------------------------------------------------- compile-time loop chain, per pixel --
+// For the compile-time loop chain (plain read, [cvt,] mul, add, loop(2, P),
+// packed fp32) with a long loop the arithmetic dwarfs the memory traffic,
+// and the 4-pixel unit leaves too few waves on small batches: 50 images of
+// 60x120 give 1,406 waves of 4-pixel lanes for 1,024 SIMDs, so the last
+// round runs 37% full.  This kernel gives each lane one pixel per round:
+// a tile is T*K pixels of one item in row-major order, lane t of round j
+// taking pixel j*T + t of the tile (5,625 waves for the same batch).
+// Loads are C elements per lane; stores are C nontemporal floats per lane,
+// consecutive across the wave.
+template <int DI, int C, bool Strict, int K>
+__global__ __launch_bounds__(kMaxBlock) void k_loop_px(const KArgs a)
+{
+    constexpr int ES = DSize<DI>::v;
+    const FK_CONST KArgs *ka = (const FK_CONST KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    const bool inl = a.inl_n > 0;
+    const bool compact = inl && a.inl_compact;
+    const FK_CONST uint32_t *tb =
+        inl ? (const FK_CONST uint32_t *)(ka->inl + kInlineTileBegin) : cptr(a.tile_begin);
+    const FK_CONST ItemRec *items = inl ? (const FK_CONST ItemRec *)ka->inl : cptr(a.items);
+    const int n_items = inl ? a.inl_n : cptr(a.hdr)->n_items;
+    const uint32_t total = inl ? a.inl_total_tiles : cptr(a.hdr)->total_tiles;
+    const int T = blockDim.x;
+    const int tid = threadIdx.x;
+    const uint32_t tile_px = (uint32_t)T * K;
+    const FK_CONST float *k = cptr(a.consts);
+    const float m = k[0];
+    const float ad = k[1];
+    const int n = a.loop_count;
+
+    for (uint32_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        int b;
+        ItemRec it;
+        uint32_t first_tile;
+        if (compact) {
+            b = (int)(tile / a.inl_tiles_per_item);
+            first_tile = (uint32_t)b * a.inl_tiles_per_item;
+            it = load_item(items);
+            const FK_CONST Roi16 *roi = (const FK_CONST Roi16 *)(ka->inl + 64) + b;
+            it.x = roi->x;
+            it.y = roi->y;
+            it.w = roi->w;
+            it.h = roi->h;
+            it.dst += (uint64_t)b * (uint64_t)a.inl_dst_stride;
+        } else {
+            b = find_item(tb, n_items, tile);
+            it = load_item(items + b);
+            first_tile = tb[b];
+        }
+        const uint32_t ow = (uint32_t)it.ow;
+        const uint32_t npx = ow * (uint32_t)it.oh;
+        const uint32_t pbase = (tile - first_tile) * tile_px;
+        gsrc_t src = (gsrc_t)it.src + (int64_t)it.x * (C * ES);
+        FK_GLOBAL float *dst = (FK_GLOBAL float *)(uintptr_t)it.dst;
+
+        float v[K][C];
+        uint32_t p[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            p[j] = pbase + (uint32_t)(j * T + tid);
+            if (p[j] < npx) {
+                const uint32_t row = p[j] / ow;
+                const uint32_t col = p[j] - row * ow;
+                gsrc_t e = src + (int64_t)(it.y + (int)row) * it.pitch + (int64_t)col * (C * ES);
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    v[j][c] = load_elem<DI>(e + c * ES);
+            } else {
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    v[j][c] = 0.0f;
+            }
+        }
+#pragma unroll 8
+        for (int q = 0; q < n; ++q) {
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    if constexpr (Strict) {
+                        const float t = v[j][c] * m;
+                        v[j][c] = t + ad;
+                    } else {
+                        v[j][c] = fmaf(v[j][c], m, ad);
+                    }
+                }
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (p[j] < npx) {
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    __builtin_nontemporal_store(v[j][c], dst + (size_t)p[j] * C + c);
+            }
+    }
+}
+
 // ------------------------------------------------------------- stats --
 // The reduction pattern (Section IV-C's second data-parallel pattern): the
 // same read and compute ops as the transform, then per channel min, max and

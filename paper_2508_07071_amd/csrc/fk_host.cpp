@@ -220,6 +220,9 @@ const void *fk::plan_kernel(const fk_plan *p, const fk_launch_config &cfg)
     case FAM_NORMALIZE: return kernel_normalize(cfg.coarsen, p->opts.strict_fp);
     case FAM_MULADD: return kernel_muladd(p->static_n, cfg.coarsen, p->opts.strict_fp);
     case FAM_MULADD_LOOP:
+        if (per_pixel(p))
+            return kernel_loop_px(p->chain.read.in_dtype, p->chain.read.channels, cfg.coarsen,
+                                  p->opts.strict_fp);
         return kernel_muladd_loop(p->chain.read.in_dtype, p->chain.read.channels, cfg.coarsen,
                                   p->opts.strict_fp);
     default:
@@ -228,9 +231,14 @@ const void *fk::plan_kernel(const fk_plan *p, const fk_launch_config &cfg)
     }
 }
 
+bool fk::per_pixel(const fk_plan *p)
+{
+    return p->family == FAM_MULADD_LOOP && p->static_n >= kLoopPxMinPairs;
+}
+
 size_t fk::lds_bytes(const fk_plan *p, const fk_launch_config &cfg)
 {
-    if (p->chain.write.layout != FK_PACKED)
+    if (p->chain.write.layout != FK_PACKED || per_pixel(p))
         return 0;
     const int ub = kUnitPx * p->chain.read.channels * dtype_size(p->chain.write.out_dtype);
     if (ub == 16 || ub == 8)
@@ -422,7 +430,9 @@ uint32_t fk::build_items(const fk_plan *p, const fk_item *items, int32_t n,
 {
     const int C = p->chain.read.channels;
     const int es_in = dtype_size(p->chain.read.in_dtype);
-    const uint64_t tile_units = (uint64_t)cfg.block_threads * cfg.coarsen;
+    // a per-pixel kernel's tile is T*K pixels: T*K/4 units of 4 pixels
+    const uint64_t tile_units = per_pixel(p) ? (uint64_t)cfg.block_threads * cfg.coarsen / kUnitPx
+                                             : (uint64_t)cfg.block_threads * cfg.coarsen;
     // stats write: an item's "tiles" are its blocks, at most slot_cap each
     const bool stats = p->chain.write.layout == FK_STATS;
     const uint64_t slot_cap =

@@ -139,6 +139,10 @@ const void *kernel_runtime(int read_kind, int in_dt, int channels, int out_dt, i
 const void *kernel_normalize(int coarsen, int strict);
 const void *kernel_muladd(int n_ops, int coarsen, int strict);
 const void *kernel_muladd_loop(int in_dt, int channels, int coarsen, int strict);
+const void *kernel_loop_px(int in_dt, int channels, int coarsen, int strict);
+// The compile-time loop chain runs per pixel (k_loop_px, a tile = T*K
+// pixels) from this many pairs on; shorter loops keep the 4-pixel unit.
+constexpr int kLoopPxMinPairs = 32;
 const void *kernel_stats(int read_kind, int in_dt, int channels, int coarsen);
 
 }  // namespace fk

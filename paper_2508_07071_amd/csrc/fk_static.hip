@@ -127,6 +127,35 @@ static const void *loop_k(int coarsen, int strict)
     return nullptr;
 }
 
+template <int DI, int C, bool Strict>
+static const void *loop_px_k(int coarsen)
+{
+    switch (coarsen) {
+    case 1: return (const void *)&k_loop_px<DI, C, Strict, 1>;
+    case 2: return (const void *)&k_loop_px<DI, C, Strict, 2>;
+    case 4: return (const void *)&k_loop_px<DI, C, Strict, 4>;
+    case 8: return (const void *)&k_loop_px<DI, C, Strict, 8>;
+    }
+    return nullptr;
+}
+
+template <int DI, int C>
+static const void *loop_px_s(int coarsen, int strict)
+{
+    return strict ? loop_px_k<DI, C, true>(coarsen) : loop_px_k<DI, C, false>(coarsen);
+}
+
+const void *kernel_loop_px(int in_dt, int channels, int coarsen, int strict)
+{
+    if (in_dt == DT_U8)
+        return channels == 1 ? loop_px_s<DT_U8, 1>(coarsen, strict)
+               : channels == 3 ? loop_px_s<DT_U8, 3>(coarsen, strict) : nullptr;
+    if (in_dt == DT_F32)
+        return channels == 1 ? loop_px_s<DT_F32, 1>(coarsen, strict)
+               : channels == 3 ? loop_px_s<DT_F32, 3>(coarsen, strict) : nullptr;
+    return nullptr;
+}
+
 const void *kernel_muladd_loop(int in_dt, int channels, int coarsen, int strict)
 {
     if (in_dt == DT_U8)
