@@ -125,6 +125,7 @@ __device__ __forceinline__ void store_elem<DT_F16>(gdst_t p, float v)
 template <int DT, int C>
 struct ReadPlain {
     static constexpr int kind = RD_PLAIN;
+    static constexpr int dtype = DT;
     static constexpr int elem_size = DSize<DT>::v;
     __device__ __forceinline__ static void load(const ItemRec &it, int oy, int ox0, int n,
                                                 float (&r)[kUnitPx][C])
@@ -1136,6 +1137,65 @@ __device__ __forceinline__ void block_reduce(StatAcc<C> &acc, StatPartial (*lds)
     __syncthreads();
 }
 
+// One tile of a plain read whose units are all whole and dword-aligned:
+// the K units' raw dwords are fetched first (K loads in flight per lane),
+// then each unit is unpacked, run through the ops and accumulated.
+template <class Read, class Compute, int C, int K>
+__device__ __forceinline__ void stats_tile_vec(const KArgs &a, const ItemRec &it, uint32_t ubase,
+                                               uint32_t units, uint32_t upr, int T, int tid,
+                                               bool swap, StatAcc<C> &acc)
+{
+    constexpr int DT = Read::dtype;
+    constexpr int NW = kUnitPx * C * DSize<DT>::v / 4;
+    uint32_t w[K][NW];
+    bool ok[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint32_t u = ubase + (uint32_t)(j * T + tid);
+        ok[j] = u < units;
+        if (ok[j]) {
+            const uint32_t row = u / upr;
+            const int ox0 = (int)(u - row * upr) * kUnitPx;
+            const FK_GLOBAL uint32_t *p =
+                (const FK_GLOBAL uint32_t *)((gsrc_t)it.src + (int64_t)(it.y + (int)row) * it.pitch +
+                                             (int64_t)(it.x + ox0) * (C * DSize<DT>::v));
+#pragma unroll
+            for (int i = 0; i < NW; ++i)
+                w[j][i] = p[i];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (!ok[j])
+            continue;
+        float v[1][kUnitPx][C];
+#pragma unroll
+        for (int i = 0; i < kUnitPx; ++i)
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                v[0][i][c] = unpack_elem<DT, NW>(w[j], i * C + c);
+        if constexpr (C >= 3) {
+            if (swap) {
+#pragma unroll
+                for (int i = 0; i < kUnitPx; ++i) {
+                    const float s = v[0][i][0];
+                    v[0][i][0] = v[0][i][2];
+                    v[0][i][2] = s;
+                }
+            }
+        }
+        Compute::template apply<1, C>(a, v);
+#pragma unroll
+        for (int i = 0; i < kUnitPx; ++i)
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                acc.mn[c] = fminf(acc.mn[c], v[0][i][c]);
+                acc.mx[c] = fmaxf(acc.mx[c], v[0][i][c]);
+                acc.sum[c] += (double)v[0][i][c];
+            }
+    }
+}
+
 template <class Read, class Compute, int C, int K>
 __global__ __launch_bounds__(kMaxBlock) void k_stats(const KArgs a)
 {
@@ -1191,6 +1251,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_stats(const KArgs a)
         // only one unit's values are live, whatever K
         for (uint32_t t = slot - first; t < item_tiles; t += nslots) {
             const uint32_t ubase = t * tile_units;
+            if constexpr (Read::kind == RD_PLAIN) {
+                // whole dword-aligned units everywhere in the item: a flag of
+                // the item, so the branch is uniform
+                if ((it.flags & IF_SRC_VEC) && it.ow % kUnitPx == 0) {
+                    stats_tile_vec<Read, Compute, C, K>(a, it, ubase, units, upr, T, tid, swap, acc);
+                    continue;
+                }
+            }
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 const uint32_t u = ubase + (uint32_t)(j * T + tid);
