@@ -10,9 +10,10 @@ GB in all, so the 256 MB Infinity Cache cannot hold the working set.
 
 Printed JSON line:
   value        algorithmic bytes of the step (5 x 124,416,000 B) / step time
-  roofline     the dominant kernel (the longest per step) against its bound;
-               its average duration comes from HIP events around each of its
-               launches inside the timed region
+  roofline     the dominant kernel (the 256-op launch, the longest of a
+               step) against its bound; its average duration comes from HIP
+               events around each of its launches inside the timed region
+               (the only events recorded there)
   per_depth    every depth's average kernel time, GB/s, fraction of HBM peak,
                and the unfused one-kernel-per-op baseline with the speedup
   cpu_baseline the CPU oracle (single thread) on a band of rows of the same
@@ -87,31 +88,44 @@ def vf_sweep(args):
         log(f"N={n}: config {best.block_threads}x{best.coarsen} static={tuned[n][2]}")
 
     counter = [0]
+    dom = DEPTHS[-1]  # the longest launch of a step (ALU-bound at 256 ops)
 
-    def step(events=None, i=0):
+    def step(events=None, i=0, only=None):
         for n in DEPTHS:
+            if only is not None and n != only:
+                continue
             r = counter[0] % R
             counter[0] += 1
-            if events is not None:
-                events[n][i][0].record()
+            timed = events is not None and (only is not None or n == dom)
+            if timed:
+                events[i][0].record()
             fk.fk_run(plans[n][0], items_by_set[n][r], 1, stream)
-            if events is not None:
-                events[n][i][1].record()
+            if timed:
+                events[i][1].record()
 
     for _ in range(args.warmup):
         step()
-    # timing events are created up front: none is created inside the timed loop
-    events = {n: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                  for _ in range(args.steps)] for n in DEPTHS}
+    # timing events are created up front: none is created inside the timed
+    # loop, and only the dominant kernel's launches are bracketed by events
+    dom_events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step(events, i)
+        step(dom_events, i)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    kern_ms = {n: float(np.mean([a.elapsed_time(b) for a, b in events[n]])) for n in DEPTHS}
-    log("kernel ms", {n: round(v, 4) for n, v in kern_ms.items()}, "step ms", round(ms_per_step, 4))
+    kern_ms = {dom: float(np.mean([a.elapsed_time(b) for a, b in dom_events]))}
+    # every other depth's launch time, outside the timed region
+    for n in DEPTHS[:-1]:
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        for i in range(args.steps):
+            step(ev, i, only=n)
+        torch.cuda.synchronize()
+        kern_ms[n] = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    log("kernel ms", {n: round(kern_ms[n], 4) for n in DEPTHS}, "step ms", round(ms_per_step, 4))
 
     # unfused baseline (outside the timed region): one kernel per op
     unfused_ms = {}
@@ -154,7 +168,6 @@ def vf_sweep(args):
             d["speedup_vs_unfused"] = round(unfused_ms[n] / kern_ms[n], 2)
         per_depth.append(d)
 
-    dom = max(DEPTHS, key=lambda n: kern_ms[n])
     n = dom
     flops = 2.0 * (n // 2) * in_bytes + (n % 2) * in_bytes
     alu_s = flops / (ALU_PEAK_TFLOPS * 1e12)
