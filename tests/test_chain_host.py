@@ -38,7 +38,10 @@ int main() {
         std::vector<float> k;
         int sn = 0;
         int fam = fk::match_static(&ch, k, sn);
-        std::printf("%d %zu %d %d %zu\n", swap, rec.size(), fam, sn, k.size());
+        double cnt[4];
+        fk::executed_counts(rec, cnt);
+        std::printf("%d %zu %d %d %zu %.0f %.0f %.0f %.0f\n", swap, rec.size(), fam, sn, k.size(), cnt[0],
+                    cnt[1], cnt[2], cnt[3]);
         for (auto &r : rec)
             std::printf("%d %a %a %a %a %a %a %a %a %d %d\n", r.code, r.a[0], r.a[1], r.a[2], r.a[3],
                         r.b[0], r.b[1], r.b[2], r.b[3], r.span, r.count);
@@ -76,7 +79,9 @@ def driver():
                                  check=True).stdout.split("\n")
             res, i = [], 0
             for _ in chains:
-                swap, n, fam, sn, nk = (int(v) for v in out[i].split())
+                f0 = out[i].split()
+                swap, n, fam, sn, nk = (int(v) for v in f0[:5])
+                executed = [float(v) for v in f0[5:9]]
                 i += 1
                 ops = []
                 for _ in range(n):
@@ -87,7 +92,7 @@ def driver():
                     i += 1
                 ks = [float.fromhex(out[i + j]) for j in range(nk)]
                 i += nk
-                res.append((swap, ops, fam, sn, ks))
+                res.append((swap, ops, fam, sn, ks, executed))
             return res
         yield run
 
@@ -166,12 +171,21 @@ def test_normalised_list_matches_oracle(driver, strict):
             fr = (g.uniform(-300, 300, size=(5, 7, C))).astype(np.float32)
         cases.append((ch, fr))
     outs = driver([(ch, strict) for ch, _ in cases])
-    for (ch, fr), (swap, ops, _, _, _) in zip(cases, outs):
+    for (ch, fr), (swap, ops, _, _, _, executed) in zip(cases, outs):
         C = ch["read"]["channels"]
         n_arith = sum(o["kind"] in ("mul", "add", "sub", "div") for o in ch["ops"])
         n_loops = sum(o["kind"] == "loop" for o in ch["ops"])
         assert len(ops) <= n_arith + n_loops and (not strict or len(ops) == n_arith + n_loops)
         assert all(op[0] != OPC_FMA for op in ops) or not strict
+        # ops the chain executes (loops unrolled) = records run, before contraction
+        runs = [1] * len(ch["ops"])
+        for i, o in enumerate(ch["ops"]):
+            if o["kind"] == "loop":
+                for j in range(i - o["span"], i):
+                    runs[j] = o["count"]
+        n_exec = sum(r for o, r in zip(ch["ops"], runs) if o["kind"] in ("mul", "add", "sub", "div"))
+        fma = executed[3]
+        assert sum(executed) + fma == n_exec and (not strict or fma == 0)
         n_swaps = sum(o["kind"] == "swap" for o in ch["ops"])
         assert swap == (n_swaps % 2 if C >= 3 else 0)
         got = evaluate(fr, C, swap, ops)
@@ -190,7 +204,7 @@ def test_contraction_pairs_mul_then_add_only(driver):
                   {"kind": "add", "k": [4.0]}, {"kind": "mul", "k": [3.0]},
                   {"kind": "cvt", "k": []}, {"kind": "add", "k": [0.5]},
                   {"kind": "mul", "k": [5.0]}, {"kind": "div", "k": [2.0]}]}
-    (swap, ops, fam, _, _), = driver([(ch, False)])
+    (swap, ops, fam, _, _, _), = driver([(ch, False)])
     codes = [op[0] for op in ops]
     # mul,sub -> fma(2,-k); add stays; mul,(cvt),add -> fma; mul; div
     assert codes == [OPC_FMA, OPC_ADD, OPC_FMA, OPC_MUL, OPC_DIV]
