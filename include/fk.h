@@ -65,10 +65,10 @@ typedef int32_t fk_status;
  * skipped; all NaN gives +inf / -inf); the sum accumulates the values in
  * fp64 (in an order that depends on the launch configuration, within
  * 2 (n - 1) 2^-53 sum|x| of any other order); mean = sum / n in fp64.
- * Requires out_dtype = FK_F64; dst must be 8-byte aligned.  One plan runs
- * one stats launch at a time (per-item completion counters live in the
- * plan); launches of one plan on one stream are ordered, so that holds
- * unless the caller overlaps streams. */
+ * Requires out_dtype = FK_F64; dst must be 8-byte aligned.  A run is two
+ * launches on the caller's stream (block partials, then one combine block
+ * per item); the partials live in the plan, so runs of one plan must not
+ * overlap on different streams. */
 #define FK_STATS 2
 
 /* Read operations (Section IV-B).

@@ -1065,14 +1065,15 @@ __global__ __launch_bounds__(kMaxBlock) void k_loop_px(const KArgs a)
 // same read and compute ops as the transform, then per channel min, max and
 // an fp64 sum of the item's values, from one read of the source.
 //
-// A batch slot (item) is covered by `nslots` blocks; block slot s strides
-// over the item's tiles s, s + nslots, ...  Each block reduces its values
-// in a fixed order (lane order within a wave by xor-shuffles, then waves in
-// order), stores one StatPartial per channel, and takes a ticket on the
-// item's counter; the block drawing the last ticket combines the item's
-// partials in slot order, writes {min, max, sum, mean} and resets the
-// counter to zero for the next launch.  No block waits for another, so
-// every block finishes whatever the scheduling.
+// Two kernels.  k_stats: a batch slot (item) is covered by `nslots` blocks;
+// block slot s strides over the item's tiles s, s + nslots, ...; each block
+// reduces its values in a fixed order (lane order within a wave by
+// xor-shuffles, then waves in order) and stores one StatPartial per
+// channel.  k_stats_final: one block per item combines the item's partials
+// in slot order and writes {min, max, sum, mean}.  The kernel boundary
+// orders the partials' stores before their loads, so no block needs a
+// device-scope fence (on a multi-XCD part each such fence writes back the
+// XCD's L2).
 
 template <int C>
 struct StatAcc {
@@ -1200,7 +1201,6 @@ template <class Read, class Compute, int C, int K>
 __global__ __launch_bounds__(kMaxBlock) void k_stats(const KArgs a)
 {
     __shared__ StatPartial red[kMaxBlock / kWave][C];
-    __shared__ uint32_t ticket;
     const FK_CONST KArgs *ka = (const FK_CONST KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
     const bool inl = a.inl_n > 0;
     const bool compact = inl && a.inl_compact;
@@ -1298,42 +1298,68 @@ __global__ __launch_bounds__(kMaxBlock) void k_stats(const KArgs a)
 #pragma unroll
             for (int c = 0; c < C; ++c)
                 a.st_part[(size_t)slot * C + c] = StatPartial{acc.mn[c], acc.mx[c], acc.sum[c]};
-            __threadfence();  // release the partial before the ticket
-            ticket = atomicAdd(&a.st_done[b], 1u);
+        }
+        __syncthreads();  // `red` is reused by the next slot
+    }
+}
+
+// One block per item: the item's partials, combined in slot order.
+template <int C>
+__global__ __launch_bounds__(kMaxBlock) void k_stats_final(const KArgs a)
+{
+    __shared__ StatPartial red[kMaxBlock / kWave][C];
+    const FK_CONST KArgs *ka = (const FK_CONST KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    const bool inl = a.inl_n > 0;
+    const bool compact = inl && a.inl_compact;
+    const FK_CONST uint32_t *tb =
+        inl ? (const FK_CONST uint32_t *)(ka->inl + kInlineTileBegin) : cptr(a.tile_begin);
+    const FK_CONST ItemRec *items = inl ? (const FK_CONST ItemRec *)ka->inl : cptr(a.items);
+    const int n_items = inl ? a.inl_n : cptr(a.hdr)->n_items;
+    const int T = blockDim.x;
+    const int tid = threadIdx.x;
+    for (int b = blockIdx.x; b < n_items; b += gridDim.x) {
+        uint32_t first, nslots;
+        uint64_t dst;
+        int ow, oh;
+        if (compact) {
+            const ItemRec t = load_item(items);
+            first = (uint32_t)b * a.inl_tiles_per_item;
+            nslots = a.inl_tiles_per_item;
+            dst = t.dst + (uint64_t)b * (uint64_t)a.inl_dst_stride;
+            ow = t.ow;  // one output size for the whole compact batch
+            oh = t.oh;
+        } else {
+            const ItemRec t = load_item(items + b);
+            first = tb[b];
+            nslots = tb[b + 1] - first;
+            dst = t.dst;
+            ow = t.ow;
+            oh = t.oh;
+        }
+        StatAcc<C> fin;
+        fin.init();
+        for (uint32_t s = (uint32_t)tid; s < nslots; s += (uint32_t)T) {
+            const StatPartial *q = a.st_part + (size_t)(first + s) * C;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                fin.mn[c] = fminf(fin.mn[c], q[c].mn);
+                fin.mx[c] = fmaxf(fin.mx[c], q[c].mx);
+                fin.sum[c] += q[c].sum;
+            }
+        }
+        block_reduce<C>(fin, red, tid, T);
+        if (tid == 0) {
+            FK_GLOBAL double *out = (FK_GLOBAL double *)(uintptr_t)dst;
+            const double n = (double)ow * (double)oh;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                out[4 * c + 0] = (double)fin.mn[c];
+                out[4 * c + 1] = (double)fin.mx[c];
+                out[4 * c + 2] = fin.sum[c];
+                out[4 * c + 3] = fin.sum[c] / n;
+            }
         }
         __syncthreads();
-        if (ticket == nslots - 1) {  // block-uniform: this block finishes the item
-            __threadfence();          // acquire every other block's partial
-            StatAcc<C> fin;
-            fin.init();
-            for (uint32_t s = (uint32_t)tid; s < nslots; s += (uint32_t)T) {
-                const StatPartial *q = a.st_part + (size_t)(first + s) * C;
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    // atomic loads: vector memory at device scope, never the scalar cache
-                    const float mn = __hip_atomic_load(&q[c].mn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    const float mx = __hip_atomic_load(&q[c].mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    const double sm = __hip_atomic_load(&q[c].sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    fin.mn[c] = fminf(fin.mn[c], mn);
-                    fin.mx[c] = fmaxf(fin.mx[c], mx);
-                    fin.sum[c] += sm;
-                }
-            }
-            block_reduce<C>(fin, red, tid, T);
-            if (tid == 0) {
-                double *out = (double *)(uintptr_t)it.dst;
-                const double n = (double)it.ow * (double)it.oh;
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    out[4 * c + 0] = (double)fin.mn[c];
-                    out[4 * c + 1] = (double)fin.mx[c];
-                    out[4 * c + 2] = fin.sum[c];
-                    out[4 * c + 3] = fin.sum[c] / n;
-                }
-                __hip_atomic_store(&a.st_done[b], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-        __syncthreads();  // `ticket` and `red` are reused by the next slot
     }
 }
 

@@ -271,8 +271,6 @@ static void plan_free(fk_plan *p)
         (void)hipFree(p->d_consts);
     if (p->d_st_part)
         (void)hipFree(p->d_st_part);
-    if (p->d_st_done)
-        (void)hipFree(p->d_st_done);
     if (p->capture_stream)
         (void)hipStreamDestroy(p->capture_stream);
     if (p->tune_stream)
@@ -344,15 +342,10 @@ extern "C" fk_status fk_plan_create(const fk_chain_desc *chain, int32_t max_batc
                               hipMemcpyHostToDevice);
         }
         if (e == hipSuccess && stats) {
-            // partials for every slot of a full batch, and counters that the
-            // kernel returns to zero after each item
+            // partials for every slot of a full batch
             p->st_capacity = (uint32_t)std::min<int64_t>((int64_t)max_batch * kStatSlots, kStatCapacity);
             e = hipMalloc(&p->d_st_part, (size_t)p->st_capacity * chain->read.channels *
                                              sizeof(StatPartial));
-            if (e == hipSuccess)
-                e = hipMalloc(&p->d_st_done, sizeof(uint32_t) * (size_t)max_batch);
-            if (e == hipSuccess)
-                e = hipMemset(p->d_st_done, 0, sizeof(uint32_t) * (size_t)max_batch);
         }
         p->table_bytes = sizeof(RunHeader) + sizeof(ItemRec) * (size_t)max_batch +
                          sizeof(uint32_t) * ((size_t)max_batch + 1);
@@ -507,7 +500,6 @@ KArgs fk::make_args(const fk_plan *p, void *d_table)
     a.strict = p->opts.strict_fp;
     a.loop_count = p->family == FAM_MULADD_LOOP ? p->static_n : 0;
     a.st_part = p->d_st_part;
-    a.st_done = p->d_st_done;
     return a;
 }
 
@@ -518,8 +510,10 @@ uint32_t fk::persistent_grid(const fk_plan *p, const fk_launch_config &cfg)
     return (uint32_t)p->num_cus * per_cu;
 }
 
+// The plan's kernel over `grid` blocks; a stats write then launches its
+// combine kernel (one block per item, same arguments) on the same stream.
 fk_status fk::launch_args(const fk_plan *p, const fk_launch_config &cfg, KArgs &a, uint32_t grid,
-                          hipStream_t stream)
+                          int32_t n_items, hipStream_t stream)
 {
     const void *fn = plan_kernel(p, cfg);
     if (!fn)
@@ -527,16 +521,22 @@ fk_status fk::launch_args(const fk_plan *p, const fk_launch_config &cfg, KArgs &
     void *args[] = {&a};
     hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(cfg.block_threads), args,
                                    lds_bytes(p, cfg), stream);
+    if (e == hipSuccess && p->chain.write.layout == FK_STATS) {
+        const void *fin = kernel_stats_final(p->chain.read.channels);
+        if (!fin)
+            return set_error(FK_ERR_UNSUPPORTED, "no stats combine kernel");
+        e = hipLaunchKernel(fin, dim3((unsigned)n_items), dim3(256), args, 0, stream);
+    }
     if (e != hipSuccess)
         return hip_error(e, "hipLaunchKernel");
     return FK_OK;
 }
 
 fk_status fk::launch(const fk_plan *p, const fk_launch_config &cfg, void *d_table, uint32_t grid,
-                     hipStream_t stream)
+                     int32_t n_items, hipStream_t stream)
 {
     KArgs a = make_args(p, d_table);
-    return launch_args(p, cfg, a, grid, stream);
+    return launch_args(p, cfg, a, grid, n_items, stream);
 }
 
 // A batch that can travel in the compact kernel-argument form: one frame,
@@ -577,7 +577,7 @@ fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_la
         a.inl_total_tiles = build_items(p, items, n, cfg, (ItemRec *)a.inl,
                                         (uint32_t *)(a.inl + kInlineTileBegin));
         const uint32_t grid = std::min<uint32_t>(a.inl_total_tiles, 1u << 20);
-        return launch_args(p, cfg, a, grid, stream);
+        return launch_args(p, cfg, a, grid, n, stream);
     }
     if (!graph && n <= kCompactItems && compact_batch(p, items, n)) {
         KArgs a = make_args(p, nullptr);
@@ -603,7 +603,7 @@ fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_la
             roi[b] = Roi16{(uint16_t)items[b].x, (uint16_t)items[b].y, (uint16_t)items[b].w,
                            (uint16_t)items[b].h};
         const uint32_t grid = std::min<uint32_t>(a.inl_total_tiles, 1u << 20);
-        return launch_args(p, cfg, a, grid, stream);
+        return launch_args(p, cfg, a, grid, n, stream);
     }
     fk_plan::Slot &sl = p->slots[p->next_slot];
     p->next_slot = (p->next_slot + 1) % fk_plan::kRing;
@@ -651,7 +651,8 @@ fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_la
                                p->capture_stream);
             fk_status s = FK_OK;
             if (e == hipSuccess)
-                s = launch(p, cfg, sl.d_table, persistent_grid(p, cfg), p->capture_stream);
+                s = launch(p, cfg, sl.d_table, persistent_grid(p, cfg), std::min(p->max_batch, 4096),
+                           p->capture_stream);
             hipError_t e2 = hipStreamEndCapture(p->capture_stream, &g);
             if (e != hipSuccess)
                 return hip_error(e, "hipMemcpyAsync (capture)");
@@ -673,7 +674,7 @@ fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_la
         if (e != hipSuccess)
             return hip_error(e, "hipMemcpyAsync");
         const uint32_t grid = std::min<uint32_t>(tiles, 1u << 20);
-        fk_status s = launch(p, cfg, sl.d_table, grid, stream);
+        fk_status s = launch(p, cfg, sl.d_table, grid, n, stream);
         if (s)
             return s;
     }

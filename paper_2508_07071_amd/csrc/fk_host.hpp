@@ -32,7 +32,6 @@ struct fk_plan {
     void *d_ops = nullptr;
     void *d_consts = nullptr;
     fk::StatPartial *d_st_part = nullptr;  // stats write: block partials
-    uint32_t *d_st_done = nullptr;         // stats write: per-slot counters (zero at rest)
     uint32_t st_capacity = 0;              // stats write: partial slots held
     size_t table_bytes = 0;
     Slot slots[kRing];
@@ -60,10 +59,10 @@ uint32_t build_table(const fk_plan *p, const fk_item *items, int32_t n, const fk
                      void *stage);
 KArgs make_args(const fk_plan *p, void *d_table);
 uint32_t persistent_grid(const fk_plan *p, const fk_launch_config &cfg);
-fk_status launch_args(const fk_plan *p, const fk_launch_config &cfg, KArgs &a, uint32_t grid,
+fk_status launch_args(const fk_plan *p, const fk_launch_config &cfg, KArgs &a, uint32_t grid, int32_t n_items,
                       hipStream_t stream);
 fk_status launch(const fk_plan *p, const fk_launch_config &cfg, void *d_table, uint32_t grid,
-                 hipStream_t stream);
+                 int32_t n_items, hipStream_t stream);
 bool compact_batch(const fk_plan *p, const fk_item *items, int32_t n);
 fk_status run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_launch_config &cfg,
                     bool graph, hipStream_t stream);

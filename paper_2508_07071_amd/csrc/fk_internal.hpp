@@ -94,7 +94,7 @@ struct StatPartial {    // 16 bytes
 
 // Stats write: a batch slot's output is covered by at most kStatSlots
 // blocks (each striding over the item's tiles); each leaves one partial per
-// channel, and the last block to finish combines them.
+// channel, and a second kernel combines each item's partials.
 constexpr int kStatSlots = 512;
 // Partials a stats plan holds (slots over a whole batch); a batch of n
 // items gives each at most kStatCapacity / n slots.
@@ -119,7 +119,6 @@ struct KArgs {
     uint32_t inl_tiles_per_item;  // compact form
     int64_t inl_dst_stride;       // compact form: bytes between item outputs
     StatPartial *st_part;  // stats write: one partial per (slot, channel)
-    uint32_t *st_done;     // stats write: finished slots per batch slot
     alignas(16) uint8_t inl[kInlineBytes];
 };
 
@@ -144,5 +143,6 @@ const void *kernel_loop_px(int in_dt, int channels, int coarsen, int strict);
 // pixels) from this many pairs on; shorter loops keep the 4-pixel unit.
 constexpr int kLoopPxMinPairs = 32;
 const void *kernel_stats(int read_kind, int in_dt, int channels, int coarsen);
+const void *kernel_stats_final(int channels);
 
 }  // namespace fk

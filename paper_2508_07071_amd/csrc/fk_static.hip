@@ -20,6 +20,16 @@ const void *kernel_runtime_nearest_f16(int, int, int, int);
 const void *kernel_runtime_nearest_f32(int, int, int, int);
 const void *kernel_runtime_nv12(int, int, int, int, int);
 
+const void *kernel_stats_final(int channels)
+{
+    switch (channels) {
+    case 1: return (const void *)&k_stats_final<1>;
+    case 3: return (const void *)&k_stats_final<3>;
+    case 4: return (const void *)&k_stats_final<4>;
+    }
+    return nullptr;
+}
+
 const void *kernel_stats(int read_kind, int in_dt, int channels, int coarsen)
 {
     if (read_kind == RD_PLAIN)

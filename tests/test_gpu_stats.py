@@ -132,8 +132,8 @@ def test_many_items_compact_and_table_paths():
 
 
 def test_repeat_runs_and_graph_replays_are_identical():
-    """The per-item counters return to zero after each launch: repeated
-    eager runs and graph replays give the same bits as the first run."""
+    """Repeated eager runs and graph replays (partials and combine captured
+    together) give the same bits as the first run."""
     say("stats: repeats and graph replays")
     cfg = datagen.config2(40, seed=5)
     ch = cfg["chain"]
