@@ -11,9 +11,10 @@ GB in all, so the 256 MB Infinity Cache cannot hold the working set.
 Printed JSON line:
   value        algorithmic bytes of the step (5 x 124,416,000 B) / step time
   roofline     the dominant kernel (the 256-op launch, the longest of a
-               step) against its bound; its average duration comes from HIP
-               events around each of its launches inside the timed region
-               (the only events recorded there)
+               step) against its bound; its average duration comes from the
+               HIP event pair each of its launches records inside the timed
+               region as its kernel starts and ends (fk_run_timed; the only
+               events recorded there)
   per_depth    every depth's average kernel time, GB/s, fraction of HBM peak,
                and the unfused one-kernel-per-op baseline with the speedup
   cpu_baseline the CPU oracle (single thread) on a band of rows of the same
@@ -98,17 +99,26 @@ def vf_sweep(args):
             counter[0] += 1
             timed = events is not None and (only is not None or n == dom)
             if timed:
-                events[i][0].record()
-            fk.fk_run(plans[n][0], items_by_set[n][r], 1, stream)
-            if timed:
-                events[i][1].record()
+                # the launch itself records the pair as its kernel starts and
+                # ends (no separate event markers in the stream)
+                fk.fk_run_timed(plans[n][0], items_by_set[n][r], 1, stream,
+                                events[i][0].cuda_event, events[i][1].cuda_event)
+            else:
+                fk.fk_run(plans[n][0], items_by_set[n][r], 1, stream)
+
+    def make_events(k):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(k)]
+        for a, b in ev:  # materialise the HIP events (outside any timed region)
+            a.record()
+            b.record()
+        torch.cuda.synchronize()
+        return ev
 
     for _ in range(args.warmup):
         step()
     # timing events are created up front: none is created inside the timed
-    # loop, and only the dominant kernel's launches are bracketed by events
-    dom_events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                  for _ in range(args.steps)]
+    # loop, and only the dominant kernel's launches carry them
+    dom_events = make_events(args.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -119,8 +129,7 @@ def vf_sweep(args):
     kern_ms = {dom: float(np.mean([a.elapsed_time(b) for a, b in dom_events]))}
     # every other depth's launch time, outside the timed region
     for n in DEPTHS[:-1]:
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
+        ev = make_events(args.steps)
         for i in range(args.steps):
             step(ev, i, only=n)
         torch.cuda.synchronize()

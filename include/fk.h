@@ -240,6 +240,16 @@ fk_status fk_plan_get_tier(const fk_plan *plan, int32_t *is_static);
  * before the call returns. */
 fk_status fk_run(fk_plan *plan, const fk_item *items, int32_t n_items, void *stream);
 
+/* fk_run with the launch's device time: `start_event` and `stop_event`
+ * (hipEvent_t, created with timing enabled by the caller, who owns them)
+ * are recorded by the fused launch itself as its kernel starts and ends
+ * (hipExtLaunchKernel), so hipEventElapsedTime gives the kernel's
+ * duration without the latency of separate event markers.  A stats write
+ * brackets both of its kernels; a plan that replays a graph records the
+ * events around the graph launch.  Either event may be NULL. */
+fk_status fk_run_timed(fk_plan *plan, const fk_item *items, int32_t n_items, void *stream,
+                       void *start_event, void *stop_event);
+
 /* Bytes of device scratch fk_run_unfused needs for these items. */
 fk_status fk_unfused_scratch_bytes(const fk_plan *plan, const fk_item *items, int32_t n_items,
                                    int64_t *bytes);

@@ -159,6 +159,7 @@ def lib():
         "fk_plan_set_config": ([P, C.POINTER(fk_launch_config)], C.c_int32),
         "fk_plan_get_tier": ([P, C.POINTER(C.c_int32)], C.c_int32),
         "fk_run": ([P, C.POINTER(fk_item), C.c_int32, P], C.c_int32),
+        "fk_run_timed": ([P, C.POINTER(fk_item), C.c_int32, P, P, P], C.c_int32),
         "fk_unfused_scratch_bytes": ([P, C.POINTER(fk_item), C.c_int32, C.POINTER(C.c_int64)],
                                      C.c_int32),
         "fk_run_unfused": ([P, C.POINTER(fk_item), C.c_int32, P, C.c_int64, P], C.c_int32),
@@ -202,7 +203,7 @@ def lib():
 EXPORTS = [
     "fk_status_string", "fk_last_error", "fk_version", "fk_chain_validate", "fk_items_validate",
     "fk_plan_create", "fk_plan_destroy", "fk_plan_get_config", "fk_plan_set_config",
-    "fk_plan_get_tier", "fk_run", "fk_unfused_scratch_bytes", "fk_run_unfused",
+    "fk_plan_get_tier", "fk_run", "fk_run_timed", "fk_unfused_scratch_bytes", "fk_run_unfused",
     "fk_autotune_space", "fk_autotune",
     "fk_model_create", "fk_model_destroy", "fk_model_param_count", "fk_model_get_params",
     "fk_model_set_params", "fk_model_get_normalization", "fk_model_set_normalization",
@@ -340,6 +341,12 @@ def fk_plan_get_tier(plan: int) -> int:
 
 def fk_run(plan: int, items, n: int, stream: int) -> None:
     check(lib().fk_run(plan, items, n, stream))
+
+
+def fk_run_timed(plan: int, items, n: int, stream: int, start_event: int, stop_event: int) -> None:
+    """fk_run whose launch records the two hipEvent_t handles (e.g. a
+    torch.cuda.Event's ``cuda_event``) as its kernel starts and ends."""
+    check(lib().fk_run_timed(plan, items, n, stream, start_event, stop_event))
 
 
 def fk_unfused_scratch_bytes(plan: int, items, n: int) -> int:

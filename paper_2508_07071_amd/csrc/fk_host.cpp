@@ -3,6 +3,7 @@
 // computed on the host once per plan and per run, then the fused kernel is
 // launched), batch tables (BatchRead parameter arrays, Section IV-B), the
 // hipGraph replay path and the launch-configuration autotuner.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -512,20 +513,33 @@ uint32_t fk::persistent_grid(const fk_plan *p, const fk_launch_config &cfg)
 
 // The plan's kernel over `grid` blocks; a stats write then launches its
 // combine kernel (one block per item, same arguments) on the same stream.
+// The plan's kernel over `grid` blocks; a stats write then launches its
+// combine kernel (one block per item, same arguments) on the same stream.
+// Given events, the launches record them as the first kernel starts and
+// the last one ends.
+static hipError_t launch_one(const void *fn, dim3 grid, dim3 block, void **args, size_t lds,
+                             hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1)
+{
+    if (!ev0 && !ev1)
+        return hipLaunchKernel(fn, grid, block, args, lds, stream);
+    return hipExtLaunchKernel(fn, grid, block, args, lds, stream, ev0, ev1, 0);
+}
+
 fk_status fk::launch_args(const fk_plan *p, const fk_launch_config &cfg, KArgs &a, uint32_t grid,
-                          int32_t n_items, hipStream_t stream)
+                          int32_t n_items, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1)
 {
     const void *fn = plan_kernel(p, cfg);
     if (!fn)
         return set_error(FK_ERR_UNSUPPORTED, "no kernel for coarsening %d", cfg.coarsen);
+    const bool stats = p->chain.write.layout == FK_STATS;
     void *args[] = {&a};
-    hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(cfg.block_threads), args,
-                                   lds_bytes(p, cfg), stream);
-    if (e == hipSuccess && p->chain.write.layout == FK_STATS) {
+    hipError_t e = launch_one(fn, dim3(grid), dim3(cfg.block_threads), args, lds_bytes(p, cfg),
+                              stream, ev0, stats ? nullptr : ev1);
+    if (e == hipSuccess && stats) {
         const void *fin = kernel_stats_final(p->chain.read.channels);
         if (!fin)
             return set_error(FK_ERR_UNSUPPORTED, "no stats combine kernel");
-        e = hipLaunchKernel(fin, dim3((unsigned)n_items), dim3(256), args, 0, stream);
+        e = launch_one(fin, dim3((unsigned)n_items), dim3(256), args, 0, stream, nullptr, ev1);
     }
     if (e != hipSuccess)
         return hip_error(e, "hipLaunchKernel");
@@ -533,10 +547,10 @@ fk_status fk::launch_args(const fk_plan *p, const fk_launch_config &cfg, KArgs &
 }
 
 fk_status fk::launch(const fk_plan *p, const fk_launch_config &cfg, void *d_table, uint32_t grid,
-                     int32_t n_items, hipStream_t stream)
+                     int32_t n_items, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1)
 {
     KArgs a = make_args(p, d_table);
-    return launch_args(p, cfg, a, grid, n_items, stream);
+    return launch_args(p, cfg, a, grid, n_items, stream, ev0, ev1);
 }
 
 // A batch that can travel in the compact kernel-argument form: one frame,
@@ -565,7 +579,7 @@ bool fk::compact_batch(const fk_plan *p, const fk_item *items, int32_t n)
 }
 
 fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_launch_config &cfg,
-                        bool graph, hipStream_t stream)
+                        bool graph, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (!graph && n <= kInlineItems) {
         // small batch: the parameters travel in the kernel arguments
@@ -577,7 +591,7 @@ fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_la
         a.inl_total_tiles = build_items(p, items, n, cfg, (ItemRec *)a.inl,
                                         (uint32_t *)(a.inl + kInlineTileBegin));
         const uint32_t grid = std::min<uint32_t>(a.inl_total_tiles, 1u << 20);
-        return launch_args(p, cfg, a, grid, n, stream);
+        return launch_args(p, cfg, a, grid, n, stream, ev0, ev1);
     }
     if (!graph && n <= kCompactItems && compact_batch(p, items, n)) {
         KArgs a = make_args(p, nullptr);
@@ -603,7 +617,7 @@ fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_la
             roi[b] = Roi16{(uint16_t)items[b].x, (uint16_t)items[b].y, (uint16_t)items[b].w,
                            (uint16_t)items[b].h};
         const uint32_t grid = std::min<uint32_t>(a.inl_total_tiles, 1u << 20);
-        return launch_args(p, cfg, a, grid, n, stream);
+        return launch_args(p, cfg, a, grid, n, stream, ev0, ev1);
     }
     fk_plan::Slot &sl = p->slots[p->next_slot];
     p->next_slot = (p->next_slot + 1) % fk_plan::kRing;
@@ -666,7 +680,12 @@ fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_la
                 return hip_error(e, "hipGraphInstantiate");
             sl.gcfg = cfg;
         }
-        e = hipGraphLaunch(sl.gexec, stream);
+        if (ev0)
+            e = hipEventRecord(ev0, stream);
+        if (e == hipSuccess)
+            e = hipGraphLaunch(sl.gexec, stream);
+        if (e == hipSuccess && ev1)
+            e = hipEventRecord(ev1, stream);
         if (e != hipSuccess)
             return hip_error(e, "hipGraphLaunch");
     } else {
@@ -674,7 +693,7 @@ fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_la
         if (e != hipSuccess)
             return hip_error(e, "hipMemcpyAsync");
         const uint32_t grid = std::min<uint32_t>(tiles, 1u << 20);
-        fk_status s = launch(p, cfg, sl.d_table, grid, n, stream);
+        fk_status s = launch(p, cfg, sl.d_table, grid, n, stream, ev0, ev1);
         if (s)
             return s;
     }
@@ -698,6 +717,25 @@ extern "C" fk_status fk_run(fk_plan *plan, const fk_item *items, int32_t n_items
             return s;
         return run_fused(plan, items, n_items, plan->cfg, plan->opts.use_graph != 0,
                          (hipStream_t)stream);
+    } catch (...) {
+        return set_error(FK_ERR_INVALID_ARG, "exception");
+    }
+}
+
+extern "C" fk_status fk_run_timed(fk_plan *plan, const fk_item *items, int32_t n_items,
+                                  void *stream, void *start_event, void *stop_event)
+{
+    try {
+        if (!plan)
+            return set_error(FK_ERR_INVALID_ARG, "plan is null");
+        if (n_items < 1 || n_items > plan->max_batch)
+            return set_error(FK_ERR_INVALID_ARG, "n_items %d outside 1..max_batch (%d)", n_items,
+                             plan->max_batch);
+        fk_status s = validate_items(&plan->chain, items, n_items);
+        if (s)
+            return s;
+        return run_fused(plan, items, n_items, plan->cfg, plan->opts.use_graph != 0,
+                         (hipStream_t)stream, (hipEvent_t)start_event, (hipEvent_t)stop_event);
     } catch (...) {
         return set_error(FK_ERR_INVALID_ARG, "exception");
     }

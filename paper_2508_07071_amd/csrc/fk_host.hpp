@@ -60,11 +60,12 @@ uint32_t build_table(const fk_plan *p, const fk_item *items, int32_t n, const fk
 KArgs make_args(const fk_plan *p, void *d_table);
 uint32_t persistent_grid(const fk_plan *p, const fk_launch_config &cfg);
 fk_status launch_args(const fk_plan *p, const fk_launch_config &cfg, KArgs &a, uint32_t grid, int32_t n_items,
-                      hipStream_t stream);
+                      hipStream_t stream, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 fk_status launch(const fk_plan *p, const fk_launch_config &cfg, void *d_table, uint32_t grid,
-                 int32_t n_items, hipStream_t stream);
+                 int32_t n_items, hipStream_t stream, hipEvent_t ev0 = nullptr,
+                 hipEvent_t ev1 = nullptr);
 bool compact_batch(const fk_plan *p, const fk_item *items, int32_t n);
 fk_status run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_launch_config &cfg,
-                    bool graph, hipStream_t stream);
+                    bool graph, hipStream_t stream, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 }  // namespace fk

@@ -370,3 +370,30 @@ def test_compact_argument_batches_match_table_path_and_oracle():
     refs = oracle.run_chain(chain, [fr], items)
     for k in range(40):
         assert_bitexact(o[k], refs[k]["out"], f"plain item {k}")
+
+
+# ------------------------------------------------------- timed launches --
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_timed_run_matches_run_and_records_its_kernel(graph):
+    """fk_run_timed gives fk_run's bits and a positive kernel duration from
+    the events its launch records (a graph plan records them around the
+    graph launch)."""
+    say("timed run, graph =", graph)
+    cfg = datagen.config1(256, seed=2, frame_hw=(270, 480))
+    dframes = to_dev(cfg["frames"])
+    with Plan(cfg["chain"], 1, use_graph=graph) as p:
+        ref = host(p.run(dframes, cfg["items"]))[0]
+        outs = alloc_outs(cfg["chain"], cfg["items"])
+        arr = fk.make_items(cfg["chain"], dframes, cfg["items"], outs)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        e1.record()
+        torch.cuda.synchronize()
+        fk.fk_run_timed(p.h, arr, 1, fk.stream_handle(), e0.cuda_event, e1.cuda_event)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        got = host(outs)[0]
+    assert_bitexact(got, ref, "timed vs plain run")
+    assert 0.0 < ms < 50.0
