@@ -877,7 +877,7 @@ def main():
                     help="autotune each depth's launch config first (default: the library default)")
     ap.add_argument("--no-unfused", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=540)
+    ap.add_argument("--cpu-rows", type=int, default=2160)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

@@ -612,6 +612,17 @@ struct StaticCompute {
     }
 };
 
+// A uniform value held in a VGPR.  A VOP3 instruction reads at most one
+// SGPR on this architecture, so an FMA with two uniform operands needs one
+// of them in a VGPR; left to itself the compiler re-copies it inside hot
+// loops.
+__device__ __forceinline__ float in_vgpr(float x)
+{
+    float r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+}
+
 // Compile-time loop chain: one Mul and one Add (scalar constants, loaded
 // once) applied loop_count times; the body is compiled, the trip count is
 // a kernel argument, so code size does not grow with the count.
@@ -622,9 +633,9 @@ struct LoopMulAddCompute {
     {
         const FK_CONST float *k = cptr(a.consts);
         const float m = k[0];
-        const float ad = k[1];
+        const float ad = in_vgpr(k[1]);
         const int n = a.loop_count;
-#pragma unroll 8
+#pragma unroll 32
         for (int p = 0; p < n; ++p) {
 #pragma unroll
             for (int j = 0; j < K; ++j)
@@ -990,7 +1001,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_loop_px(const KArgs a)
     const uint32_t tile_px = (uint32_t)T * K;
     const FK_CONST float *k = cptr(a.consts);
     const float m = k[0];
-    const float ad = k[1];
+    const float ad = in_vgpr(k[1]);
     const int n = a.loop_count;
 
     for (uint32_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
@@ -1036,7 +1047,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_loop_px(const KArgs a)
                     v[j][c] = 0.0f;
             }
         }
-#pragma unroll 8
+#pragma unroll 32
         for (int q = 0; q < n; ++q) {
 #pragma unroll
             for (int j = 0; j < K; ++j)
