@@ -120,7 +120,7 @@ def label(n, seed=0, reps=3, log_every=250, start=0):
 
 def load_shards(paths):
     """Concatenate label shards (ordered by their start index)."""
-    parts = sorted((dict(np.load(p)) for p in paths), key=lambda d: int(d.get("start", 0)))
+    parts = sorted((dict(np.load(p, allow_pickle=False)) for p in paths), key=lambda d: int(d.get("start", 0)))
     out = {}
     for k in ("features", "times_ms", "default_idx", "meta"):
         out[k] = np.concatenate([d[k] for d in parts])
@@ -187,6 +187,9 @@ def main():
     a.add_argument("--reps", type=int, default=3)
     a.add_argument("--start", type=int, default=0)
     a.add_argument("--out", required=True)
+    m = sub.add_parser("merge", help="concatenate label shards into one dataset file")
+    m.add_argument("--data", required=True, nargs="+")
+    m.add_argument("--out", required=True)
     b = sub.add_parser("fit")
     b.add_argument("--data", required=True, nargs="+", help="one or more label shards, in order")
     b.add_argument("--model", default=None)
@@ -200,6 +203,11 @@ def main():
         d["start"] = np.array(args.start)
         np.savez_compressed(args.out, **d)
         print(f"[label] wrote {args.out}", flush=True)
+    elif args.cmd == "merge":
+        d = load_shards(args.data)
+        d["start"] = np.array(0)
+        np.savez_compressed(args.out, **d)
+        print(f"[merge] {d['features'].shape[0]} chains -> {args.out}", flush=True)
     else:
         import paper_2508_07071_amd as fk
         data = load_shards(args.data)
