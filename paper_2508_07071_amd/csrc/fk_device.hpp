@@ -859,6 +859,26 @@ __device__ __forceinline__ ItemRec load_item(const FK_CONST ItemRec *p)
     return it;
 }
 
+// Row of index u (a unit or a pixel) for d indices per row: a
+// double-precision reciprocal estimate, within one of the quotient (u <
+// 2^28, a 53-bit product), corrected by exact 32-bit products ((q + 1) * d
+// <= u + 2d < 2^29 for d < 2^16).  Cheaper than a 32-bit integer
+// division; the reciprocal is taken once per tile.
+struct RowDiv {
+    uint32_t upr;
+    double rcp;
+    __device__ __forceinline__ explicit RowDiv(uint32_t d) : upr(d), rcp(1.0 / (double)d) {}
+    __device__ __forceinline__ uint32_t operator()(uint32_t u) const
+    {
+        uint32_t q = (uint32_t)((double)u * rcp);
+        if ((q + 1) * upr <= u)
+            ++q;
+        else if (q * upr > u)
+            --q;
+        return q;
+    }
+};
+
 // Batch slot owning a tile: the last item whose first tile is <= tile.
 __device__ __forceinline__ int find_item(const FK_CONST uint32_t *tb, int n_items, uint32_t tile)
 {
@@ -924,6 +944,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_transform(const KArgs a)
         const uint32_t upr = (uint32_t)(it.ow + kUnitPx - 1) / kUnitPx;
         const uint32_t units = upr * (uint32_t)it.oh;
         const uint32_t ubase = (tile - first_tile) * tile_units;
+        const RowDiv rowdiv(upr);
 
         float v[K][kUnitPx][C];
         int oy[K], ox0[K], nv[K];
@@ -931,7 +952,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_transform(const KArgs a)
         for (int j = 0; j < K; ++j) {
             const uint32_t u = ubase + (uint32_t)(j * T + tid);
             if (u < units) {
-                const uint32_t row = u / upr;
+                const uint32_t row = rowdiv(u);
                 oy[j] = (int)row;
                 ox0[j] = (int)(u - row * upr) * kUnitPx;
                 const int left = it.ow - ox0[j];
@@ -1026,6 +1047,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_loop_px(const KArgs a)
         const uint32_t ow = (uint32_t)it.ow;
         const uint32_t npx = ow * (uint32_t)it.oh;
         const uint32_t pbase = (tile - first_tile) * tile_px;
+        const RowDiv rowdiv(ow);  // pixel p < 2^28 in a row of ow <= 65535 pixels
         gsrc_t src = (gsrc_t)it.src + (int64_t)it.x * (C * ES);
         FK_GLOBAL float *dst = (FK_GLOBAL float *)(uintptr_t)it.dst;
 
@@ -1035,7 +1057,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_loop_px(const KArgs a)
         for (int j = 0; j < K; ++j) {
             p[j] = pbase + (uint32_t)(j * T + tid);
             if (p[j] < npx) {
-                const uint32_t row = p[j] / ow;
+                const uint32_t row = rowdiv(p[j]);
                 const uint32_t col = p[j] - row * ow;
                 gsrc_t e = src + (int64_t)(it.y + (int)row) * it.pitch + (int64_t)col * (C * ES);
 #pragma unroll
@@ -1154,7 +1176,7 @@ __device__ __forceinline__ void block_reduce(StatAcc<C> &acc, StatPartial (*lds)
 // then each unit is unpacked, run through the ops and accumulated.
 template <class Read, class Compute, int C, int K>
 __device__ __forceinline__ void stats_tile_vec(const KArgs &a, const ItemRec &it, uint32_t ubase,
-                                               uint32_t units, uint32_t upr, int T, int tid,
+                                               uint32_t units, const RowDiv &rowdiv, int T, int tid,
                                                bool swap, StatAcc<C> &acc)
 {
     constexpr int DT = Read::dtype;
@@ -1166,8 +1188,8 @@ __device__ __forceinline__ void stats_tile_vec(const KArgs &a, const ItemRec &it
         const uint32_t u = ubase + (uint32_t)(j * T + tid);
         ok[j] = u < units;
         if (ok[j]) {
-            const uint32_t row = u / upr;
-            const int ox0 = (int)(u - row * upr) * kUnitPx;
+            const uint32_t row = rowdiv(u);
+            const int ox0 = (int)(u - row * rowdiv.upr) * kUnitPx;
             const FK_GLOBAL uint32_t *p =
                 (const FK_GLOBAL uint32_t *)((gsrc_t)it.src + (int64_t)(it.y + (int)row) * it.pitch +
                                              (int64_t)(it.x + ox0) * (C * DSize<DT>::v));
@@ -1255,6 +1277,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_stats(const KArgs a)
         const uint32_t upr = (uint32_t)(it.ow + kUnitPx - 1) / kUnitPx;
         const uint32_t units = upr * (uint32_t)it.oh;
         const uint32_t item_tiles = (units + tile_units - 1) / tile_units;
+        const RowDiv rowdiv(upr);
 
         StatAcc<C> acc;
         acc.init();
@@ -1266,7 +1289,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_stats(const KArgs a)
                 // whole dword-aligned units everywhere in the item: a flag of
                 // the item, so the branch is uniform
                 if ((it.flags & IF_SRC_VEC) && it.ow % kUnitPx == 0) {
-                    stats_tile_vec<Read, Compute, C, K>(a, it, ubase, units, upr, T, tid, swap, acc);
+                    stats_tile_vec<Read, Compute, C, K>(a, it, ubase, units, rowdiv, T, tid, swap, acc);
                     continue;
                 }
             }
@@ -1275,7 +1298,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_stats(const KArgs a)
                 const uint32_t u = ubase + (uint32_t)(j * T + tid);
                 if (u >= units)
                     continue;
-                const uint32_t row = u / upr;
+                const uint32_t row = rowdiv(u);
                 const int ox0 = (int)(u - row * upr) * kUnitPx;
                 const int left = it.ow - ox0;
                 const int nv = left < kUnitPx ? left : kUnitPx;
