@@ -161,3 +161,27 @@ def test_unfused_stats_match_oracle():
         outs = host(p.run_unfused(dframes, cfg["items"]))
     for b, o in enumerate(outs):
         check(o, st[b], ims[b], True, f"unfused item {b}")
+
+
+def test_timed_stats_run_brackets_both_kernels():
+    """fk_run_timed on a stats plan: the same results as fk_run, and an
+    elapsed time from the first kernel's start to the combine's end."""
+    say("stats: timed run")
+    cfg = datagen.config2(12, seed=8)
+    ch = stats_of(cfg["chain"])
+    dframes = to_dev(cfg["frames"])
+    with Plan(ch, 12) as p:
+        ref = host(p.run(dframes, cfg["items"]))
+        outs = [torch.full((3, 4), float("nan"), dtype=torch.float64, device="cuda:0") for _ in range(12)]
+        arr = fk.make_items(ch, dframes, cfg["items"], outs)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        e1.record()
+        torch.cuda.synchronize()
+        fk.fk_run_timed(p.h, arr, 12, fk.stream_handle(), e0.cuda_event, e1.cuda_event)
+        torch.cuda.synchronize()
+        assert 0.0 < e0.elapsed_time(e1) < 50.0
+        got = host(outs)
+    for a, b in zip(got, ref):
+        np.testing.assert_array_equal(a, b)
