@@ -578,18 +578,21 @@ def stats_workload(args):
 
 DATA_SIZES = [100, 1000, 10000, 100000, 282370, 1000000, 4000000, 9032740, 16654030]
 HF_PLAIN_BATCHES = [1, 10, 50, 100, 300, 600, 1191]
+IPO_SIZES = [1, 5, 10, 25, 50, 100, 250, 500]
 DTYPE_PAIRS = [("u8", "f32"), ("u8", "f16"), ("f16", "f32"), ("f16", "f16"), ("f32", "f32"), ("f32", "f16")]
 
 
 def sweeps_workload(args):
-    """The paper's parameter sweeps on this library (Sections VI-C, VI-G,
-    VI-I), fused vs the unfused one-kernel-per-op baseline:
+    """The paper's parameter sweeps on this library (Sections VI-C, VI-E,
+    VI-G, VI-I), fused vs the unfused one-kernel-per-op baseline:
       data_size: 1-D fp32 arrays of N values (rows of 4096 above 4096), 100
                  Mul+Add pairs through the loop op, no batch;
       hf_plain:  B single-channel 60x120 u8 images, Read -> Cast -> Mul ->
                  Sub -> Div -> Write, one batched launch vs one launch per
                  image vs unfused;
-      dtypes:    the same chain at B = 50 for six input -> output types."""
+      dtypes:    the same chain at B = 50 for six input -> output types;
+      instructions_per_op: 500 multiplications as ops of M instructions
+                 over 66,355,200 fp32 values, fused vs one kernel per op."""
     import numpy as np
     import torch
 
@@ -664,6 +667,26 @@ def sweeps_workload(args):
         fk.fk_plan_destroy(plan)
         log("dtypes", r)
         dtypes.append(r)
+    # Section VI-E: 500 fp32 multiplications split into ops of M instructions
+    # over 66,355,200 values (the paper's 259,200 blocks of 256 threads):
+    # one fused kernel vs the unfused baseline with one kernel per op, each
+    # applying its multiplication M times
+    per_op = []
+    for M in IPO_SIZES:
+        cfg = datagen.instructions_per_op_case(M, n_elems=66355200, seed=args.seed)
+        ch = cfg["chain"]
+        frame = torch.from_numpy(cfg["frames"][0]).to(dev)
+        out = torch.empty(fk.out_shape(ch, cfg["items"][0]), dtype=torch.float32, device=dev)
+        arr = fk.make_items(ch, [frame], cfg["items"], [out])
+        plan = fk.fk_plan_create(fk.chain_desc(ch), 1, fk.plan_opts(unfused_loop_kernel=True))
+        r = {"per_op": M, "ops": -(-500 // M), "fused_ms": round(timeit(lambda: fk.fk_run(plan, arr, 1, stream), 10), 4)}
+        if not args.no_unfused:
+            r["unfused_ms"] = round(unfused_ms(plan, arr, 1, 2), 4)
+            r["speedup"] = round(r["unfused_ms"] / r["fused_ms"], 2)
+        fk.fk_plan_destroy(plan)
+        del frame, out
+        log("instructions_per_op", r)
+        per_op.append(r)
     top = data_size[-1]
     n = top["n"]
     flops = 2.0 * 100 * n
@@ -675,7 +698,7 @@ def sweeps_workload(args):
             "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": round(tf / ALU_PEAK_TFLOPS, 4), "traffic": None,
                          "kernel": f"fused 100 mul+add pairs over {n} fp32 values", "kernel_ms": top["fused_ms"]},
-            "data_size": data_size, "hf_plain": hf_plain, "dtypes": dtypes}
+            "data_size": data_size, "hf_plain": hf_plain, "dtypes": dtypes, "instructions_per_op": per_op}
 
 
 def reads_workload(args):

@@ -164,6 +164,29 @@ def data_size_case(n_elems: int, pairs: int = 100, seed: int = 0, row: int = 409
     return {"frames": [fr], "items": [whole_frame_item(fr)], "chain": chain, "seed": seed}
 
 
+def instructions_per_op_case(per_op: int, total: int = 500, n_elems: int = 1 << 16, seed: int = 0,
+                             row: int = 4096) -> dict:
+    """Section VI-E: `total` fp32 multiplications split into ops of
+    `per_op` instructions each (the last op takes the remainder), as a
+    chain of Mul ops each looped `per_op` times, over a 1-D fp32 array held
+    as rows of `row` values.  Multiplier uniform in [0.999, 1.001) (drawn
+    after the values), so 500 products stay within a factor of two."""
+    g = rng(seed)
+    h = max(1, n_elems // row)
+    fr = frame(g, h, min(n_elems, row), 1, dtype="f32")
+    m = f32(g.uniform(0.999, 1.001))
+    ops, left = [], total
+    while left > 0:
+        k = min(per_op, left)
+        ops.append({"kind": "mul", "k": [m]})
+        if k > 1:
+            ops.append({"kind": "loop", "span": 1, "count": int(k)})
+        left -= k
+    chain = {"read": {"kind": "plain", "dtype": "f32", "channels": 1, "out_w": 0, "out_h": 0},
+             "ops": ops, "write": {"dtype": "f32", "layout": "packed"}}
+    return {"frames": [fr], "items": [whole_frame_item(fr)], "chain": chain, "seed": seed}
+
+
 def cast_chain_batch(batch: int = 50, in_dtype: str = "u8", out_dtype: str = "f32", seed: int = 0,
                      hw=(120, 60)) -> dict:
     """Sections VI-C and VI-I: `batch` single-channel images of hw (height,

@@ -197,6 +197,10 @@ typedef struct {
                                 per-op definition; 0: a multiply followed by an
                                 add/sub is one fused multiply-add */
     int32_t tier;            /* FK_TIER_* */
+    int32_t unfused_loop_kernel; /* fk_run_unfused only: 1 = a loop over a single
+                                    op is one kernel applying it loop_count times
+                                    (an op of that many instructions, Section
+                                    VI-E); 0 = one kernel per run of the op */
 } fk_plan_opts;
 
 typedef struct fk_plan fk_plan;

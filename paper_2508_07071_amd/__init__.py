@@ -84,7 +84,7 @@ class fk_launch_config(C.Structure):
 
 class fk_plan_opts(C.Structure):
     _fields_ = [("config_source", C.c_int32), ("manual", fk_launch_config), ("use_graph", C.c_int32),
-                ("strict_fp", C.c_int32), ("tier", C.c_int32)]
+                ("strict_fp", C.c_int32), ("tier", C.c_int32), ("unfused_loop_kernel", C.c_int32)]
 
 
 class fk_crop(C.Structure):
@@ -563,11 +563,12 @@ def output_offsets(chain: dict, crops) -> list:
 
 
 def plan_opts(config_source=FK_CONFIG_DEFAULT, manual=(256, 1), use_graph=False, strict=False,
-              tier=FK_TIER_AUTO) -> fk_plan_opts:
+              tier=FK_TIER_AUTO, unfused_loop_kernel=False) -> fk_plan_opts:
     o = fk_plan_opts()
     o.config_source = config_source
     o.manual.block_threads, o.manual.coarsen = manual
     o.use_graph = int(bool(use_graph))
     o.strict_fp = int(bool(strict))
     o.tier = tier
+    o.unfused_loop_kernel = int(bool(unfused_loop_kernel))
     return o

@@ -657,9 +657,10 @@ struct LoopMulAddCompute {
 // ------------------------------------------------------ run-time ops --
 // The op list is uniform across the grid: each op is one scalar branch and
 // its constants come through the scalar cache, then applied to all
-// K * 4 * C values of the thread's tile.  A LOOP record jumps back over its
-// body until the body has run `count` times (bodies hold no loops, so one
-// counter serves every loop of the list).
+// K * 4 * C values of the thread's tile.  A LOOP record over one record
+// makes that record run `count` times in a register loop; a longer LOOP
+// jumps back over its body until the body has run `count` times (bodies
+// hold no loops, so one counter serves every loop of the list).
 struct RuntimeCompute {
     template <int K, int C>
     __device__ __forceinline__ static void apply(const KArgs &a, float (&v)[K][kUnitPx][C])
@@ -669,6 +670,8 @@ struct RuntimeCompute {
         for (int o = 0; o < a.n_ops; ++o) {
             const int code = ops[o].code;
             if (code == OPC_LOOP) {
+                if (ops[o].span == 1)
+                    continue;  // already run by its one-record body, below
                 if (runs < ops[o].count) {
                     ++runs;
                     o -= ops[o].span + 1;  // the loop's ++o lands on the body's first record
@@ -677,6 +680,11 @@ struct RuntimeCompute {
                 }
                 continue;
             }
+            // a record followed by a one-record LOOP runs `count` times here,
+            // in a register loop with its constants loaded once
+            int reps = 1;
+            if (o + 1 < a.n_ops && ops[o + 1].code == OPC_LOOP && ops[o + 1].span == 1)
+                reps = ops[o + 1].count;
             float ka[C], kb[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) {
@@ -684,37 +692,41 @@ struct RuntimeCompute {
                 kb[c] = ops[o].b[c];
             }
             if (code == OPC_FMA) {
+                for (int r = 0; r < reps; ++r)
 #pragma unroll
-                for (int j = 0; j < K; ++j)
+                    for (int j = 0; j < K; ++j)
 #pragma unroll
-                    for (int i = 0; i < kUnitPx; ++i)
+                        for (int i = 0; i < kUnitPx; ++i)
 #pragma unroll
-                        for (int c = 0; c < C; ++c)
-                            v[j][i][c] = fmaf(v[j][i][c], ka[c], kb[c]);
+                            for (int c = 0; c < C; ++c)
+                                v[j][i][c] = fmaf(v[j][i][c], ka[c], kb[c]);
             } else if (code == OPC_MUL) {
+                for (int r = 0; r < reps; ++r)
 #pragma unroll
-                for (int j = 0; j < K; ++j)
+                    for (int j = 0; j < K; ++j)
 #pragma unroll
-                    for (int i = 0; i < kUnitPx; ++i)
+                        for (int i = 0; i < kUnitPx; ++i)
 #pragma unroll
-                        for (int c = 0; c < C; ++c)
-                            v[j][i][c] = v[j][i][c] * ka[c];
+                            for (int c = 0; c < C; ++c)
+                                v[j][i][c] = v[j][i][c] * ka[c];
             } else if (code == OPC_ADD) {
+                for (int r = 0; r < reps; ++r)
 #pragma unroll
-                for (int j = 0; j < K; ++j)
+                    for (int j = 0; j < K; ++j)
 #pragma unroll
-                    for (int i = 0; i < kUnitPx; ++i)
+                        for (int i = 0; i < kUnitPx; ++i)
 #pragma unroll
-                        for (int c = 0; c < C; ++c)
-                            v[j][i][c] = v[j][i][c] + ka[c];
+                            for (int c = 0; c < C; ++c)
+                                v[j][i][c] = v[j][i][c] + ka[c];
             } else {
+                for (int r = 0; r < reps; ++r)
 #pragma unroll
-                for (int j = 0; j < K; ++j)
+                    for (int j = 0; j < K; ++j)
 #pragma unroll
-                    for (int i = 0; i < kUnitPx; ++i)
+                        for (int i = 0; i < kUnitPx; ++i)
 #pragma unroll
-                        for (int c = 0; c < C; ++c)
-                            v[j][i][c] = v[j][i][c] / ka[c];
+                            for (int c = 0; c < C; ++c)
+                                v[j][i][c] = v[j][i][c] / ka[c];
             }
         }
     }

@@ -298,7 +298,7 @@ extern "C" fk_status fk_plan_create(const fk_chain_desc *chain, int32_t max_batc
         const bool stats = chain->write.layout == FK_STATS;
         if (stats && max_batch > kStatCapacity)
             return set_error(FK_ERR_UNSUPPORTED, "stats write: max_batch above %d", kStatCapacity);
-        fk_plan_opts o = {FK_CONFIG_DEFAULT, kDefaultConfig, 0, 0, FK_TIER_AUTO};
+        fk_plan_opts o = {FK_CONFIG_DEFAULT, kDefaultConfig, 0, 0, FK_TIER_AUTO, 0};
         if (opts)
             o = *opts;
         if (o.config_source == FK_CONFIG_MANUAL && !config_valid(o.manual))

@@ -97,27 +97,28 @@ __global__ __launch_bounds__(kUnfusedBlock) void k_nv12(const uint8_t *frame, in
 
 // One elementwise op over a packed image of n elements: TIn -> fp32.
 // code: -1 cvt (copy), OPC_MUL, OPC_ADD (SUB arrives as ADD of -k), OPC_DIV.
+// (`reps` > 1: the op applied that many times in one kernel -- an op of
+// `reps` instructions.)
 template <int DT>
 __global__ __launch_bounds__(kUnfusedBlock) void k_elem(const uint8_t *src, float *dst, int64_t n,
                                                        int C, int code, float k0, float k1, float k2,
-                                                       float k3)
+                                                       float k3, int reps)
 {
     gsrc_t s = (gsrc_t)src;
     FK_GLOBAL float *d = (FK_GLOBAL float *)dst;
     const float kk[4] = {k0, k1, k2, k3};
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const float v = uload<DT>(s, e);
+        float r = uload<DT>(s, e);
         const float k = kk[(int)(e % C)];
-        float r;
-        if (code == OPC_MUL)
-            r = v * k;
-        else if (code == OPC_ADD)
-            r = v + k;
-        else if (code == OPC_DIV)
-            r = v / k;
-        else
-            r = v;
+        for (int q = 0; q < reps; ++q) {
+            if (code == OPC_MUL)
+                r = r * k;
+            else if (code == OPC_ADD)
+                r = r + k;
+            else if (code == OPC_DIV)
+                r = r / k;
+        }
         d[e] = r;
     }
 }
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(kUnfusedBlock) void k_elem(const uint8_t *src, floa
 template <int DT>
 __global__ __launch_bounds__(kUnfusedBlock) void k_elem4(const uint8_t *src, float *dst, int64_t n4,
                                                         int C, int code, float k0, float k1,
-                                                        float k2, float k3)
+                                                        float k2, float k3, int reps)
 {
     const float kk[4] = {k0, k1, k2, k3};
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n4;
@@ -150,16 +151,22 @@ __global__ __launch_bounds__(kUnfusedBlock) void k_elem4(const uint8_t *src, flo
                 v[t] = w[t];
         }
         int c = (int)((uint64_t)(4 * q) % (uint64_t)C);
+        float kt[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const float k = kk[c];
-            if (code == OPC_MUL)
-                v[t] = v[t] * k;
-            else if (code == OPC_ADD)
-                v[t] = v[t] + k;
-            else if (code == OPC_DIV)
-                v[t] = v[t] / k;
+            kt[t] = kk[c];
             c = c + 1 == C ? 0 : c + 1;
+        }
+        for (int r = 0; r < reps; ++r) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (code == OPC_MUL)
+                    v[t] = v[t] * kt[t];
+                else if (code == OPC_ADD)
+                    v[t] = v[t] + kt[t];
+                else if (code == OPC_DIV)
+                    v[t] = v[t] / kt[t];
+            }
         }
         store_nt((gdst_t)(dst + 4 * q), fx4{v[0], v[1], v[2], v[3]});
     }
@@ -329,27 +336,27 @@ static ScratchPlan scratch_for(const fk_plan *p, const fk_item &it)
 
 template <int DT>
 static void launch_elem(const void *src, float *dst, int64_t n, int C, int code, const float *k,
-                        hipStream_t st)
+                        int reps, hipStream_t st)
 {
     const uintptr_t need = DT == DT_U8 ? 4 : DT == DT_F16 ? 8 : 16;
     if (n % 4 == 0 && (uintptr_t)src % need == 0 && (uintptr_t)dst % 16 == 0) {
         k_elem4<DT><<<grid_for(n / 4), kUnfusedBlock, 0, st>>>((const uint8_t *)src, dst, n / 4, C,
-                                                              code, k[0], k[1], k[2], k[3]);
+                                                              code, k[0], k[1], k[2], k[3], reps);
         return;
     }
     k_elem<DT><<<grid_for(n), kUnfusedBlock, 0, st>>>((const uint8_t *)src, dst, n, C, code, k[0],
-                                                      k[1], k[2], k[3]);
+                                                      k[1], k[2], k[3], reps);
 }
 
 static void elem_any(int dt, const void *src, float *dst, int64_t n, int C, int code,
-                     const float *k, hipStream_t st)
+                     const float *k, int reps, hipStream_t st)
 {
     if (dt == DT_U8)
-        launch_elem<DT_U8>(src, dst, n, C, code, k, st);
+        launch_elem<DT_U8>(src, dst, n, C, code, k, reps, st);
     else if (dt == DT_F16)
-        launch_elem<DT_F16>(src, dst, n, C, code, k, st);
+        launch_elem<DT_F16>(src, dst, n, C, code, k, reps, st);
     else
-        launch_elem<DT_F32>(src, dst, n, C, code, k, st);
+        launch_elem<DT_F32>(src, dst, n, C, code, k, reps, st);
 }
 
 static void swap_any(int dt, const void *src, float *dst, int64_t npix, int C, hipStream_t st)
@@ -446,16 +453,25 @@ static fk_status run_item_unfused(const fk_plan *p, const fk_item &it, uint8_t *
         cur_dt = DT_F32;
     }
     const bool direct = p->chain.write.layout == FK_PACKED && p->chain.write.out_dtype == FK_F32;
-    // one kernel per op as the chain executes: a loop's body once per run
-    std::vector<int> seq;
+    // one kernel per op as the chain executes: a loop's body once per run;
+    // with unfused_loop_kernel, a loop over one op is that op's kernel
+    // applying it loop_count times
+    std::vector<int> seq, reps;
     for (int i = 0; i < p->chain.n_ops; ++i) {
         const fk_op_desc &d = p->chain.ops[i];
         if (d.kind == FK_OP_LOOP) {
+            if (p->opts.unfused_loop_kernel && d.loop_span == 1) {
+                reps.back() = d.loop_count;  // the body: the entry just pushed
+                continue;
+            }
             for (int r = 1; r < d.loop_count; ++r)
-                for (int j = i - d.loop_span; j < i; ++j)
+                for (int j = i - d.loop_span; j < i; ++j) {
                     seq.push_back(j);
+                    reps.push_back(1);
+                }
         } else if (d.kind != FK_OP_SWAP_RB || C >= 3) {  // a 1-channel swap is no kernel
             seq.push_back(i);
+            reps.push_back(1);
         }
     }
     for (size_t s = 0; s < seq.size(); ++s) {
@@ -482,7 +498,7 @@ static fk_status run_item_unfused(const fk_plan *p, const fk_item &it, uint8_t *
             } else if (d.kind == FK_OP_DIV) {
                 code = OPC_DIV;
             }
-            elem_any(cur_dt, cur, o, npix * C, C, code, k, st);
+            elem_any(cur_dt, cur, o, npix * C, C, code, k, reps[s], st);
         }
         cur = o;
         cur_dt = DT_F32;

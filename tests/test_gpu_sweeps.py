@@ -52,3 +52,23 @@ def test_plain_batch_1191_images_sampled():
     say("plain-read batch 1191")
     cfg = datagen.cast_chain_batch(1191, seed=4)
     both_modes(cfg, "B=1191", sample=[0, 1, 500, 1189, 1190])
+
+
+@pytest.mark.parametrize("per_op", [1, 7, 100, 500])
+def test_instructions_per_op_fused_and_one_kernel_per_op(per_op):
+    """500 multiplications as ops of `per_op` instructions (looped Mul ops):
+    the fused run matches the oracle bit for bit, and so does the unfused
+    baseline in both of its loop forms (one kernel per looped op, or one
+    kernel per multiplication)."""
+    say("instructions per op", per_op)
+    cfg = datagen.instructions_per_op_case(per_op, n_elems=3 * 4096 + 4096, seed=per_op)
+    ref = oracle.run_chain(cfg["chain"], cfg["frames"], cfg["items"])[0]["out"]
+    dframes = to_dev(cfg["frames"])
+    for one_kernel in (True, False):
+        if not one_kernel and per_op > 100:
+            continue  # 500 launches: covered by the smaller cases
+        with Plan(cfg["chain"], 1, strict=True, unfused_loop_kernel=one_kernel) as p:
+            fused = host(p.run(dframes, cfg["items"]))[0]
+            unfused = host(p.run_unfused(dframes, cfg["items"]))[0]
+        assert_bitexact(fused, ref, f"fused per_op={per_op}")
+        assert_bitexact(unfused, ref, f"unfused per_op={per_op} one_kernel={one_kernel}")
