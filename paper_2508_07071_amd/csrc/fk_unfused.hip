@@ -111,12 +111,14 @@ __global__ __launch_bounds__(kUnfusedBlock) void k_elem(const uint8_t *src, floa
          e += (int64_t)gridDim.x * blockDim.x) {
         float r = uload<DT>(s, e);
         const float k = kk[(int)(e % C)];
-        for (int q = 0; q < reps; ++q) {
-            if (code == OPC_MUL)
+        if (code == OPC_MUL) {
+            for (int q = 0; q < reps; ++q)
                 r = r * k;
-            else if (code == OPC_ADD)
+        } else if (code == OPC_ADD) {
+            for (int q = 0; q < reps; ++q)
                 r = r + k;
-            else if (code == OPC_DIV)
+        } else if (code == OPC_DIV) {
+            for (int q = 0; q < reps; ++q)
                 r = r / k;
         }
         d[e] = r;
@@ -157,16 +159,22 @@ __global__ __launch_bounds__(kUnfusedBlock) void k_elem4(const uint8_t *src, flo
             kt[t] = kk[c];
             c = c + 1 == C ? 0 : c + 1;
         }
-        for (int r = 0; r < reps; ++r) {
+        // the op's branch outside its repetitions (uniform across the grid)
+        if (code == OPC_MUL) {
+            for (int r = 0; r < reps; ++r)
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                if (code == OPC_MUL)
+                for (int t = 0; t < 4; ++t)
                     v[t] = v[t] * kt[t];
-                else if (code == OPC_ADD)
+        } else if (code == OPC_ADD) {
+            for (int r = 0; r < reps; ++r)
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
                     v[t] = v[t] + kt[t];
-                else if (code == OPC_DIV)
+        } else if (code == OPC_DIV) {
+            for (int r = 0; r < reps; ++r)
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
                     v[t] = v[t] / kt[t];
-            }
         }
         store_nt((gdst_t)(dst + 4 * q), fx4{v[0], v[1], v[2], v[3]});
     }
