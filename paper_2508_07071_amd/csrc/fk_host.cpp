@@ -517,8 +517,6 @@ uint32_t fk::persistent_grid(const fk_plan *p, const fk_launch_config &cfg)
 
 // The plan's kernel over `grid` blocks; a stats write then launches its
 // combine kernel (one block per item, same arguments) on the same stream.
-// The plan's kernel over `grid` blocks; a stats write then launches its
-// combine kernel (one block per item, same arguments) on the same stream.
 // Given events, the launches record them as the first kernel starts and
 // the last one ends.
 static hipError_t launch_one(const void *fn, dim3 grid, dim3 block, void **args, size_t lds,
