@@ -1242,6 +1242,180 @@ __device__ __forceinline__ void stats_tile_vec(const KArgs &a, const ItemRec &it
     }
 }
 
+// Statistics of u8 values with no arithmetic after the cast, in integer
+// registers.  A unit's C dwords hold its 4C bytes; byte k of dword i is
+// channel (4i + k) % C.  Sums: a dot product of each dword with a 0/1 byte
+// mask per channel (one v_dot4_u32_u8 adds up to four bytes).  Min/max: a
+// dword's even and odd bytes, spread over two 16-bit halves, go through
+// packed 16-bit min/max, so one instruction covers two bytes.  The results
+// equal the fp32/fp64 path's exactly: the values are integers in [0, 255]
+// and every partial sum is an integer below 2^53.
+typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+
+template <int C>
+struct U8Acc {
+    uint32_t s[C];       // per channel; moved into the fp64 sums after each tile
+    us2 mx[C][2], mn[C][2];  // [dword][parity]: halves hold bytes p and p + 2
+
+    static constexpr uint32_t mask(int i, int c)
+    {
+        uint32_t m = 0;
+        for (int k = 0; k < 4; ++k)
+            if ((4 * i + k) % C == c)
+                m |= 1u << (8 * k);
+        return m;
+    }
+    __device__ __forceinline__ void init()
+    {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            s[c] = 0;
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                // neutral here because every value lies in [0, 255]
+                mx[c][p] = us2{0, 0};
+                mn[c][p] = us2{255, 255};
+            }
+        }
+    }
+    __device__ __forceinline__ void add(const uint32_t (&w)[C])
+    {
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (mask(i, c) != 0)  // constant once unrolled
+                    s[c] = __builtin_amdgcn_udot4(w[i], mask(i, c), s[c], false);
+            const us2 even = __builtin_bit_cast(us2, w[i] & 0x00ff00ffu);
+            const us2 odd = __builtin_bit_cast(us2, (w[i] >> 8) & 0x00ff00ffu);
+            mx[i][0] = __builtin_elementwise_max(mx[i][0], even);
+            mn[i][0] = __builtin_elementwise_min(mn[i][0], even);
+            mx[i][1] = __builtin_elementwise_max(mx[i][1], odd);
+            mn[i][1] = __builtin_elementwise_min(mn[i][1], odd);
+        }
+    }
+    template <int K>
+    __device__ __forceinline__ void add_tile(const uint32_t (&w)[K][C], const bool (&ok)[K])
+    {
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (ok[j])
+                add(w[j]);
+    }
+    // into the float accumulators, by source channel
+    __device__ __forceinline__ void flush_sums(StatAcc<C> &acc)
+    {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            acc.sum[c] += (double)s[c];
+            s[c] = 0;
+        }
+    }
+    __device__ __forceinline__ void merge_minmax(StatAcc<C> &acc) const
+    {
+#pragma unroll
+        for (int i = 0; i < C; ++i)
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int c = (4 * i + p + 2 * h) % C;
+                    acc.mx[c] = fmaxf(acc.mx[c], (float)mx[i][p][h]);
+                    acc.mn[c] = fminf(acc.mn[c], (float)mn[i][p][h]);
+                }
+    }
+};
+
+template <class Read>
+constexpr bool plain_u8()
+{
+    if constexpr (Read::kind == RD_PLAIN)
+        return Read::dtype == DT_U8;
+    else
+        return false;
+}
+
+// Fetch one tile of u8 units (whole and dword-aligned) for the integer
+// statistics.  Lanes past the item's last unit load its last unit instead
+// and are masked out (ok = false): every lane issues the same loads, so the
+// wait for this tile counts exactly the loads issued after it.
+template <int C, int K>
+__device__ __forceinline__ void fetch_tile_u8(const ItemRec &it, uint32_t ubase, uint32_t units,
+                                              const RowDiv &rowdiv, int T, int tid,
+                                              uint32_t (&w)[K][C], bool (&ok)[K])
+{
+    const bool contig = it.flags & IF_CONTIG;  // uniform
+    gsrc_t base = (gsrc_t)it.src + (int64_t)it.y * it.pitch;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        uint32_t u = ubase + (uint32_t)(j * T + tid);
+        ok[j] = u < units;
+        u = ok[j] ? u : units - 1;
+        gsrc_t q;
+        if (contig) {
+            q = base + (uint64_t)u * (kUnitPx * C);
+        } else {
+            const uint32_t row = rowdiv(u);
+            const int ox0 = (int)(u - row * rowdiv.upr) * kUnitPx;
+            q = base + (int64_t)row * it.pitch + (int64_t)(it.x + ox0) * C;
+        }
+        const FK_GLOBAL uint32_t *p = (const FK_GLOBAL uint32_t *)q;
+#pragma unroll
+        for (int i = 0; i < C; ++i)
+            w[j][i] = p[i];
+    }
+}
+
+// The batch slot owning stats block `slot`: its item (with the compact
+// form's per-item fields filled in), the item's first block and its number
+// of blocks.
+template <class Read, int C>
+__device__ __forceinline__ void stats_slot_item(const KArgs &a, const FK_CONST KArgs *ka, bool compact,
+                                                const FK_CONST uint32_t *tb,
+                                                const FK_CONST ItemRec *items, int n_items,
+                                                uint32_t slot, ItemRec &it, uint32_t &first,
+                                                uint32_t &nslots)
+{
+    if (compact) {
+        const int b = (int)(slot / a.inl_tiles_per_item);
+        first = (uint32_t)b * a.inl_tiles_per_item;
+        nslots = a.inl_tiles_per_item;
+        it = load_item(items);
+        const FK_CONST Roi16 *roi = (const FK_CONST Roi16 *)(ka->inl + 64) + b;
+        it.x = roi->x;
+        it.y = roi->y;
+        it.w = roi->w;
+        it.h = roi->h;
+        it.dst += (uint64_t)b * (uint64_t)a.inl_dst_stride;
+        if constexpr (rd_bilinear(Read::kind)) {
+            it.sx = (float)it.w / (float)it.ow;
+            it.sy = (float)it.h / (float)it.oh;
+        }
+        if ((it.x * C * Read::elem_size) % 4 != 0)
+            it.flags &= ~IF_SRC_VEC;
+    } else {
+        const int b = find_item(tb, n_items, slot);
+        it = load_item(items + b);
+        first = tb[b];
+        nslots = tb[b + 1] - first;
+    }
+}
+
+// The block's statistics into thread 0, then one StatPartial per channel.
+template <int C>
+__device__ __forceinline__ void stats_store_partial(const KArgs &a, StatAcc<C> &acc,
+                                                    StatPartial (*red)[C], uint32_t slot, int tid,
+                                                    int T)
+{
+    block_reduce<C>(acc, red, tid, T);
+    if (tid == 0) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            a.st_part[(size_t)slot * C + c] = StatPartial{acc.mn[c], acc.mx[c], acc.sum[c]};
+    }
+    __syncthreads();  // `red` is reused by the next slot
+}
+
 template <class Read, class Compute, int C, int K>
 __global__ __launch_bounds__(kMaxBlock) void k_stats(const KArgs a)
 {
@@ -1260,32 +1434,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_stats(const KArgs a)
     const bool swap = a.swap != 0;
 
     for (uint32_t slot = blockIdx.x; slot < total; slot += gridDim.x) {
-        int b;
         ItemRec it;
         uint32_t first, nslots;
-        if (compact) {
-            b = (int)(slot / a.inl_tiles_per_item);
-            first = (uint32_t)b * a.inl_tiles_per_item;
-            nslots = a.inl_tiles_per_item;
-            it = load_item(items);
-            const FK_CONST Roi16 *roi = (const FK_CONST Roi16 *)(ka->inl + 64) + b;
-            it.x = roi->x;
-            it.y = roi->y;
-            it.w = roi->w;
-            it.h = roi->h;
-            it.dst += (uint64_t)b * (uint64_t)a.inl_dst_stride;
-            if constexpr (rd_bilinear(Read::kind)) {
-                it.sx = (float)it.w / (float)it.ow;
-                it.sy = (float)it.h / (float)it.oh;
-            }
-            if ((it.x * C * Read::elem_size) % 4 != 0)
-                it.flags &= ~IF_SRC_VEC;
-        } else {
-            b = find_item(tb, n_items, slot);
-            it = load_item(items + b);
-            first = tb[b];
-            nslots = tb[b + 1] - first;
-        }
+        stats_slot_item<Read, C>(a, ka, compact, tb, items, n_items, slot, it, first, nslots);
         const uint32_t upr = (uint32_t)(it.ow + kUnitPx - 1) / kUnitPx;
         const uint32_t units = upr * (uint32_t)it.oh;
         const uint32_t item_tiles = (units + tile_units - 1) / tile_units;
@@ -1339,13 +1490,112 @@ __global__ __launch_bounds__(kMaxBlock) void k_stats(const KArgs a)
                     }
             }
         }
-        block_reduce<C>(acc, red, tid, T);
-        if (tid == 0) {
+        stats_store_partial<C>(a, acc, red, slot, tid, T);
+    }
+}
+
+// The stats write of a u8 plain read with no arithmetic after the cast:
+// the same slots, tiles and partials as k_stats, with integer accumulation
+// (U8Acc).  A kernel of its own, so that it keeps fewer registers live than
+// the float path and more waves stay resident.  Items whose units are not
+// all whole and dword-aligned take a byte-by-byte loop.
+template <int C, int K>
+__global__ __launch_bounds__(kMaxBlock) void k_stats_u8(const KArgs a)
+{
+    using Read = ReadPlain<DT_U8, C>;
+    __shared__ StatPartial red[kMaxBlock / kWave][C];
+    const FK_CONST KArgs *ka = (const FK_CONST KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    const bool inl = a.inl_n > 0;
+    const bool compact = inl && a.inl_compact;
+    const FK_CONST uint32_t *tb =
+        inl ? (const FK_CONST uint32_t *)(ka->inl + kInlineTileBegin) : cptr(a.tile_begin);
+    const FK_CONST ItemRec *items = inl ? (const FK_CONST ItemRec *)ka->inl : cptr(a.items);
+    const int n_items = inl ? a.inl_n : cptr(a.hdr)->n_items;
+    const uint32_t total = inl ? a.inl_total_tiles : cptr(a.hdr)->total_tiles;
+    const int T = blockDim.x;
+    const int tid = threadIdx.x;
+    const uint32_t tile_units = (uint32_t)T * K;
+    const bool swap = a.swap != 0;
+
+    for (uint32_t slot = blockIdx.x; slot < total; slot += gridDim.x) {
+        ItemRec it;
+        uint32_t first, nslots;
+        stats_slot_item<Read, C>(a, ka, compact, tb, items, n_items, slot, it, first, nslots);
+        const uint32_t upr = (uint32_t)(it.ow + kUnitPx - 1) / kUnitPx;
+        const uint32_t units = upr * (uint32_t)it.oh;
+        const uint32_t item_tiles = (units + tile_units - 1) / tile_units;
+        const RowDiv rowdiv(upr);
+
+        StatAcc<C> acc;
+        acc.init();
+        if ((it.flags & IF_SRC_VEC) && it.ow % kUnitPx == 0) {
+            // software pipeline over two register buffers: tile t + nslots
+            // is in flight while tile t is accumulated
+            U8Acc<C> iacc;
+            iacc.init();
+            uint32_t wa[K][C], wb[K][C];
+            bool oka[K], okb[K];
+            uint32_t t = slot - first;
+            fetch_tile_u8<C, K>(it, t * tile_units, units, rowdiv, T, tid, wa, oka);
+            for (;;) {
+                const uint32_t t1 = t + nslots;
+                if (t1 >= item_tiles) {
+                    iacc.add_tile(wa, oka);
+                    break;
+                }
+                fetch_tile_u8<C, K>(it, t1 * tile_units, units, rowdiv, T, tid, wb, okb);
+                iacc.add_tile(wa, oka);
+                iacc.flush_sums(acc);
+                const uint32_t t2 = t1 + nslots;
+                if (t2 >= item_tiles) {
+                    iacc.add_tile(wb, okb);
+                    break;
+                }
+                fetch_tile_u8<C, K>(it, t2 * tile_units, units, rowdiv, T, tid, wa, oka);
+                iacc.add_tile(wb, okb);
+                iacc.flush_sums(acc);
+                t = t2;
+            }
+            iacc.flush_sums(acc);  // at most 2 * K * 4 * 255 per channel between flushes
+            iacc.merge_minmax(acc);
+        } else {
+            for (uint32_t t = slot - first; t < item_tiles; t += nslots) {
+                for (int j = 0; j < K; ++j) {
+                    const uint32_t u = t * tile_units + (uint32_t)(j * T + tid);
+                    if (u >= units)
+                        break;
+                    const uint32_t row = rowdiv(u);
+                    const int ox0 = (int)(u - row * upr) * kUnitPx;
+                    const int left = it.ow - ox0;
+                    const int nv = left < kUnitPx ? left : kUnitPx;
+                    gsrc_t p = (gsrc_t)it.src + (int64_t)(it.y + (int)row) * it.pitch +
+                               (int64_t)(it.x + ox0) * C;
+                    for (int i = 0; i < nv; ++i)
 #pragma unroll
-            for (int c = 0; c < C; ++c)
-                a.st_part[(size_t)slot * C + c] = StatPartial{acc.mn[c], acc.mx[c], acc.sum[c]};
+                        for (int c = 0; c < C; ++c) {
+                            const float x = (float)p[i * C + c];
+                            acc.mn[c] = fminf(acc.mn[c], x);
+                            acc.mx[c] = fmaxf(acc.mx[c], x);
+                            acc.sum[c] += (double)x;
+                        }
+                }
+            }
         }
-        __syncthreads();  // `red` is reused by the next slot
+        if constexpr (C >= 3) {
+            // the chain's net swap: statistics of source channel 2 are
+            // those of output channel 0, and the other way round
+            if (swap) {
+                const float mn0 = acc.mn[0], mx0 = acc.mx[0];
+                const double s0 = acc.sum[0];
+                acc.mn[0] = acc.mn[2];
+                acc.mx[0] = acc.mx[2];
+                acc.sum[0] = acc.sum[2];
+                acc.mn[2] = mn0;
+                acc.mx[2] = mx0;
+                acc.sum[2] = s0;
+            }
+        }
+        stats_store_partial<C>(a, acc, red, slot, tid, T);
     }
 }
 

@@ -218,9 +218,12 @@ bool fk::config_valid(const fk_launch_config &c)
 
 const void *fk::plan_kernel(const fk_plan *p, const fk_launch_config &cfg)
 {
-    if (p->chain.write.layout == FK_STATS)
+    if (p->chain.write.layout == FK_STATS) {
+        if (p->chain.read.kind == FK_READ_PLAIN && p->chain.read.in_dtype == FK_U8 && p->ops.empty())
+            return kernel_stats_u8(p->chain.read.channels, cfg.coarsen);
         return kernel_stats(p->chain.read.kind, p->chain.read.in_dtype, p->chain.read.channels,
                             cfg.coarsen);
+    }
     switch (p->family) {
     case FAM_NORMALIZE: return kernel_normalize(cfg.coarsen, p->opts.strict_fp);
     case FAM_MULADD: return kernel_muladd(p->static_n, cfg.coarsen, p->opts.strict_fp);
@@ -431,10 +434,14 @@ uint32_t fk::build_items(const fk_plan *p, const fk_item *items, int32_t n,
     // a per-pixel kernel's tile is T*K pixels: T*K/4 units of 4 pixels
     const uint64_t tile_units = per_pixel(p) ? (uint64_t)cfg.block_threads * cfg.coarsen / kUnitPx
                                              : (uint64_t)cfg.block_threads * cfg.coarsen;
-    // stats write: an item's "tiles" are its blocks, at most slot_cap each
+    // stats write: an item's "tiles" are its blocks, at most slot_cap each;
+    // a batch shares about one resident grid, so each block walks several
+    // tiles
     const bool stats = p->chain.write.layout == FK_STATS;
+    const uint64_t batch = (uint64_t)(batch_n > 0 ? batch_n : n);
     const uint64_t slot_cap =
-        stats ? std::min<uint64_t>(kStatSlots, p->st_capacity / (uint64_t)(batch_n > 0 ? batch_n : n))
+        stats ? std::max<uint64_t>(1, std::min<uint64_t>({(uint64_t)kStatSlots, p->st_capacity / batch,
+                                                          persistent_grid(p, cfg) / batch}))
               : ~0ull;
     uint64_t tiles = 0;
     for (int32_t b = 0; b < n; ++b) {
@@ -468,6 +475,9 @@ uint32_t fk::build_items(const fk_plan *p, const fk_item *items, int32_t n,
             flags |= IF_SRC_VEC;
         if (r.ow % kUnitPx == 0 && (uintptr_t)it.dst % 16 == 0)
             flags |= IF_DST_VEC;
+        if (p->chain.read.kind == FK_READ_PLAIN && it.x == 0 && it.w == it.src.width &&
+            it.src.pitch_bytes == (int64_t)it.src.width * C * es_in && r.ow % kUnitPx == 0)
+            flags |= IF_CONTIG;
         r.flags = flags;
         tb[b] = (uint32_t)tiles;
         const uint64_t units = (uint64_t)upr * (uint64_t)r.oh;

@@ -46,6 +46,8 @@ struct OpRec {          // 48 bytes
 enum : int32_t {
     IF_SRC_VEC = 1,     // source rows 4-byte aligned: unit loads as dwords
     IF_DST_VEC = 2,     // output rows hold whole units and are 16/8-byte aligned
+    IF_CONTIG = 4,      // plain read of whole frame rows stored back to back, whole
+                        // units per row: unit u starts u * 4 pixels after row y
 };
 
 struct ItemRec {        // 64 bytes: one batch slot's parameters
@@ -97,7 +99,8 @@ struct StatPartial {    // 16 bytes
 // channel, and a second kernel combines each item's partials.
 constexpr int kStatSlots = 512;
 // Partials a stats plan holds (slots over a whole batch); a batch of n
-// items gives each at most kStatCapacity / n slots.
+// items gives each at most kStatCapacity / n slots, and at most the
+// resident grid's blocks / n, so that each block walks several tiles.
 constexpr int kStatCapacity = 65536;
 
 // Kernel arguments (by value, the only kernel argument, so it starts the
@@ -143,6 +146,8 @@ const void *kernel_loop_px(int in_dt, int channels, int coarsen, int strict);
 // pixels) from this many pairs on; shorter loops keep the 4-pixel unit.
 constexpr int kLoopPxMinPairs = 32;
 const void *kernel_stats(int read_kind, int in_dt, int channels, int coarsen);
+// stats write of a plain u8 read with no arithmetic after the cast
+const void *kernel_stats_u8(int channels, int coarsen);
 const void *kernel_stats_final(int channels);
 
 }  // namespace fk

@@ -1,5 +1,6 @@
 // fk_stats_plain.hip -- instantiations of the stats (reduction) kernel:
-// run-time op list, plain read of u8, fp16 and fp32 frames.
+// run-time op list, plain read of u8, fp16 and fp32 frames; and the
+// integer kernel for u8 frames with no arithmetic after the cast.
 #include "fk_device.hpp"
 
 namespace fk {
@@ -33,6 +34,28 @@ const void *kernel_stats_plain(int in_dt, int channels, int coarsen)
     case DT_U8: return stats_c<DT_U8>(channels, coarsen);
     case DT_F16: return stats_c<DT_F16>(channels, coarsen);
     case DT_F32: return stats_c<DT_F32>(channels, coarsen);
+    }
+    return nullptr;
+}
+
+template <int C>
+static const void *stats_u8_k(int k)
+{
+    switch (k) {
+    case 1: return (const void *)&k_stats_u8<C, 1>;
+    case 2: return (const void *)&k_stats_u8<C, 2>;
+    case 4: return (const void *)&k_stats_u8<C, 4>;
+    case 8: return (const void *)&k_stats_u8<C, 8>;
+    }
+    return nullptr;
+}
+
+const void *kernel_stats_u8(int channels, int coarsen)
+{
+    switch (channels) {
+    case 1: return stats_u8_k<1>(coarsen);
+    case 3: return stats_u8_k<3>(coarsen);
+    case 4: return stats_u8_k<4>(coarsen);
     }
     return nullptr;
 }

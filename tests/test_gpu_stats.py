@@ -185,3 +185,41 @@ def test_timed_stats_run_brackets_both_kernels():
         got = host(outs)
     for a, b in zip(got, ref):
         np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("C", [1, 3, 4])
+def test_u8_cast_only_stats_match_oracle_and_float_path(C):
+    """u8 chains with no arithmetic after the cast (integer accumulation)
+    against the oracle, exactly: whole frames, dword-aligned and unaligned
+    crops, widths that are not a multiple of 4, with and without the
+    channel swap.  The same chain with a Mul by 1 (float accumulation, the
+    same values) gives the same bits."""
+    g = datagen.rng(40 + C)
+    H, W = 45, 203
+    frames = [datagen.frame(g, H, W, C) for _ in range(2)]
+    # W * C bytes per row: 203, 609, 812 -> rows dword-aligned only for C = 4
+    items = [datagen.whole_frame_item(frames[0]),
+             {"frame": 1, "x": 4, "y": 3, "w": 96, "h": 40, "out_w": 96, "out_h": 40},
+             {"frame": 0, "x": 1, "y": 0, "w": 64, "h": 17, "out_w": 64, "out_h": 17},
+             {"frame": 1, "x": 8, "y": 5, "w": 13, "h": 9, "out_w": 13, "out_h": 9}]
+    aligned = np.ascontiguousarray(frames[0][:, :200])  # 200 * C bytes per row
+    dframes = to_dev(frames + [aligned])
+    items.append({"frame": 2, "x": 0, "y": 0, "w": 200, "h": H, "out_w": 200, "out_h": H})
+    frames_all = frames + [aligned]
+    for swap in ([False, True] if C >= 3 else [False]):
+        say("stats: u8 cast only, C", C, "swap", swap)
+        ops = ([{"kind": "swap", "k": []}] if swap else []) + [{"kind": "cvt", "k": []}]
+        ch = {"read": {"kind": "plain", "dtype": "u8", "channels": C, "out_w": 0, "out_h": 0},
+              "ops": ops, "write": {"dtype": "f32", "layout": "packed"}}
+        ch_f = dict(ch, ops=ops + [{"kind": "mul", "k": [1.0]}])
+        st = [r["out"] for r in oracle.run_chain(stats_of(ch), frames_all, items)]
+        for t, k in ((256, 8), (64, 1), (1024, 2)):
+            with Plan(stats_of(ch), len(items), config_source=fk.FK_CONFIG_MANUAL,
+                      manual=(t, k)) as p:
+                got = host(p.run(dframes, items))
+            with Plan(stats_of(ch_f), len(items), config_source=fk.FK_CONFIG_MANUAL,
+                      manual=(t, k)) as p:
+                got_f = host(p.run(dframes, items))
+            for b in range(len(items)):
+                np.testing.assert_array_equal(got[b], st[b], err_msg=f"item {b} T={t} K={k} swap={swap}")
+                np.testing.assert_array_equal(got[b], got_f[b], err_msg=f"float path, item {b}")
