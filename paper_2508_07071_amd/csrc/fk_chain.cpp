@@ -1,6 +1,7 @@
 // fk_chain.cpp -- chain rewriting done once per plan (no HIP).
 #include "fk_chain.hpp"
 
+#include <cstdint>
 #include <cstring>
 #include <utility>
 
@@ -13,6 +14,7 @@
 // becomes a LOOP record after its body's records; contraction pairs only
 // records of one run: a loop body, or the stretch between two loop
 // boundaries (a MUL that repeats cannot absorb an ADD that does not).
+// Finally, runs of identical records become one record and a LOOP.
 void fk::normalise_chain(const fk_chain_desc *ch, bool strict, std::vector<OpRec> &ops,
                          int32_t &swap)
 {
@@ -88,6 +90,64 @@ void fk::normalise_chain(const fk_chain_desc *ch, bool strict, std::vector<OpRec
             ++n;
         ops[k].span = n;
     }
+    merge_repeats(ops);
+}
+
+static bool same_record(const fk::OpRec &x, const fk::OpRec &y)
+{
+    return x.code == y.code && std::memcmp(x.a, y.a, sizeof x.a) == 0 &&
+           std::memcmp(x.b, y.b, sizeof x.b) == 0;
+}
+
+// Consecutive identical records outside multi-record loop bodies, each
+// possibly repeated by a one-record LOOP, become one record and one
+// one-record LOOP with the summed count: the same operations in the same
+// order, run by the kernels as a register loop with the constants loaded
+// once instead of one table record per repetition.
+void fk::merge_repeats(std::vector<OpRec> &ops)
+{
+    const size_t n = ops.size();
+    std::vector<char> in_body(n, 0);
+    for (size_t k = 0; k < n; ++k)
+        if (ops[k].code == OPC_LOOP && ops[k].span > 1)
+            for (size_t j = k - (size_t)ops[k].span; j < k; ++j)
+                in_body[j] = 1;
+    std::vector<OpRec> out;
+    out.reserve(n);
+    size_t k = 0;
+    while (k < n) {
+        if (ops[k].code == OPC_LOOP || in_body[k]) {
+            out.push_back(ops[k]);
+            ++k;
+            continue;
+        }
+        const OpRec r = ops[k];
+        int64_t total = 0;
+        size_t j = k;
+        while (j < n && ops[j].code != OPC_LOOP && !in_body[j] && same_record(ops[j], r)) {
+            int64_t c = 1;
+            size_t next = j + 1;
+            if (next < n && ops[next].code == OPC_LOOP && ops[next].span == 1) {
+                c = ops[next].count;
+                ++next;
+            }
+            if (total + c > INT32_MAX)
+                break;
+            total += c;
+            j = next;
+        }
+        out.push_back(r);
+        if (total > 1) {
+            OpRec l;
+            std::memset(&l, 0, sizeof l);
+            l.code = OPC_LOOP;
+            l.span = 1;
+            l.count = (int32_t)total;
+            out.push_back(l);
+        }
+        k = j;
+    }
+    ops.swap(out);
 }
 
 // Runs of each record code when the list executes, loops unrolled

@@ -15,6 +15,10 @@ namespace fk {
 // when the read must exchange channels 0 and 2.
 void normalise_chain(const fk_chain_desc *ch, bool strict, std::vector<OpRec> &ops, int32_t &swap);
 // Executed records per code (loops unrolled) of a normalised list.
+// Consecutive identical records (outside multi-record loop bodies) merged
+// into one record repeated by a one-record LOOP; the last step of
+// normalise_chain.
+void merge_repeats(std::vector<OpRec> &ops);
 void executed_counts(const std::vector<OpRec> &ops, double cnt[4]);
 // FAM_NORMALIZE / FAM_MULADD / FAM_MULADD_LOOP with their constants (and
 // op count, or the loop's count of pairs) when the chain is one of the

@@ -958,17 +958,28 @@ __global__ __launch_bounds__(kMaxBlock) void k_transform(const KArgs a)
         const uint32_t ubase = (tile - first_tile) * tile_units;
         const RowDiv rowdiv(upr);
 
+        // a plain read of whole frame rows stored back to back (and its
+        // output) is one row of ow * oh pixels: no row division
+        bool contig = false;
+        if constexpr (Read::kind == RD_PLAIN)
+            contig = it.flags & IF_CONTIG;
         float v[K][kUnitPx][C];
         int oy[K], ox0[K], nv[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const uint32_t u = ubase + (uint32_t)(j * T + tid);
             if (u < units) {
-                const uint32_t row = rowdiv(u);
-                oy[j] = (int)row;
-                ox0[j] = (int)(u - row * upr) * kUnitPx;
-                const int left = it.ow - ox0[j];
-                nv[j] = left < kUnitPx ? left : kUnitPx;
+                if (contig) {
+                    oy[j] = 0;
+                    ox0[j] = (int)(u * kUnitPx);
+                    nv[j] = kUnitPx;
+                } else {
+                    const uint32_t row = rowdiv(u);
+                    oy[j] = (int)row;
+                    ox0[j] = (int)(u - row * upr) * kUnitPx;
+                    const int left = it.ow - ox0[j];
+                    nv[j] = left < kUnitPx ? left : kUnitPx;
+                }
                 Read::load(it, oy[j], ox0[j], nv[j], v[j]);
             } else {
                 oy[j] = 0;

@@ -476,7 +476,8 @@ uint32_t fk::build_items(const fk_plan *p, const fk_item *items, int32_t n,
         if (r.ow % kUnitPx == 0 && (uintptr_t)it.dst % 16 == 0)
             flags |= IF_DST_VEC;
         if (p->chain.read.kind == FK_READ_PLAIN && it.x == 0 && it.w == it.src.width &&
-            it.src.pitch_bytes == (int64_t)it.src.width * C * es_in && r.ow % kUnitPx == 0)
+            it.src.pitch_bytes == (int64_t)it.src.width * C * es_in && r.ow % kUnitPx == 0 &&
+            (int64_t)r.ow * r.oh < ((int64_t)1 << 31))
             flags |= IF_CONTIG;
         r.flags = flags;
         tb[b] = (uint32_t)tiles;

@@ -47,7 +47,8 @@ enum : int32_t {
     IF_SRC_VEC = 1,     // source rows 4-byte aligned: unit loads as dwords
     IF_DST_VEC = 2,     // output rows hold whole units and are 16/8-byte aligned
     IF_CONTIG = 4,      // plain read of whole frame rows stored back to back, whole
-                        // units per row: unit u starts u * 4 pixels after row y
+                        // units per row, under 2^31 pixels: unit u starts u * 4
+                        // pixels after row y
 };
 
 struct ItemRec {        // 64 bytes: one batch slot's parameters
