@@ -26,6 +26,7 @@
 
 #include <stdint.h>
 
+#include <type_traits>
 #include <utility>
 
 #include "fk_internal.hpp"
@@ -218,51 +219,75 @@ struct ReadCropResize {
         return (float)((d[k >> 2] >> (8 * (k & 3))) & 0xffu);
     }
 
-    __device__ __forceinline__ static void load(const ItemRec &it, int oy, int ox0, int n,
-                                                float (&r)[kUnitPx][C])
+    // one output pixel from its source rows r0, r1 (ROI-relative column 0)
+    // and its output column ox
+    __device__ __forceinline__ static void pixel(const ItemRec &it, gsrc_t r0, gsrc_t r1, float ay,
+                                                 int ox, bool win, float (&r)[C])
+    {
+        constexpr int ES = DSize<DT>::v;
+        int x0, x1;
+        float ax;
+        bilinear_coord(ox, it.sx, it.w, x0, x1, ax);
+        float p00[C], p01[C], p10[C], p11[C];
+        if (DT == DT_U8 && win) {
+            uint32_t t[2], b[2];
+            window((uint64_t)(uintptr_t)(r0 + x0 * C), t);
+            window((uint64_t)(uintptr_t)(r1 + x0 * C), b);
+            const int o1 = (x1 == x0) ? 0 : C;  // clamped tap: the same pixel
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                p00[c] = byte_at(t, c);
+                p01[c] = byte_at(t, o1 + c);
+                p10[c] = byte_at(b, c);
+                p11[c] = byte_at(b, o1 + c);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                p00[c] = load_elem<DT>(r0 + (x0 * C + c) * ES);
+                p01[c] = load_elem<DT>(r0 + (x1 * C + c) * ES);
+                p10[c] = load_elem<DT>(r1 + (x0 * C + c) * ES);
+                p11[c] = load_elem<DT>(r1 + (x1 * C + c) * ES);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const float top = fmaf(ax, p01[c] - p00[c], p00[c]);
+            const float bot = fmaf(ax, p11[c] - p10[c], p10[c]);
+            r[c] = fmaf(ay, bot - top, top);
+        }
+    }
+
+    // source rows of output row oy, and the vertical weight.  A frame
+    // below 4 GiB with rows under 16 MiB (IF_SMALL_FRAME) takes 32-bit
+    // offsets from full-rate 24-bit multiplies.
+    __device__ __forceinline__ static void rows(const ItemRec &it, int oy, gsrc_t &r0, gsrc_t &r1,
+                                                float &ay)
     {
         constexpr int ES = DSize<DT>::v;
         int y0, y1;
-        float ay;
         bilinear_coord(oy, it.sy, it.h, y0, y1, ay);
         gsrc_t base = (gsrc_t)it.src + (int64_t)it.x * (C * ES);
-        gsrc_t r0 = base + (int64_t)(it.y + y0) * it.pitch;
-        gsrc_t r1 = base + (int64_t)(it.y + y1) * it.pitch;
+        if (it.flags & IF_SMALL_FRAME) {
+            r0 = base + __umul24((uint32_t)(it.y + y0), (uint32_t)it.pitch);
+            r1 = base + __umul24((uint32_t)(it.y + y1), (uint32_t)it.pitch);
+        } else {
+            r0 = base + (int64_t)(it.y + y0) * it.pitch;
+            r1 = base + (int64_t)(it.y + y1) * it.pitch;
+        }
+    }
+
+    __device__ __forceinline__ static void load(const ItemRec &it, int oy, int ox0, int n,
+                                                float (&r)[kUnitPx][C])
+    {
+        gsrc_t r0, r1;
+        float ay;
+        rows(it, oy, r0, r1, ay);
         const bool win = window_ok(it);
 #pragma unroll
         for (int i = 0; i < kUnitPx; ++i) {
             if (i < n) {
-                int x0, x1;
-                float ax;
-                bilinear_coord(ox0 + i, it.sx, it.w, x0, x1, ax);
-                float p00[C], p01[C], p10[C], p11[C];
-                if (DT == DT_U8 && win) {
-                    uint32_t t[2], b[2];
-                    window((uint64_t)(uintptr_t)(r0 + x0 * C), t);
-                    window((uint64_t)(uintptr_t)(r1 + x0 * C), b);
-                    const int o1 = (x1 == x0) ? 0 : C;  // clamped tap: the same pixel
-#pragma unroll
-                    for (int c = 0; c < C; ++c) {
-                        p00[c] = byte_at(t, c);
-                        p01[c] = byte_at(t, o1 + c);
-                        p10[c] = byte_at(b, c);
-                        p11[c] = byte_at(b, o1 + c);
-                    }
-                } else {
-#pragma unroll
-                    for (int c = 0; c < C; ++c) {
-                        p00[c] = load_elem<DT>(r0 + (x0 * C + c) * ES);
-                        p01[c] = load_elem<DT>(r0 + (x1 * C + c) * ES);
-                        p10[c] = load_elem<DT>(r1 + (x0 * C + c) * ES);
-                        p11[c] = load_elem<DT>(r1 + (x1 * C + c) * ES);
-                    }
-                }
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    const float top = fmaf(ax, p01[c] - p00[c], p00[c]);
-                    const float bot = fmaf(ax, p11[c] - p10[c], p10[c]);
-                    r[i][c] = fmaf(ay, bot - top, top);
-                }
+                pixel(it, r0, r1, ay, ox0 + i, win, r[i]);
             } else {
 #pragma unroll
                 for (int c = 0; c < C; ++c)
@@ -580,10 +605,12 @@ struct Compose {
 };
 
 // The hot normalise chain: swap, cvt, *k, -mean, /std.  Constant table:
-// [k, mean0..2, std0..2].
+// [k, mean0..2, std0..2]; the contracted (non-strict) form holds 1/std
+// there and multiplies by it.
 template <bool Strict>
-using NormalizeChain = typename Compose<Strict, OpSwapRB, OpCvtF32, OpMul<0, false>,
-                                        OpSub<1, true>, OpDiv<4, true>>::type;
+using NormalizeChain =
+    typename Compose<Strict, OpSwapRB, OpCvtF32, OpMul<0, false>, OpSub<1, true>,
+                     std::conditional_t<Strict, OpDiv<4, true>, OpMul<4, true>>>::type;
 
 // cvt then N alternating Mul (even op) / Add (odd op), scalar constants in
 // op order at slots 0..N-1.
@@ -876,6 +903,8 @@ __device__ __forceinline__ ItemRec load_item(const FK_CONST ItemRec *p)
 // 2^28, a 53-bit product), corrected by exact 32-bit products ((q + 1) * d
 // <= u + 2d < 2^29 for d < 2^16).  Cheaper than a 32-bit integer
 // division; the reciprocal is taken once per tile.
+// The quotients here are row indices (below 2^16), so the corrections use
+// the full-rate 24-bit multiply.
 struct RowDiv {
     uint32_t upr;
     double rcp;
@@ -883,9 +912,9 @@ struct RowDiv {
     __device__ __forceinline__ uint32_t operator()(uint32_t u) const
     {
         uint32_t q = (uint32_t)((double)u * rcp);
-        if ((q + 1) * upr <= u)
+        if (__umul24(q + 1, upr) <= u)
             ++q;
-        else if (q * upr > u)
+        else if (__umul24(q, upr) > u)
             --q;
         return q;
     }
@@ -903,6 +932,42 @@ __device__ __forceinline__ int find_item(const FK_CONST uint32_t *tb, int n_item
             hi = mid - 1;
     }
     return lo;
+}
+
+// The item owning `tile` (with the compact form's per-item fields filled
+// in), and the tile's first unit within it.
+template <class Read, int C>
+__device__ __forceinline__ void tile_item(const KArgs &a, const FK_CONST KArgs *ka, bool compact,
+                                          const FK_CONST uint32_t *tb, const FK_CONST ItemRec *items,
+                                          int n_items, uint32_t tile, uint32_t tile_units,
+                                          ItemRec &it, uint32_t &ubase)
+{
+    uint32_t first_tile;
+    if (compact) {
+        const int b = (int)(tile / a.inl_tiles_per_item);
+        first_tile = (uint32_t)b * a.inl_tiles_per_item;
+        it = load_item(items);  // the template (item 0)
+        const FK_CONST Roi16 *roi = (const FK_CONST Roi16 *)(ka->inl + 64) + b;
+        it.x = roi->x;
+        it.y = roi->y;
+        it.w = roi->w;
+        it.h = roi->h;
+        it.dst += (uint64_t)b * (uint64_t)a.inl_dst_stride;
+        if constexpr (rd_bilinear(Read::kind)) {
+            // the same IEEE fp32 divisions the host performs for the table forms
+            it.sx = (float)it.w / (float)it.ow;
+            it.sy = (float)it.h / (float)it.oh;
+        }
+        // template bit: frame base and pitch dword-aligned; the ROI's
+        // column offset decides the rest
+        if ((it.x * C * Read::elem_size) % 4 != 0)
+            it.flags &= ~IF_SRC_VEC;
+    } else {
+        const int b = find_item(tb, n_items, tile);
+        it = load_item(items + b);
+        first_tile = tb[b];
+    }
+    ubase = (tile - first_tile) * tile_units;
 }
 
 template <class Read, class Compute, class Write, int C, int K>
@@ -926,36 +991,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_transform(const KArgs a)
     const bool swap = a.swap != 0;
 
     for (uint32_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
-        int b;
         ItemRec it;
-        uint32_t first_tile;
-        if (compact) {
-            b = (int)(tile / a.inl_tiles_per_item);
-            first_tile = (uint32_t)b * a.inl_tiles_per_item;
-            it = load_item(items);  // the template (item 0)
-            const FK_CONST Roi16 *roi = (const FK_CONST Roi16 *)(ka->inl + 64) + b;
-            it.x = roi->x;
-            it.y = roi->y;
-            it.w = roi->w;
-            it.h = roi->h;
-            it.dst += (uint64_t)b * (uint64_t)a.inl_dst_stride;
-            if constexpr (rd_bilinear(Read::kind)) {
-                // the same IEEE fp32 divisions the host performs for the table forms
-                it.sx = (float)it.w / (float)it.ow;
-                it.sy = (float)it.h / (float)it.oh;
-            }
-            // template bit: frame base and pitch dword-aligned; the ROI's
-            // column offset decides the rest
-            if ((it.x * C * Read::elem_size) % 4 != 0)
-                it.flags &= ~IF_SRC_VEC;
-        } else {
-            b = find_item(tb, n_items, tile);
-            it = load_item(items + b);
-            first_tile = tb[b];
-        }
+        uint32_t ubase;
+        tile_item<Read, C>(a, ka, compact, tb, items, n_items, tile, tile_units, it, ubase);
         const uint32_t upr = (uint32_t)(it.ow + kUnitPx - 1) / kUnitPx;
         const uint32_t units = upr * (uint32_t)it.oh;
-        const uint32_t ubase = (tile - first_tile) * tile_units;
         const RowDiv rowdiv(upr);
 
         // a plain read of whole frame rows stored back to back (and its
@@ -1014,6 +1054,98 @@ __global__ __launch_bounds__(kMaxBlock) void k_transform(const KArgs a)
             const bool wave_whole = __all(whole ? 1 : 0);
             if (nv[j] > 0)
                 Write::store(it, oy[j], ox0[j], nv[j], v[j], wave_lds, wave_whole);
+        }
+    }
+}
+
+// ----------------------------------------- crop+resize, pixel-strided lanes --
+// The transform pattern for a bilinear crop+resize with a planar write,
+// laid out for the gather: lane t of a tile takes output pixels
+// pbase + q * T + t (q < 4K) instead of K units of 4 adjacent pixels.  Each
+// gather instruction of a wave then reads the taps of 64 consecutive output
+// pixels, a segment of one or two source rows, instead of 64 units spread
+// over several output rows, so the L1 sees far fewer distinct lines per
+// instruction.  Tiles are those of k_transform (T * K units = 4 T K
+// pixels); the per-pixel planar stores of consecutive lanes are
+// consecutive.
+template <class Compute, int DO, int C, int K>
+__global__ __launch_bounds__(kMaxBlock) void k_resize_px(const KArgs a)
+{
+    using Read = ReadCropResize<DT_U8, C>;
+    constexpr int ES = DSize<DO>::v;
+    const FK_CONST KArgs *ka = (const FK_CONST KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    const bool inl = a.inl_n > 0;
+    const bool compact = inl && a.inl_compact;
+    const FK_CONST uint32_t *tb =
+        inl ? (const FK_CONST uint32_t *)(ka->inl + kInlineTileBegin) : cptr(a.tile_begin);
+    const FK_CONST ItemRec *items = inl ? (const FK_CONST ItemRec *)ka->inl : cptr(a.items);
+    const int n_items = inl ? a.inl_n : cptr(a.hdr)->n_items;
+    const uint32_t total = inl ? a.inl_total_tiles : cptr(a.hdr)->total_tiles;
+    const int T = blockDim.x;
+    const int tid = threadIdx.x;
+    const uint32_t tile_units = (uint32_t)T * K;
+    const bool swap = a.swap != 0;
+
+    for (uint32_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        ItemRec it;
+        uint32_t ubase;
+        tile_item<Read, C>(a, ka, compact, tb, items, n_items, tile, tile_units, it, ubase);
+        const uint32_t npx = (uint32_t)it.ow * (uint32_t)it.oh;  // < 2^32
+        const uint32_t pbase = ubase * kUnitPx;
+        const RowDiv rowdiv((uint32_t)it.ow);  // exact below 2^28 pixels
+        const bool big = npx >= (1u << 28);
+        const bool win = Read::window_ok(it);
+
+        const int64_t plane = (int64_t)it.ow * it.oh;
+        gdst_t dst = (gdst_t)it.dst;
+        // groups of 4 pixels per lane, one after another: registers do not
+        // grow with K (K only sizes the tile)
+        for (int j = 0; j < K; ++j) {
+            float v[1][kUnitPx][C];
+            int oy[kUnitPx], ox[kUnitPx];
+#pragma unroll
+            for (int i = 0; i < kUnitPx; ++i) {
+                const uint32_t q = (uint32_t)(j * kUnitPx + i);
+                const uint32_t p = pbase + q * (uint32_t)T + (uint32_t)tid;
+                if (p < npx && p >= pbase) {
+                    const uint32_t row = big ? p / (uint32_t)it.ow : rowdiv(p);
+                    oy[i] = (int)row;
+                    ox[i] = (int)(p - __umul24(row, (uint32_t)it.ow));
+                    gsrc_t r0, r1;
+                    float ay;
+                    Read::rows(it, oy[i], r0, r1, ay);
+                    Read::pixel(it, r0, r1, ay, ox[i], win, v[0][i]);
+                } else {
+                    oy[i] = -1;
+                    ox[i] = 0;
+#pragma unroll
+                    for (int c = 0; c < C; ++c)
+                        v[0][i][c] = 0.0f;
+                }
+            }
+            if constexpr (C >= 3) {
+                // run-time tier: the chain's net channel swap, applied at the read
+                if (swap) {
+#pragma unroll
+                    for (int i = 0; i < kUnitPx; ++i) {
+                        const float t = v[0][i][0];
+                        v[0][i][0] = v[0][i][2];
+                        v[0][i][2] = t;
+                    }
+                }
+            }
+
+            Compute::template apply<1, C>(a, v);
+
+#pragma unroll
+            for (int i = 0; i < kUnitPx; ++i)
+                if (oy[i] >= 0) {
+                    // below ow * oh < 2^32
+                    const uint32_t p = __umul24((uint32_t)oy[i], (uint32_t)it.ow) + (uint32_t)ox[i];
+#pragma unroll
+                    for (int c = 0; c < C; ++c)
+                        store_elem<DO>(dst + (c * plane + (int64_t)p) * ES, v[0][i][c]);
+                }
         }
     }
 }

@@ -334,6 +334,16 @@ extern "C" fk_status fk_plan_create(const fk_chain_desc *chain, int32_t max_batc
         int sn = 0;
         p->family = o.tier == FK_TIER_AUTO && !stats ? match_static(&p->chain, consts, sn)
                                                      : FAM_RUNTIME;
+        if (p->family == FAM_NORMALIZE && !o.strict_fp) {
+            // the contracted kernel multiplies by 1/std, as the run-time
+            // tier does; otherwise the run-time tier divides
+            if (recip_ok(&consts[4], 3)) {
+                for (int c = 0; c < 3; ++c)
+                    consts[4 + c] = 1.0f / consts[4 + c];
+            } else {
+                p->family = FAM_RUNTIME;
+            }
+        }
         p->static_n = sn;
         normalise_chain(&p->chain, o.strict_fp != 0, p->ops, p->swap);
         p->cfg = o.config_source == FK_CONFIG_MANUAL ? o.manual : default_config(p);
@@ -425,6 +435,13 @@ extern "C" fk_status fk_plan_get_tier(const fk_plan *plan, int32_t *is_static)
 
 // Fill the item records and tile prefix sums of a run; returns the number
 // of tiles.
+// Row offsets of the frame fit 32 bits and its pitch 24 bits (full-rate
+// 24-bit multiplies in the kernels).
+static bool small_frame(const fk_image &f)
+{
+    return f.pitch_bytes < ((int64_t)1 << 24) && f.pitch_bytes * (int64_t)f.height < ((int64_t)1 << 32);
+}
+
 uint32_t fk::build_items(const fk_plan *p, const fk_item *items, int32_t n,
                          const fk_launch_config &cfg, ItemRec *recs, uint32_t *tb,
                          int32_t batch_n)
@@ -475,6 +492,8 @@ uint32_t fk::build_items(const fk_plan *p, const fk_item *items, int32_t n,
             flags |= IF_SRC_VEC;
         if (r.ow % kUnitPx == 0 && (uintptr_t)it.dst % 16 == 0)
             flags |= IF_DST_VEC;
+        if (small_frame(it.src))
+            flags |= IF_SMALL_FRAME;
         if (p->chain.read.kind == FK_READ_PLAIN && it.x == 0 && it.w == it.src.width &&
             it.src.pitch_bytes == (int64_t)it.src.width * C * es_in && r.ow % kUnitPx == 0 &&
             (int64_t)r.ow * r.oh < ((int64_t)1 << 31))
@@ -625,6 +644,8 @@ fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_la
             t.flags |= IF_SRC_VEC;
         if (t.ow % kUnitPx == 0 && (uintptr_t)items[0].dst % 16 == 0 && a.inl_dst_stride % 16 == 0)
             t.flags |= IF_DST_VEC;
+        if (small_frame(items[0].src))
+            t.flags |= IF_SMALL_FRAME;
         Roi16 *roi = (Roi16 *)(a.inl + 64);
         for (int32_t b = 0; b < n; ++b)
             roi[b] = Roi16{(uint16_t)items[b].x, (uint16_t)items[b].y, (uint16_t)items[b].w,

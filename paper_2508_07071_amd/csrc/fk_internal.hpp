@@ -37,7 +37,7 @@ struct OpRec {          // 48 bytes
     int32_t code;
     int32_t span;       // LOOP: body records just before this one
     int32_t count;      // LOOP: runs of the body in all (>= 1)
-    int32_t pad;
+    int32_t from_div;   // MUL: a division by 1 / a (contracted mode), counted as DIV
     float a[4];         // MUL/ADD/DIV constant per channel, or FMA multiplier
     float b[4];         // FMA addend per channel
 };
@@ -49,6 +49,7 @@ enum : int32_t {
     IF_CONTIG = 4,      // plain read of whole frame rows stored back to back, whole
                         // units per row, under 2^31 pixels: unit u starts u * 4
                         // pixels after row y
+    IF_SMALL_FRAME = 8, // frame below 4 GiB, rows below 16 MiB: 32-bit row offsets
 };
 
 struct ItemRec {        // 64 bytes: one batch slot's parameters

@@ -66,12 +66,12 @@ const void *kernel_runtime(int read_kind, int in_dt, int channels, int out_dt, i
     return nullptr;
 }
 
-// Crop+resize u8x3 -> swap, cvt, *k, -mean, /std -> planar fp32.
+// Crop+resize u8x3 -> swap, cvt, *k, -mean, /std -> planar fp32, with
+// pixel-strided lanes for the gather.
 template <bool Strict, int K>
 static const void *norm_ptr()
 {
-    return (const void *)&k_transform<ReadCropResize<DT_U8, 3>, StaticCompute<NormalizeChain<Strict>>,
-                                      WritePlanar<DT_F32, 3>, 3, K>;
+    return (const void *)&k_resize_px<StaticCompute<NormalizeChain<Strict>>, DT_F32, 3, K>;
 }
 
 const void *kernel_normalize(int coarsen, int strict)
