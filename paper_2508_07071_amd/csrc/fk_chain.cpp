@@ -1,26 +1,15 @@
 // fk_chain.cpp -- chain rewriting done once per plan (no HIP).
 #include "fk_chain.hpp"
 
-#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <utility>
 
 // --------------------------------------------------------- normalisation --
 
-// 1 / k[c] is a normal float for every channel in use, as is k[c].
-bool fk::recip_ok(const float *k, int C)
-{
-    for (int c = 0; c < C; ++c)
-        if (!std::isnormal(k[c]) || !std::isnormal(1.0f / k[c]))
-            return false;
-    return true;
-}
-
 // Run-time op list: swaps moved to the read (each later-crossed op's
 // per-channel constants permuted), CVT dropped, SUB -> ADD(-k), and unless
-// strict, DIV by k -> MUL by 1/k (when both are normal floats) and MUL
-// immediately followed by ADD -> FMA.  Every rewrite preserves
+// strict, MUL immediately followed by ADD -> FMA.  Every rewrite preserves
 // the per-element fp32 arithmetic exactly except the contraction.  A loop
 // becomes a LOOP record after its body's records; contraction pairs only
 // records of one run: a loop body, or the stretch between two loop
@@ -73,21 +62,13 @@ void fk::normalise_chain(const fk_chain_desc *ch, bool strict, std::vector<OpRec
         }
         for (int c = 0; c < 4; ++c)
             r.a[c] = k[c];
-        if (!strict && r.code == OPC_DIV && recip_ok(k, C)) {
-            // contracted mode: a multiply by the correctly rounded reciprocal
-            // (within 2^-23 relative of the quotient for normal results)
-            r.code = OPC_MUL;
-            r.from_div = 1;
-            for (int c = 0; c < C; ++c)
-                r.a[c] = 1.0f / k[c];
-        }
         lin.push_back(r);
         run.push_back(cur);
     }
     ops.clear();
     std::vector<int> orun;
     for (size_t i = 0; i < lin.size(); ++i) {
-        if (!strict && lin[i].code == OPC_MUL && !lin[i].from_div && i + 1 < lin.size() &&
+        if (!strict && lin[i].code == OPC_MUL && i + 1 < lin.size() &&
             lin[i + 1].code == OPC_ADD && run[i] == run[i + 1]) {
             OpRec f = lin[i];
             f.code = OPC_FMA;
@@ -114,7 +95,7 @@ void fk::normalise_chain(const fk_chain_desc *ch, bool strict, std::vector<OpRec
 
 static bool same_record(const fk::OpRec &x, const fk::OpRec &y)
 {
-    return x.code == y.code && x.from_div == y.from_div && std::memcmp(x.a, y.a, sizeof x.a) == 0 &&
+    return x.code == y.code && std::memcmp(x.a, y.a, sizeof x.a) == 0 &&
            std::memcmp(x.b, y.b, sizeof x.b) == 0;
 }
 
@@ -182,7 +163,7 @@ void fk::executed_counts(const std::vector<OpRec> &ops, double cnt[4])
                 times[j] = ops[k].count;
     for (size_t k = 0; k < ops.size(); ++k)
         if (ops[k].code != OPC_LOOP)
-            cnt[ops[k].from_div ? OPC_DIV : ops[k].code] += times[k];
+            cnt[ops[k].code] += times[k];
 }
 
 // Compile-time chains built into the library.

@@ -14,11 +14,7 @@ namespace fk {
 // Run-time tier op list for a validated chain (see fk_chain.cpp); swap = 1
 // when the read must exchange channels 0 and 2.
 void normalise_chain(const fk_chain_desc *ch, bool strict, std::vector<OpRec> &ops, int32_t &swap);
-// 1 / k[c] and k[c] are normal floats for c < C (a division may then run as
-// a multiply by the reciprocal in the contracted mode).
-bool recip_ok(const float *k, int C);
-// Executed records per code (loops unrolled) of a normalised list; a MUL
-// that replaced a division counts as DIV.
+// Executed records per code (loops unrolled) of a normalised list.
 // Consecutive identical records (outside multi-record loop bodies) merged
 // into one record repeated by a one-record LOOP; the last step of
 // normalise_chain.

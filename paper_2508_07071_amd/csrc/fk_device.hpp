@@ -26,7 +26,6 @@
 
 #include <stdint.h>
 
-#include <type_traits>
 #include <utility>
 
 #include "fk_internal.hpp"
@@ -605,12 +604,10 @@ struct Compose {
 };
 
 // The hot normalise chain: swap, cvt, *k, -mean, /std.  Constant table:
-// [k, mean0..2, std0..2]; the contracted (non-strict) form holds 1/std
-// there and multiplies by it.
+// [k, mean0..2, std0..2].
 template <bool Strict>
-using NormalizeChain =
-    typename Compose<Strict, OpSwapRB, OpCvtF32, OpMul<0, false>, OpSub<1, true>,
-                     std::conditional_t<Strict, OpDiv<4, true>, OpMul<4, true>>>::type;
+using NormalizeChain = typename Compose<Strict, OpSwapRB, OpCvtF32, OpMul<0, false>,
+                                        OpSub<1, true>, OpDiv<4, true>>::type;
 
 // cvt then N alternating Mul (even op) / Add (odd op), scalar constants in
 // op order at slots 0..N-1.

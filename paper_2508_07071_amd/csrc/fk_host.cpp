@@ -334,16 +334,6 @@ extern "C" fk_status fk_plan_create(const fk_chain_desc *chain, int32_t max_batc
         int sn = 0;
         p->family = o.tier == FK_TIER_AUTO && !stats ? match_static(&p->chain, consts, sn)
                                                      : FAM_RUNTIME;
-        if (p->family == FAM_NORMALIZE && !o.strict_fp) {
-            // the contracted kernel multiplies by 1/std, as the run-time
-            // tier does; otherwise the run-time tier divides
-            if (recip_ok(&consts[4], 3)) {
-                for (int c = 0; c < 3; ++c)
-                    consts[4 + c] = 1.0f / consts[4 + c];
-            } else {
-                p->family = FAM_RUNTIME;
-            }
-        }
         p->static_n = sn;
         normalise_chain(&p->chain, o.strict_fp != 0, p->ops, p->swap);
         p->cfg = o.config_source == FK_CONFIG_MANUAL ? o.manual : default_config(p);

@@ -37,7 +37,7 @@ struct OpRec {          // 48 bytes
     int32_t code;
     int32_t span;       // LOOP: body records just before this one
     int32_t count;      // LOOP: runs of the body in all (>= 1)
-    int32_t from_div;   // MUL: a division by 1 / a (contracted mode), counted as DIV
+    int32_t pad;
     float a[4];         // MUL/ADD/DIV constant per channel, or FMA multiplier
     float b[4];         // FMA addend per channel
 };

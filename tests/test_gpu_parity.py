@@ -46,7 +46,7 @@ def test_config0_hot_chain_full_size():
 def test_static_and_runtime_tiers_agree_bitwise(strict):
     """The compile-time normalise kernel and the run-time op list compute
     the same operations: bit-identical in the strict mode, and in the
-    contracted mode too (both fuse Mul+Sub and multiply by 1/std)."""
+    contracted mode too (both fuse Mul+Sub into one FMA, then divide)."""
     say("config0 static vs runtime tier, strict", strict)
     cfg = datagen.config0(seed=1, frame_hw=(300, 500), crop=(7, 9, 333, 201), out=(100, 60))
     dframes = to_dev(cfg["frames"])
@@ -224,6 +224,33 @@ def test_frame_with_row_padding():
     with Plan(chain, 1, strict=True) as p:
         o = host(p.run([dview], [it]))[0]
     assert_bitexact(o, ref["out"], "padded pitch")
+
+
+def test_frame_rows_of_16_mib_take_64_bit_offsets():
+    """A pitch of 2^24 bytes puts the frame outside the 32-bit row-offset
+    form (IF_SMALL_FRAME): the crop+resize reads through 64-bit offsets and
+    still matches the oracle bit for bit."""
+    say("frame with a 16 MiB pitch")
+    g = datagen.rng(17)
+    H, W = 5, 64
+    img = datagen.frame(g, H, W, 3)
+    dbig = torch.zeros((H, 1 << 24), dtype=torch.uint8, device="cuda:0")
+    dbig[:, :W * 3] = torch.from_numpy(img.reshape(H, W * 3)).to("cuda:0")
+    dview = dbig[:, :W * 3].unflatten(1, (W, 3))
+    assert dview.stride(0) == 1 << 24
+    chain = datagen.normalize_chain(24, 9)
+    items = [{"frame": 0, "x": 3, "y": 1, "w": 50, "h": 4, "out_w": 24, "out_h": 9},
+             {"frame": 0, "x": 0, "y": 0, "w": 64, "h": 5, "out_w": 7, "out_h": 3}]
+    refs = oracle.run_chain(chain, [img], items)
+    for strict in (True, False):
+        with Plan(chain, 2, strict=strict) as p:
+            outs = host(p.run([dview], items))
+        for b in range(2):
+            if strict:
+                assert_bitexact(outs[b], refs[b]["out"], f"item {b}")
+            else:
+                assert_close(outs[b], refs[b], s_floor=1.0, what=f"item {b}")
+    del dbig
 
 
 def test_single_pixel_and_extreme_scales():
