@@ -216,7 +216,7 @@ bool fk::config_valid(const fk_launch_config &c)
     return t && k;
 }
 
-const void *fk::plan_kernel(const fk_plan *p, const fk_launch_config &cfg)
+const void *fk::plan_kernel(const fk_plan *p, const fk_launch_config &cfg, bool large)
 {
     if (p->chain.write.layout == FK_STATS) {
         if (p->chain.read.kind == FK_READ_PLAIN && p->chain.read.in_dtype == FK_U8 && p->ops.empty())
@@ -225,7 +225,11 @@ const void *fk::plan_kernel(const fk_plan *p, const fk_launch_config &cfg)
                             cfg.coarsen);
     }
     switch (p->family) {
-    case FAM_NORMALIZE: return kernel_normalize(cfg.coarsen, p->opts.strict_fp);
+    case FAM_NORMALIZE:
+        // measured: 4-pixel units win on small, latency-bound launches
+        // (B <= 50 crops of 64x128); pixel-strided lanes from about 1M
+        // output pixels on (B = 256: 16.0 vs 20.1 us)
+        return kernel_normalize(cfg.coarsen, p->opts.strict_fp, large);
     case FAM_MULADD: return kernel_muladd(p->static_n, cfg.coarsen, p->opts.strict_fp);
     case FAM_MULADD_LOOP:
         if (per_pixel(p))
@@ -365,7 +369,7 @@ extern "C" fk_status fk_plan_create(const fk_chain_desc *chain, int32_t max_batc
         }
         for (int k : {1, 2, 4, 8}) {
             fk_launch_config c = {256, k};
-            if (!plan_kernel(p, c)) {
+            if (!plan_kernel(p, c, false) || !plan_kernel(p, c, true)) {
                 plan_free(p);
                 return set_error(FK_ERR_UNSUPPORTED, "no kernel built for this chain");
             }
@@ -550,7 +554,10 @@ static hipError_t launch_one(const void *fn, dim3 grid, dim3 block, void **args,
 fk_status fk::launch_args(const fk_plan *p, const fk_launch_config &cfg, KArgs &a, uint32_t grid,
                           int32_t n_items, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1)
 {
-    const void *fn = plan_kernel(p, cfg);
+    // output pixels the launch covers: grid blocks of T * K units of 4 pixels
+    const bool large = (uint64_t)grid * (uint64_t)cfg.block_threads * (uint64_t)cfg.coarsen * kUnitPx >=
+                       kStridedMinPixels;
+    const void *fn = plan_kernel(p, cfg, large);
     if (!fn)
         return set_error(FK_ERR_UNSUPPORTED, "no kernel for coarsening %d", cfg.coarsen);
     const bool stats = p->chain.write.layout == FK_STATS;

@@ -51,7 +51,9 @@ fk_status validate_chain(const fk_chain_desc *ch);
 fk_status validate_items(const fk_chain_desc *ch, const fk_item *items, int32_t n);
 bool config_valid(const fk_launch_config &c);
 bool per_pixel(const fk_plan *p);
-const void *plan_kernel(const fk_plan *p, const fk_launch_config &cfg);
+// The plan's kernel for a launch configuration; `large`: the launch covers
+// at least kStridedMinPixels output pixels.
+const void *plan_kernel(const fk_plan *p, const fk_launch_config &cfg, bool large = true);
 size_t lds_bytes(const fk_plan *p, const fk_launch_config &cfg);
 uint32_t build_items(const fk_plan *p, const fk_item *items, int32_t n, const fk_launch_config &cfg,
                      ItemRec *recs, uint32_t *tb, int32_t batch_n = 0);

@@ -140,7 +140,10 @@ enum : int32_t {
 // combination is not built.
 const void *kernel_runtime(int read_kind, int in_dt, int channels, int out_dt, int layout,
                            int coarsen);
-const void *kernel_normalize(int coarsen, int strict);
+// strided: pixel-strided lanes (launches of at least kStridedMinPixels
+// output pixels), else 4-pixel units
+const void *kernel_normalize(int coarsen, int strict, int strided);
+constexpr uint64_t kStridedMinPixels = 1u << 20;
 const void *kernel_muladd(int n_ops, int coarsen, int strict);
 const void *kernel_muladd_loop(int in_dt, int channels, int coarsen, int strict);
 const void *kernel_loop_px(int in_dt, int channels, int coarsen, int strict);

@@ -66,21 +66,24 @@ const void *kernel_runtime(int read_kind, int in_dt, int channels, int out_dt, i
     return nullptr;
 }
 
-// Crop+resize u8x3 -> swap, cvt, *k, -mean, /std -> planar fp32, with
-// pixel-strided lanes for the gather.
+// Crop+resize u8x3 -> swap, cvt, *k, -mean, /std -> planar fp32: 4-pixel
+// units, or pixel-strided lanes for the gather of large launches.
 template <bool Strict, int K>
-static const void *norm_ptr()
+static const void *norm_ptr(bool strided)
 {
-    return (const void *)&k_resize_px<StaticCompute<NormalizeChain<Strict>>, DT_F32, 3, K>;
+    if (strided)
+        return (const void *)&k_resize_px<StaticCompute<NormalizeChain<Strict>>, DT_F32, 3, K>;
+    return (const void *)&k_transform<ReadCropResize<DT_U8, 3>, StaticCompute<NormalizeChain<Strict>>,
+                                      WritePlanar<DT_F32, 3>, 3, K>;
 }
 
-const void *kernel_normalize(int coarsen, int strict)
+const void *kernel_normalize(int coarsen, int strict, int strided)
 {
     switch (coarsen) {
-    case 1: return strict ? norm_ptr<true, 1>() : norm_ptr<false, 1>();
-    case 2: return strict ? norm_ptr<true, 2>() : norm_ptr<false, 2>();
-    case 4: return strict ? norm_ptr<true, 4>() : norm_ptr<false, 4>();
-    case 8: return strict ? norm_ptr<true, 8>() : norm_ptr<false, 8>();
+    case 1: return strict ? norm_ptr<true, 1>(strided) : norm_ptr<false, 1>(strided);
+    case 2: return strict ? norm_ptr<true, 2>(strided) : norm_ptr<false, 2>(strided);
+    case 4: return strict ? norm_ptr<true, 4>(strided) : norm_ptr<false, 4>(strided);
+    case 8: return strict ? norm_ptr<true, 8>(strided) : norm_ptr<false, 8>(strided);
     }
     return nullptr;
 }
