@@ -276,6 +276,17 @@ struct ReadCropResize {
         }
     }
 
+    // one output pixel on its own (pixel-strided lanes); prep = window_ok
+    __device__ __forceinline__ static bool px_prep(const ItemRec &it) { return window_ok(it); }
+    __device__ __forceinline__ static void load_px(const ItemRec &it, bool win, int oy, int ox,
+                                                   float (&r)[C])
+    {
+        gsrc_t r0, r1;
+        float ay;
+        rows(it, oy, r0, r1, ay);
+        pixel(it, r0, r1, ay, ox, win, r);
+    }
+
     __device__ __forceinline__ static void load(const ItemRec &it, int oy, int ox0, int n,
                                                 float (&r)[kUnitPx][C])
     {
@@ -317,19 +328,35 @@ struct ReadCropNearest {
     static constexpr int kind = RD_CROP_NEAREST;
     static constexpr int elem_size = DSize<DT>::v;
 
-    __device__ __forceinline__ static void load(const ItemRec &it, int oy, int ox0, int n,
-                                                float (&r)[kUnitPx][C])
+    // the ROI row holding output row oy's source pixels
+    __device__ __forceinline__ static gsrc_t row_of(const ItemRec &it, int oy)
     {
         constexpr int ES = DSize<DT>::v;
         const int sy = nearest_index(oy, it.h, it.oh);
-        gsrc_t row = (gsrc_t)it.src + (int64_t)(it.y + sy) * it.pitch + (int64_t)it.x * (C * ES);
+        return (gsrc_t)it.src + (int64_t)(it.y + sy) * it.pitch + (int64_t)it.x * (C * ES);
+    }
+    __device__ __forceinline__ static void pixel(const ItemRec &it, gsrc_t row, int ox, float (&r)[C])
+    {
+        constexpr int ES = DSize<DT>::v;
+        const int sx = nearest_index(ox, it.w, it.ow);
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            r[c] = load_elem<DT>(row + (sx * C + c) * ES);
+    }
+    __device__ __forceinline__ static bool px_prep(const ItemRec &) { return false; }
+    __device__ __forceinline__ static void load_px(const ItemRec &it, bool, int oy, int ox, float (&r)[C])
+    {
+        pixel(it, row_of(it, oy), ox, r);
+    }
+
+    __device__ __forceinline__ static void load(const ItemRec &it, int oy, int ox0, int n,
+                                                float (&r)[kUnitPx][C])
+    {
+        gsrc_t row = row_of(it, oy);
 #pragma unroll
         for (int i = 0; i < kUnitPx; ++i) {
             if (i < n) {
-                const int sx = nearest_index(ox0 + i, it.w, it.ow);
-#pragma unroll
-                for (int c = 0; c < C; ++c)
-                    r[i][c] = load_elem<DT>(row + (sx * C + c) * ES);
+                pixel(it, row, ox0 + i, r[i]);
             } else {
 #pragma unroll
                 for (int c = 0; c < C; ++c)
@@ -369,6 +396,12 @@ struct ReadNV12 {
     static constexpr int kind = RD_NV12;
     static constexpr int elem_size = 1;
 
+    __device__ __forceinline__ static bool px_prep(const ItemRec &) { return false; }
+    __device__ __forceinline__ static void load_px(const ItemRec &it, bool, int oy, int ox, float (&r)[C])
+    {
+        nv12_pixel(it, it.x + ox, it.y + oy, r);
+    }
+
     __device__ __forceinline__ static void load(const ItemRec &it, int oy, int ox0, int n,
                                                 float (&r)[kUnitPx][C])
     {
@@ -393,6 +426,34 @@ struct ReadNV12Resize {
     static constexpr int kind = RD_NV12_RESIZE;
     static constexpr int elem_size = 1;
 
+    // output column ox of the output row whose source rows are y0, y1
+    __device__ __forceinline__ static void pixel(const ItemRec &it, int y0, int y1, float ay, int ox,
+                                                 float (&r)[C])
+    {
+        int x0, x1;
+        float ax;
+        bilinear_coord(ox, it.sx, it.w, x0, x1, ax);
+        float p00[3], p01[3], p10[3], p11[3];
+        nv12_pixel(it, it.x + x0, it.y + y0, p00);
+        nv12_pixel(it, it.x + x1, it.y + y0, p01);
+        nv12_pixel(it, it.x + x0, it.y + y1, p10);
+        nv12_pixel(it, it.x + x1, it.y + y1, p11);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const float top = fmaf(ax, p01[c] - p00[c], p00[c]);
+            const float bot = fmaf(ax, p11[c] - p10[c], p10[c]);
+            r[c] = fmaf(ay, bot - top, top);
+        }
+    }
+    __device__ __forceinline__ static bool px_prep(const ItemRec &) { return false; }
+    __device__ __forceinline__ static void load_px(const ItemRec &it, bool, int oy, int ox, float (&r)[C])
+    {
+        int y0, y1;
+        float ay;
+        bilinear_coord(oy, it.sy, it.h, y0, y1, ay);
+        pixel(it, y0, y1, ay, ox, r);
+    }
+
     __device__ __forceinline__ static void load(const ItemRec &it, int oy, int ox0, int n,
                                                 float (&r)[kUnitPx][C])
     {
@@ -402,20 +463,7 @@ struct ReadNV12Resize {
 #pragma unroll
         for (int i = 0; i < kUnitPx; ++i) {
             if (i < n) {
-                int x0, x1;
-                float ax;
-                bilinear_coord(ox0 + i, it.sx, it.w, x0, x1, ax);
-                float p00[3], p01[3], p10[3], p11[3];
-                nv12_pixel(it, it.x + x0, it.y + y0, p00);
-                nv12_pixel(it, it.x + x1, it.y + y0, p01);
-                nv12_pixel(it, it.x + x0, it.y + y1, p10);
-                nv12_pixel(it, it.x + x1, it.y + y1, p11);
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    const float top = fmaf(ax, p01[c] - p00[c], p00[c]);
-                    const float bot = fmaf(ax, p11[c] - p10[c], p10[c]);
-                    r[i][c] = fmaf(ay, bot - top, top);
-                }
+                pixel(it, y0, y1, ay, ox0 + i, r[i]);
             } else {
 #pragma unroll
                 for (int c = 0; c < C; ++c)
@@ -1055,9 +1103,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_transform(const KArgs a)
     }
 }
 
-// ----------------------------------------- crop+resize, pixel-strided lanes --
-// The transform pattern for a bilinear crop+resize with a planar write,
-// laid out for the gather: lane t of a tile takes output pixels
+// ----------------------------------------- gathers, pixel-strided lanes --
+// The transform pattern for a gathering read (bilinear or nearest crop+
+// resize, NV12) with a planar write, laid out for the gather: lane t of a
+// tile takes output pixels
 // pbase + q * T + t (q < 4K) instead of K units of 4 adjacent pixels.  Each
 // gather instruction of a wave then reads the taps of 64 consecutive output
 // pixels, a segment of one or two source rows, instead of 64 units spread
@@ -1065,10 +1114,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_transform(const KArgs a)
 // instruction.  Tiles are those of k_transform (T * K units = 4 T K
 // pixels); the per-pixel planar stores of consecutive lanes are
 // consecutive.
-template <class Compute, int DO, int C, int K>
+template <class Read, class Compute, int DO, int C, int K>
 __global__ __launch_bounds__(kMaxBlock) void k_resize_px(const KArgs a)
 {
-    using Read = ReadCropResize<DT_U8, C>;
     constexpr int ES = DSize<DO>::v;
     const FK_CONST KArgs *ka = (const FK_CONST KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
     const bool inl = a.inl_n > 0;
@@ -1091,7 +1139,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_resize_px(const KArgs a)
         const uint32_t pbase = ubase * kUnitPx;
         const RowDiv rowdiv((uint32_t)it.ow);  // exact below 2^28 pixels
         const bool big = npx >= (1u << 28);
-        const bool win = Read::window_ok(it);
+        const bool prep = Read::px_prep(it);
 
         const int64_t plane = (int64_t)it.ow * it.oh;
         gdst_t dst = (gdst_t)it.dst;
@@ -1108,10 +1156,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_resize_px(const KArgs a)
                     const uint32_t row = big ? p / (uint32_t)it.ow : rowdiv(p);
                     oy[i] = (int)row;
                     ox[i] = (int)(p - __umul24(row, (uint32_t)it.ow));
-                    gsrc_t r0, r1;
-                    float ay;
-                    Read::rows(it, oy[i], r0, r1, ay);
-                    Read::pixel(it, r0, r1, ay, ox[i], win, v[0][i]);
+                    Read::load_px(it, prep, oy[i], ox[i], v[0][i]);
                 } else {
                     oy[i] = -1;
                     ox[i] = 0;

@@ -21,6 +21,9 @@ constexpr bool rd_resizes(int rk) { return rk == RD_CROP_RESIZE || rk == RD_CROP
 constexpr bool rd_bilinear(int rk) { return rk == RD_CROP_RESIZE || rk == RD_NV12_RESIZE; }
 enum : int32_t { DT_U8 = 0, DT_F16 = 1, DT_F32 = 2 };
 enum : int32_t { LY_PACKED = 0, LY_PLANAR = 1, LY_STATS = 2 };
+// Kernel selection only: a planar write from pixel-strided lanes (bilinear
+// reads on launches of at least kStridedMinPixels output pixels).
+enum : int32_t { LY_PLANAR_PX = 3 };
 
 // Normalised compute op codes.  SUB becomes ADD of the negated constant
 // (IEEE x - y is x + (-y)), CVT disappears (fp32 from the read on), swaps

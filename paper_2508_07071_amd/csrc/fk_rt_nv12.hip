@@ -20,8 +20,23 @@ static const void *pick_k(int k)
     return nullptr;
 }
 template <int RK, int DO>
+static const void *pick_px(int k)
+{
+    switch (k) {
+    case 1: return (const void *)&k_resize_px<NV12Read<RK>, RuntimeCompute, DO, 3, 1>;
+    case 2: return (const void *)&k_resize_px<NV12Read<RK>, RuntimeCompute, DO, 3, 2>;
+    case 4: return (const void *)&k_resize_px<NV12Read<RK>, RuntimeCompute, DO, 3, 4>;
+    case 8: return (const void *)&k_resize_px<NV12Read<RK>, RuntimeCompute, DO, 3, 8>;
+    }
+    return nullptr;
+}
+template <int RK, int DO>
 static const void *pick_ly(int ly, int k)
 {
+    if constexpr (RK == RD_NV12_RESIZE) {
+        if (ly == LY_PLANAR_PX)
+            return pick_px<RK, DO>(k);
+    }
     return ly == LY_PLANAR ? pick_k<RK, DO, LY_PLANAR>(k) : pick_k<RK, DO, LY_PACKED>(k);
 }
 template <int RK>

@@ -1,4 +1,5 @@
-// fk_rt_resize_f32.hip -- instantiations of the fused transform kernel: run-time op list, resize read of f32 frames.
+// fk_rt_resize_f32.hip -- instantiations of the fused transform kernel: run-time op list, resize read of f32 frames
+// (4-pixel units, and pixel-strided lanes for planar writes).
 #include "fk_device.hpp"
 
 namespace fk {
@@ -20,8 +21,21 @@ static const void *pick_k(int k)
     return nullptr;
 }
 template <int RK, int DI, int C, int DO>
+static const void *pick_px(int k)
+{
+    switch (k) {
+    case 1: return (const void *)&k_resize_px<ReadCropResize<DI, C>, RuntimeCompute, DO, C, 1>;
+    case 2: return (const void *)&k_resize_px<ReadCropResize<DI, C>, RuntimeCompute, DO, C, 2>;
+    case 4: return (const void *)&k_resize_px<ReadCropResize<DI, C>, RuntimeCompute, DO, C, 4>;
+    case 8: return (const void *)&k_resize_px<ReadCropResize<DI, C>, RuntimeCompute, DO, C, 8>;
+    }
+    return nullptr;
+}
+template <int RK, int DI, int C, int DO>
 static const void *pick_ly(int ly, int k)
 {
+    if (ly == LY_PLANAR_PX)
+        return pick_px<RK, DI, C, DO>(k);
     return ly == LY_PLANAR ? pick_k<RK, DI, C, DO, LY_PLANAR>(k) : pick_k<RK, DI, C, DO, LY_PACKED>(k);
 }
 template <int RK, int DI, int C>

@@ -72,7 +72,8 @@ template <bool Strict, int K>
 static const void *norm_ptr(bool strided)
 {
     if (strided)
-        return (const void *)&k_resize_px<StaticCompute<NormalizeChain<Strict>>, DT_F32, 3, K>;
+        return (const void *)&k_resize_px<ReadCropResize<DT_U8, 3>, StaticCompute<NormalizeChain<Strict>>,
+                                          DT_F32, 3, K>;
     return (const void *)&k_transform<ReadCropResize<DT_U8, 3>, StaticCompute<NormalizeChain<Strict>>,
                                       WritePlanar<DT_F32, 3>, 3, K>;
 }

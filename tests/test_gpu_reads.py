@@ -113,3 +113,32 @@ def test_stats_over_nearest_and_nv12_reads():
             np.testing.assert_array_equal(o[:, :2], s_["out"][:, :2])
             bound = 2 * (n - 1) * 2.0 ** -53 * np.abs(v).sum(0)
             assert np.all(np.abs(o[:, 2] - s_["out"][:, 2]) <= bound), (read["kind"], b)
+
+
+@pytest.mark.parametrize("kind,dtype,C,out_dtype", [
+    ("crop_nearest", "u8", 3, "f32"), ("crop_nearest", "f16", 1, "f16"), ("crop_nearest", "f32", 4, "f32"),
+    ("crop_resize", "u8", 3, "f16"), ("crop_resize", "f16", 3, "f32"), ("crop_resize", "f32", 1, "f32"),
+    ("nv12", "u8", 3, "f32"), ("nv12_resize", "u8", 3, "f16")])
+def test_large_planar_gathers_match_oracle(kind, dtype, C, out_dtype):
+    """Launches of at least 2^20 output pixels with a planar write: the
+    bilinear reads take the pixel-strided layout (run-time op list), the
+    others keep 4-pixel units; the same bits as the oracle in the strict
+    mode, within tolerance otherwise, for a large crop and a batch."""
+    say("large planar gather", kind, dtype, C, out_dtype)
+    g = datagen.rng(31 + C + len(kind) + len(dtype))
+    if kind.startswith("nv12"):
+        fr = datagen.nv12_frame(g, 832, 1280)
+        fh, fw = 832, 1280
+    else:
+        fh, fw = 700, 900
+        fr = datagen.frame(g, fh, fw, C, dtype=dtype)
+    if kind == "nv12":
+        items = [{"frame": 0, "x": 0, "y": 0, "w": 1280, "h": 832, "out_w": 1280, "out_h": 832},
+                 {"frame": 0, "x": 7, "y": 3, "w": 333, "h": 101, "out_w": 333, "out_h": 101}]
+    else:
+        items = [{"frame": 0, "x": 11, "y": 5, "w": fw - 30, "h": fh - 21, "out_w": 1100, "out_h": 960}]
+        items += datagen.random_crops(g, 5, fw, fh, lo=3, hi=500, out=(97, 61))
+    ch = {"read": {"kind": kind, "dtype": dtype, "channels": C, "out_w": 0, "out_h": 0},
+          "ops": norm_ops(C), "write": {"dtype": out_dtype, "layout": "planar"}}
+    assert sum(it["out_w"] * it["out_h"] for it in items) >= 1 << 20
+    both_modes(ch, [fr], items, f"large {kind} {dtype}x{C} -> {out_dtype}")
