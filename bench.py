@@ -114,29 +114,13 @@ def vf_sweep(args):
         torch.cuda.synchronize()
         return ev
 
-    for _ in range(args.warmup):
-        step()
-    # timing events are created up front: none is created inside the timed
-    # loop, and only the dominant kernel's launches carry them
-    dom_events = make_events(args.steps)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(dom_events, i)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    kern_ms = {dom: float(np.mean([a.elapsed_time(b) for a, b in dom_events]))}
-    # every other depth's launch time, outside the timed region
-    for n in DEPTHS[:-1]:
-        ev = make_events(args.steps)
-        for i in range(args.steps):
-            step(ev, i, only=n)
-        torch.cuda.synchronize()
-        kern_ms[n] = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    log("kernel ms", {n: round(kern_ms[n], 4) for n in DEPTHS}, "step ms", round(ms_per_step, 4))
-
-    # unfused baseline (outside the timed region): one kernel per op
+    # The baselines and the other depths' launch times are measured first,
+    # outside the timed region.  Run before the warm-up, they also take the
+    # GPU out of its first milliseconds of load, during which the ALU-bound
+    # depth runs up to 12% slower while the clocks settle (measured: the
+    # N = 256 launches of the first 50 steps average 106 us, of the next 50
+    # 98 us, and 94.5-95 us from then on).
+    # unfused baseline: one kernel per op
     unfused_ms = {}
     if not args.no_unfused:
         for n in DEPTHS:
@@ -159,6 +143,30 @@ def vf_sweep(args):
             unfused_ms[n] = float(np.median(ts))
             del scratch
         log("unfused ms", {n: round(v, 3) for n, v in unfused_ms.items()})
+
+    kern_ms = {}
+    # every other depth's launch time (its own launches back to back)
+    for n in DEPTHS[:-1]:
+        ev = make_events(args.steps)
+        for i in range(args.steps):
+            step(ev, i, only=n)
+        torch.cuda.synchronize()
+        kern_ms[n] = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    for _ in range(args.warmup):
+        step()
+    # timing events are created up front: none is created inside the timed
+    # loop, and only the dominant kernel's launches carry them
+    dom_events = make_events(args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(dom_events, i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    kern_ms[dom] = float(np.mean([a.elapsed_time(b) for a, b in dom_events]))
+    log("kernel ms", {n: round(kern_ms[n], 4) for n in DEPTHS}, "step ms", round(ms_per_step, 4))
 
     per_depth = []
     for n in DEPTHS:

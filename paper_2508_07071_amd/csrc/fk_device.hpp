@@ -21,6 +21,11 @@
 // item; thread t handles units tile_base + j * blockDim.x + t (j < K), so
 // every load/store instruction of a wave touches consecutive units.  The
 // grid strides over the tiles of all items (persistent horizontal fusion).
+//
+// Also here: k_resize_px, the same pattern with pixel-strided lanes for the
+// bilinear gathers of large launches; k_loop_px, one pixel per lane for long
+// compile-time loop chains; and the reduction pattern (k_stats, k_stats_u8,
+// k_stats_final).
 #pragma once
 #include <hip/hip_runtime.h>
 
