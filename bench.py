@@ -623,10 +623,15 @@ def sweeps_workload(args):
         return e0.elapsed_time(e1) / reps
 
     def setup(cfg):
+        # one output tensor for the batch (equal item sizes), one view per
+        # item: a constant output stride, as a batched consumer would use
         ch = cfg["chain"]
         frame = torch.from_numpy(cfg["frames"][0]).to(dev)
-        outs = [torch.empty(fk.out_shape(ch, it), dtype=fk.TORCH_DTYPE[ch["write"]["dtype"]], device=dev)
-                for it in cfg["items"]]
+        shape = fk.out_shape(ch, cfg["items"][0])
+        assert all(fk.out_shape(ch, it) == shape for it in cfg["items"])
+        batch_out = torch.empty((len(cfg["items"]),) + tuple(shape), dtype=fk.TORCH_DTYPE[ch["write"]["dtype"]],
+                                device=dev)
+        outs = [batch_out[b] for b in range(len(cfg["items"]))]
         arr = fk.make_items(ch, [frame], cfg["items"], outs)
         plan = fk.fk_plan_create(fk.chain_desc(ch), len(cfg["items"]), fk.plan_opts())
         return ch, frame, outs, arr, plan
@@ -840,7 +845,9 @@ def costmodel_workload(args):
     import paper_2508_07071_amd as fk
     from paper_2508_07071_amd import costmodel as cm
 
-    data = cm.load_shards(args.data)
+    # the committed labelled dataset unless shards are named
+    shards = args.data or [os.path.join(os.path.dirname(cm.__file__), "data", "costmodel_dataset.npz")]
+    data = cm.load_shards(shards)
     model, rep = cm.fit(data, epochs=args.epochs)
     out = {"workload": "cost model: 20,000 training / 2,000 held-out random chains", "report": rep}
     if not args.no_cpu_baseline:
@@ -895,7 +902,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="vf", choices=["vf", "hf", "loop", "stats", "sweeps", "reads", "copy", "serve", "costmodel"])
-    ap.add_argument("--data", nargs="+", default=[], help="cost-model label shards")
+    ap.add_argument("--data", nargs="+", default=[],
+                    help="cost-model label shards (default: the committed dataset)")
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--rates", type=float, nargs="+", default=[200, 500, 1000, 2000])
     ap.add_argument("--serve-seconds", type=float, default=2.0)
