@@ -614,6 +614,61 @@ bool fk::compact_batch(const fk_plan *p, const fk_item *items, int32_t n)
     return true;
 }
 
+// One compact kernel-argument launch of n items (1 <= n <= kCompactItems)
+// that share the template of items[0]; item b's output is items[0].dst +
+// b * stride.  batch_n is the batch size the per-item tiling assumes.
+static fk_status launch_compact(const fk_plan *p, const fk_item *items, int32_t n, intptr_t stride,
+                                int32_t batch_n, const fk_launch_config &cfg, hipStream_t stream,
+                                hipEvent_t ev0, hipEvent_t ev1)
+{
+    KArgs a = make_args(p, nullptr);
+    a.hdr = nullptr;
+    a.items = nullptr;
+    a.tile_begin = nullptr;
+    a.inl_n = n;
+    a.inl_compact = 1;
+    uint32_t tb[2];
+    ItemRec &t = *(ItemRec *)a.inl;
+    a.inl_tiles_per_item = build_items(p, items, 1, cfg, &t, tb, batch_n);
+    a.inl_total_tiles = a.inl_tiles_per_item * (uint32_t)n;
+    a.inl_dst_stride = (int64_t)stride;
+    // template flags: frame base and pitch dword-aligned; outputs aligned
+    // for every item (base and stride multiples of 16)
+    t.flags = 0;
+    if ((uintptr_t)items[0].src.ptr % 4 == 0 && items[0].src.pitch_bytes % 4 == 0)
+        t.flags |= IF_SRC_VEC;
+    if (t.ow % kUnitPx == 0 && (uintptr_t)items[0].dst % 16 == 0 && a.inl_dst_stride % 16 == 0)
+        t.flags |= IF_DST_VEC;
+    if (small_frame(items[0].src))
+        t.flags |= IF_SMALL_FRAME;
+    Roi16 *roi = (Roi16 *)(a.inl + 64);
+    for (int32_t b = 0; b < n; ++b)
+        roi[b] = Roi16{(uint16_t)items[b].x, (uint16_t)items[b].y, (uint16_t)items[b].w,
+                       (uint16_t)items[b].h};
+    const uint32_t grid = std::min<uint32_t>(a.inl_total_tiles, 1u << 20);
+    return launch_args(p, cfg, a, grid, n, stream, ev0, ev1);
+}
+
+static_assert(sizeof(RunHeader) % 16 == 0 && sizeof(ItemRec) % 16 == 0,
+              "the run table uploads in 16-byte units");
+
+// Queue the copy of a slot's table to the device: the header, items
+// [0, n) and tile_begin[0 .. n], in 16-byte units (the prefix sums rounded
+// up; the table's size is a multiple of 256 bytes, so the rounding stays
+// inside it).
+static hipError_t upload_table(const fk_plan *p, const fk_plan::Slot &sl, int32_t n,
+                               hipStream_t stream)
+{
+    uint32_t n0 = (uint32_t)((sizeof(RunHeader) + sizeof(ItemRec) * (size_t)n) / 16);
+    uint32_t off1 = (uint32_t)((sizeof(RunHeader) + sizeof(ItemRec) * (size_t)p->max_batch) / 16);
+    uint32_t n1 = (uint32_t)((sizeof(uint32_t) * ((size_t)n + 1) + 15) / 16);
+    const void *src = sl.h_dev;
+    void *dst = sl.d_table;
+    void *args[] = {&src, &dst, &n0, &off1, &n1};
+    return hipLaunchKernel(kernel_table_upload(), dim3((n0 + n1 + 255) / 256), dim3(256), args, 0,
+                           stream);
+}
+
 fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_launch_config &cfg,
                         bool graph, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1)
 {
@@ -629,39 +684,32 @@ fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_la
         const uint32_t grid = std::min<uint32_t>(a.inl_total_tiles, 1u << 20);
         return launch_args(p, cfg, a, grid, n, stream, ev0, ev1);
     }
-    if (!graph && n <= kCompactItems && compact_batch(p, items, n)) {
-        KArgs a = make_args(p, nullptr);
-        a.hdr = nullptr;
-        a.items = nullptr;
-        a.tile_begin = nullptr;
-        a.inl_n = n;
-        a.inl_compact = 1;
-        uint32_t tb[2];
-        ItemRec &t = *(ItemRec *)a.inl;
-        a.inl_tiles_per_item = build_items(p, items, 1, cfg, &t, tb, n);
-        a.inl_total_tiles = a.inl_tiles_per_item * (uint32_t)n;
-        a.inl_dst_stride = (int64_t)((uintptr_t)items[1].dst - (uintptr_t)items[0].dst);
-        // template flags: frame base and pitch dword-aligned; outputs aligned
-        // for every item (base and stride multiples of 16)
-        t.flags = 0;
-        if ((uintptr_t)items[0].src.ptr % 4 == 0 && items[0].src.pitch_bytes % 4 == 0)
-            t.flags |= IF_SRC_VEC;
-        if (t.ow % kUnitPx == 0 && (uintptr_t)items[0].dst % 16 == 0 && a.inl_dst_stride % 16 == 0)
-            t.flags |= IF_DST_VEC;
-        if (small_frame(items[0].src))
-            t.flags |= IF_SMALL_FRAME;
-        Roi16 *roi = (Roi16 *)(a.inl + 64);
-        for (int32_t b = 0; b < n; ++b)
-            roi[b] = Roi16{(uint16_t)items[b].x, (uint16_t)items[b].y, (uint16_t)items[b].w,
-                           (uint16_t)items[b].h};
-        const uint32_t grid = std::min<uint32_t>(a.inl_total_tiles, 1u << 20);
-        return launch_args(p, cfg, a, grid, n, stream, ev0, ev1);
+    if (!graph && compact_batch(p, items, n)) {
+        const intptr_t stride = (intptr_t)items[1].dst - (intptr_t)items[0].dst;
+        if (n <= kCompactItems)
+            return launch_compact(p, items, n, stride, n, cfg, stream, ev0, ev1);
+        if (p->chain.write.layout != FK_STATS) {
+            // beyond one launch's argument capacity: consecutive compact
+            // launches of up to kCompactItems items, still no table copy
+            for (int32_t b0 = 0; b0 < n; b0 += kCompactItems) {
+                const int32_t m = std::min(n - b0, kCompactItems);
+                fk_status s = launch_compact(p, items + b0, m, stride, m, cfg, stream,
+                                             b0 == 0 ? ev0 : nullptr, b0 + m == n ? ev1 : nullptr);
+                if (s)
+                    return s;
+            }
+            return FK_OK;
+        }
     }
     fk_plan::Slot &sl = p->slots[p->next_slot];
     p->next_slot = (p->next_slot + 1) % fk_plan::kRing;
     hipError_t e = hipSuccess;
     if (!sl.h_stage) {  // the table ring is allocated on first use
-        e = hipHostMalloc(&sl.h_stage, p->table_bytes, hipHostMallocDefault);
+        // coherent: the upload kernel reads each byte once, straight from
+        // host memory, after the host has rewritten the slot
+        e = hipHostMalloc(&sl.h_stage, p->table_bytes, hipHostMallocMapped | hipHostMallocCoherent);
+        if (e == hipSuccess)
+            e = hipHostGetDevicePointer(&sl.h_dev, sl.h_stage, 0);
         if (e == hipSuccess)
             e = hipMalloc(&sl.d_table, p->table_bytes);
         if (e == hipSuccess)
@@ -685,8 +733,6 @@ fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_la
     const uint32_t tiles = build_table(p, items, n, cfg, sl.h_stage);
     if (tiles == 0)
         return FK_OK;
-    const size_t used = sizeof(RunHeader) + sizeof(ItemRec) * (size_t)p->max_batch +
-                        sizeof(uint32_t) * ((size_t)n + 1);
     if (graph) {
         const bool stale = !sl.gexec || sl.gcfg.block_threads != cfg.block_threads ||
                            sl.gcfg.coarsen != cfg.coarsen;
@@ -699,15 +745,14 @@ fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_la
             e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess)
                 return hip_error(e, "hipStreamBeginCapture");
-            e = hipMemcpyAsync(sl.d_table, sl.h_stage, p->table_bytes, hipMemcpyHostToDevice,
-                               p->capture_stream);
+            e = upload_table(p, sl, p->max_batch, p->capture_stream);
             fk_status s = FK_OK;
             if (e == hipSuccess)
                 s = launch(p, cfg, sl.d_table, persistent_grid(p, cfg), std::min(p->max_batch, 4096),
                            p->capture_stream);
             hipError_t e2 = hipStreamEndCapture(p->capture_stream, &g);
             if (e != hipSuccess)
-                return hip_error(e, "hipMemcpyAsync (capture)");
+                return hip_error(e, "table upload (capture)");
             if (s)
                 return s;
             if (e2 != hipSuccess)
@@ -727,9 +772,9 @@ fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_la
         if (e != hipSuccess)
             return hip_error(e, "hipGraphLaunch");
     } else {
-        e = hipMemcpyAsync(sl.d_table, sl.h_stage, used, hipMemcpyHostToDevice, stream);
+        e = upload_table(p, sl, n, stream);
         if (e != hipSuccess)
-            return hip_error(e, "hipMemcpyAsync");
+            return hip_error(e, "table upload");
         const uint32_t grid = std::min<uint32_t>(tiles, 1u << 20);
         fk_status s = launch(p, cfg, sl.d_table, grid, n, stream, ev0, ev1);
         if (s)

@@ -13,6 +13,7 @@ struct fk_plan {
     static constexpr int kRing = 4;  // item tables in flight
     struct Slot {
         void *h_stage = nullptr;      // pinned host staging of the run table
+        void *h_dev = nullptr;        // the staging buffer's device address
         void *d_table = nullptr;      // device run table
         hipEvent_t done = nullptr;    // recorded after the slot's last launch
         bool used = false;
@@ -67,6 +68,7 @@ fk_status launch(const fk_plan *p, const fk_launch_config &cfg, void *d_table, u
                  int32_t n_items, hipStream_t stream, hipEvent_t ev0 = nullptr,
                  hipEvent_t ev1 = nullptr);
 bool compact_batch(const fk_plan *p, const fk_item *items, int32_t n);
+const void *kernel_table_upload();  // fk_table.hip
 fk_status run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_launch_config &cfg,
                     bool graph, hipStream_t stream, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 

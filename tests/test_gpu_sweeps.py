@@ -54,6 +54,34 @@ def test_plain_batch_1191_images_sampled():
     both_modes(cfg, "B=1191", sample=[0, 1, 500, 1189, 1190])
 
 
+@pytest.mark.parametrize("batch", [625, 1191])
+def test_plain_batch_one_output_tensor_chunked(batch):
+    """Items written into one output tensor at a constant stride: a batch
+    above one launch's kernel-argument capacity (312 items) goes out as
+    consecutive kernel-argument launches.  The items on both sides of every
+    launch boundary, and a last launch of one item (625 = 2 x 312 + 1),
+    match the oracle."""
+    import torch
+    from fkhelpers import device
+    say("plain-read batch, one output tensor", batch)
+    cfg = datagen.cast_chain_batch(batch, seed=5)
+    items = cfg["items"]
+    idx = sorted({0, batch - 1} | {b for k in range(312, batch, 312) for b in (k - 1, k)})
+    refs = oracle.run_chain(cfg["chain"], cfg["frames"], [items[i] for i in idx])
+    dframes = to_dev(cfg["frames"])
+    shape = fk.out_shape(cfg["chain"], items[0])
+    for strict in (True, False):
+        big = torch.full((batch,) + tuple(shape), float("nan"), dtype=torch.float32, device=device())
+        with Plan(cfg["chain"], batch, strict=strict) as p:
+            outs = host(p.run(dframes, items, outs=[big[b] for b in range(batch)]))
+        for i, r in zip(idx, refs):
+            if strict:
+                assert_bitexact(outs[i], r["out"], f"B={batch} strict item {i}")
+            else:
+                assert_close(outs[i], r, what=f"B={batch} item {i}")
+        assert not np.isnan(np.stack(outs)).any(), "an item was not written"
+
+
 @pytest.mark.parametrize("per_op", [1, 7, 100, 500])
 def test_instructions_per_op_fused_and_one_kernel_per_op(per_op):
     """500 multiplications as ops of `per_op` instructions (looped Mul ops):
