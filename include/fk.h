@@ -241,8 +241,15 @@ fk_status fk_plan_get_tier(const fk_plan *plan, int32_t *is_static);
 
 /* Fused execution (asynchronous on `stream`, a hipStream_t; NULL = the
  * default stream): one horizontally and vertically fused launch covering
- * all `n_items` items (1 <= n_items <= max_batch).  `items` is copied
- * before the call returns. */
+ * all `n_items` items (1 <= n_items <= max_batch).  The items' parameters
+ * travel in the kernel arguments (up to 32 items; up to 312 items that
+ * share one frame and one output size and whose outputs lie at a constant
+ * stride), else in a device run table that a small upload kernel fills
+ * on the same stream just before the launch.  A constant-stride batch of
+ * more than 312 items (not a stats write) goes out as consecutive launches
+ * of up to 312 items.  `items` is copied before the call returns; a
+ * table run first waits for the run that used the same table slot four
+ * table runs earlier. */
 fk_status fk_run(fk_plan *plan, const fk_item *items, int32_t n_items, void *stream);
 
 /* fk_run with the launch's device time: `start_event` and `stop_event`
@@ -250,8 +257,10 @@ fk_status fk_run(fk_plan *plan, const fk_item *items, int32_t n_items, void *str
  * are recorded by the fused launch itself as its kernel starts and ends
  * (hipExtLaunchKernel), so hipEventElapsedTime gives the kernel's
  * duration without the latency of separate event markers.  A stats write
- * brackets both of its kernels; a plan that replays a graph records the
- * events around the graph launch.  Either event may be NULL. */
+ * brackets both of its kernels, a batch split into several launches the
+ * first and the last; the table upload kernel stays outside.  A plan that
+ * replays a graph records the events around the graph launch.  Either
+ * event may be NULL. */
 fk_status fk_run_timed(fk_plan *plan, const fk_item *items, int32_t n_items, void *stream,
                        void *start_event, void *stop_event);
 

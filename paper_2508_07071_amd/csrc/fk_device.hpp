@@ -984,13 +984,43 @@ __device__ __forceinline__ int find_item(const FK_CONST uint32_t *tb, int n_item
     return lo;
 }
 
+// The same search for a transform tile (tile < total = tb[n_items]).  The
+// first probe is where the tile would fall if every item had the same
+// number of tiles, which is exact for a batch of equal items: one pair of
+// adjacent offsets instead of a search.  A miss leaves the search on one
+// side of the probe.  tb holds n_items + 1 offsets.  Up to 4 items the
+// plain search takes at most two loads and no division (one item: none).
+__device__ __forceinline__ int find_item_guess(const FK_CONST uint32_t *tb, int n_items,
+                                               uint32_t tile, uint32_t total)
+{
+    if (n_items <= 4)
+        return find_item(tb, n_items, tile);
+    int lo = 0, hi = n_items - 1;
+    const int g = (int)(((uint64_t)tile * (uint64_t)n_items) / total);  // 0 <= g < n_items
+    if (tb[g] <= tile) {
+        if (tb[g + 1] > tile)
+            return g;
+        lo = g + 1;
+    } else {
+        hi = g - 1;
+    }
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tb[mid] <= tile)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 // The item owning `tile` (with the compact form's per-item fields filled
 // in), and the tile's first unit within it.
 template <class Read, int C>
 __device__ __forceinline__ void tile_item(const KArgs &a, const FK_CONST KArgs *ka, bool compact,
                                           const FK_CONST uint32_t *tb, const FK_CONST ItemRec *items,
-                                          int n_items, uint32_t tile, uint32_t tile_units,
-                                          ItemRec &it, uint32_t &ubase)
+                                          int n_items, uint32_t tile, uint32_t total,
+                                          uint32_t tile_units, ItemRec &it, uint32_t &ubase)
 {
     uint32_t first_tile;
     if (compact) {
@@ -1013,7 +1043,7 @@ __device__ __forceinline__ void tile_item(const KArgs &a, const FK_CONST KArgs *
         if ((it.x * C * Read::elem_size) % 4 != 0)
             it.flags &= ~IF_SRC_VEC;
     } else {
-        const int b = find_item(tb, n_items, tile);
+        const int b = find_item_guess(tb, n_items, tile, total);
         it = load_item(items + b);
         first_tile = tb[b];
     }
@@ -1043,7 +1073,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_transform(const KArgs a)
     for (uint32_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
         ItemRec it;
         uint32_t ubase;
-        tile_item<Read, C>(a, ka, compact, tb, items, n_items, tile, tile_units, it, ubase);
+        tile_item<Read, C>(a, ka, compact, tb, items, n_items, tile, total, tile_units, it, ubase);
         const uint32_t upr = (uint32_t)(it.ow + kUnitPx - 1) / kUnitPx;
         const uint32_t units = upr * (uint32_t)it.oh;
         const RowDiv rowdiv(upr);
@@ -1139,7 +1169,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_resize_px(const KArgs a)
     for (uint32_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
         ItemRec it;
         uint32_t ubase;
-        tile_item<Read, C>(a, ka, compact, tb, items, n_items, tile, tile_units, it, ubase);
+        tile_item<Read, C>(a, ka, compact, tb, items, n_items, tile, total, tile_units, it, ubase);
         const uint32_t npx = (uint32_t)it.ow * (uint32_t)it.oh;  // < 2^32
         const uint32_t pbase = ubase * kUnitPx;
         const RowDiv rowdiv((uint32_t)it.ow);  // exact below 2^28 pixels
@@ -1242,7 +1272,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_loop_px(const KArgs a)
             it.h = roi->h;
             it.dst += (uint64_t)b * (uint64_t)a.inl_dst_stride;
         } else {
-            b = find_item(tb, n_items, tile);
+            b = find_item_guess(tb, n_items, tile, total);
             it = load_item(items + b);
             first_tile = tb[b];
         }

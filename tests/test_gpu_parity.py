@@ -161,6 +161,27 @@ def test_graph_replays_match_eager_runs():
                 assert_bitexact(a[i], b[i], f"replay {rep} item {i}")
 
 
+def test_device_table_runs_of_changing_size():
+    """Batches above the kernel-argument forms go through the device table,
+    of which a run uploads only its own n items and n + 1 tile offsets: runs
+    of changing n on one plan (outputs in reverse address order, so no
+    constant stride) match the oracle bit for bit, whatever the earlier runs
+    left in the table ring."""
+    say("device table, changing batch sizes")
+    g = datagen.rng(23)
+    fr = datagen.frame(g, 720, 1280, 3)
+    dframes = to_dev([fr])
+    chain = datagen.normalize_chain(64, 128)
+    with Plan(chain, 200, strict=True) as p:
+        for rep, n in enumerate([200, 45, 120, 33, 200, 57]):
+            items = datagen.random_crops(g, n, 1280, 720)
+            outs = list(reversed(alloc_outs(chain, items)))
+            got = host(p.run(dframes, items, outs=outs))
+            refs = oracle.run_chain(chain, [fr], items)
+            for i in range(n):
+                assert_bitexact(got[i], refs[i]["out"], f"run {rep} (n={n}) item {i}")
+
+
 # --------------------------------------------- general chains and edges --
 
 CASES = [
