@@ -48,6 +48,29 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def timeit(fn, reps=50, warm_s=0.0):
+    """Mean ms per call over `reps` back-to-back calls of fn, bracketed by
+    events on the current stream, after one call and a synchronisation.
+    warm_s > 0 first runs that many seconds of back-to-back calls: right
+    after an autotuning pass (short bursts, each followed by a
+    synchronisation) a 50-call point reads up to twice its steady time,
+    and 2 ms of calls settle it."""
+    import torch
+    t_end = time.perf_counter() + warm_s
+    fn()
+    while time.perf_counter() < t_end:
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def vf_sweep(args):
     import numpy as np
     import torch
@@ -293,18 +316,6 @@ def hf_workload(args):
         alg = taps + B * 3 * 128 * 64 * 4
         alg_rows = rows_b + B * 3 * 128 * 64 * 4
 
-        def timeit(fn, reps=50):
-            for _ in range(5):
-                fn()
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(reps):
-                fn()
-            e1.record()
-            torch.cuda.synchronize()
-            return e0.elapsed_time(e1) / reps
 
         res = {"batch": B, "alg_bytes": alg, "alg_bytes_rows": alg_rows}
         for graph in (False, True):
@@ -315,7 +326,7 @@ def hf_workload(args):
                 cfg_best = best
             else:
                 fk.fk_plan_set_config(h, cfg_best)
-            ms = timeit(lambda: fk.fk_run(h, arr, B, stream))
+            ms = timeit(lambda: fk.fk_run(h, arr, B, stream), warm_s=2e-3)
             res["graph_ms" if graph else "fused_ms"] = round(ms, 4)
             if not graph:
                 singles = [fk.make_items(ch, [frame], [it], [out[b]]) for b, it in enumerate(cfg["items"])]
@@ -406,17 +417,6 @@ def loop_workload(args):
     elems = B * h * w
     alg_bytes = elems * (1 + 4)
 
-    def timeit(fn, reps):
-        fn()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
 
     rows = []
     for P in LOOP_PAIRS:
@@ -519,17 +519,6 @@ def stats_workload(args):
     arr = fk.make_items(chain, frames, items, [stats[f] for f in range(F)])
     alg = F * H * W * 3
 
-    def timeit(fn, reps):
-        fn()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
 
     plan = fk.fk_plan_create(fk.chain_desc(chain), F, fk.plan_opts())
     res = {"frames": F, "alg_bytes": alg}
@@ -538,7 +527,7 @@ def stats_workload(args):
         res["autotuned"] = [best.block_threads, best.coarsen]
     c = fk.fk_plan_get_config(plan)
     res["launch_config"] = [c.block_threads, c.coarsen]
-    res["fused_ms"] = round(timeit(lambda: fk.fk_run(plan, arr, F, stream), 50), 5)
+    res["fused_ms"] = round(timeit(lambda: fk.fk_run(plan, arr, F, stream), 50, warm_s=2e-3), 5)
     res["fused_gbps"] = round(alg / (res["fused_ms"] * 1e-3) / 1e9, 1)
     res["hbm_frac"] = round(res["fused_gbps"] / HBM_PEAK_GBPS, 4)
     # fused transform to fp32, then four library reductions over the image
@@ -597,7 +586,8 @@ def sweeps_workload(args):
                  Mul+Add pairs through the loop op, no batch;
       hf_plain:  B single-channel 60x120 u8 images, Read -> Cast -> Mul ->
                  Sub -> Div -> Write, one batched launch vs one launch per
-                 image vs unfused;
+                 image vs unfused (default configuration), and the
+                 autotuner's own time for its choice and for the default;
       dtypes:    the same chain at B = 50 for six input -> output types;
       instructions_per_op: 500 multiplications as ops of M instructions
                  over 66,355,200 fp32 values, fused vs one kernel per op."""
@@ -610,17 +600,6 @@ def sweeps_workload(args):
     dev = torch.device("cuda:0")
     stream = fk.stream_handle()
 
-    def timeit(fn, reps):
-        fn()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
 
     def setup(cfg):
         # one output tensor for the batch (equal item sizes), one view per
@@ -665,6 +644,14 @@ def sweeps_workload(args):
         if not args.no_unfused:
             r["unfused_ms"] = round(unfused_ms(plan, arr, B, 3), 4)
             r["speedup_vs_unfused"] = round(r["unfused_ms"] / r["fused_ms"], 1)
+        # the autotuner's choice and its own time for it (median of 3
+        # samples of 10 back-to-back launches), next to its time for the
+        # default configuration
+        best, times = fk.fk_autotune(plan, arr, B, 10)
+        space = [(c.block_threads, c.coarsen) for c in fk.fk_autotune_space()]
+        r["autotuned"] = [best.block_threads, best.coarsen]
+        r["autotuned_ms"] = round(min(times), 5)
+        r["tuner_default_ms"] = round(times[space.index((256, 1))], 5)
         fk.fk_plan_destroy(plan)
         log("hf_plain", r)
         hf_plain.append(r)
@@ -734,17 +721,6 @@ def reads_workload(args):
     H, W = FRAME_HW
     g = datagen.rng(args.seed)
 
-    def timeit(fn, reps):
-        fn()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
 
     def measure(ch, frame, items, alg, name, reps=50):
         outs = [torch.empty(fk.out_shape(ch, it), dtype=fk.TORCH_DTYPE[ch["write"]["dtype"]], device=dev)
@@ -754,7 +730,7 @@ def reads_workload(args):
         plan = fk.fk_plan_create(fk.chain_desc(ch), n, fk.plan_opts())
         best, _ = fk.fk_autotune(plan, arr, n, 5)
         r = {"case": name, "items": n, "alg_bytes": alg, "autotuned": [best.block_threads, best.coarsen]}
-        r["fused_ms"] = round(timeit(lambda: fk.fk_run(plan, arr, n, stream), reps), 5)
+        r["fused_ms"] = round(timeit(lambda: fk.fk_run(plan, arr, n, stream), reps, warm_s=2e-3), 5)
         r["gbps"] = round(alg / (r["fused_ms"] * 1e-3) / 1e9, 1)
         r["hbm_frac"] = round(r["gbps"] / HBM_PEAK_GBPS, 4)
         if not args.no_unfused:
