@@ -586,8 +586,10 @@ def sweeps_workload(args):
                  Mul+Add pairs through the loop op, no batch;
       hf_plain:  B single-channel 60x120 u8 images, Read -> Cast -> Mul ->
                  Sub -> Div -> Write, one batched launch vs one launch per
-                 image vs unfused (default configuration), and the
-                 autotuner's own time for its choice and for the default;
+                 image vs unfused (default configuration), the batch
+                 through the device run table (one output tensor per item),
+                 and the autotuner's own time for its choice and for the
+                 default;
       dtypes:    the same chain at B = 50 for six input -> output types;
       instructions_per_op: 500 multiplications as ops of M instructions
                  over 66,355,200 fp32 values, fused vs one kernel per op."""
@@ -644,6 +646,14 @@ def sweeps_workload(args):
         if not args.no_unfused:
             r["unfused_ms"] = round(unfused_ms(plan, arr, B, 3), 4)
             r["speedup_vs_unfused"] = round(r["unfused_ms"] / r["fused_ms"], 1)
+        # the same batch with one output tensor per item, in reverse address
+        # order (no constant stride): its parameters go through the device
+        # run table and its upload kernel
+        # (up to 32 items travel in the kernel arguments either way)
+        if B > 32:
+            sep = [torch.empty_like(o) for o in outs][::-1]
+            arr_t = fk.make_items(ch, [frame], cfg["items"], sep)
+            r["table_ms"] = round(timeit(lambda: fk.fk_run(plan, arr_t, B, stream), 50), 5)
         # the autotuner's choice and its own time for it (median of 3
         # samples of 10 back-to-back launches), next to its time for the
         # default configuration
