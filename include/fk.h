@@ -152,7 +152,9 @@ typedef struct {
 /* A frame in device memory, packed HWC with `channels` channels of
  * `in_dtype` (the RawPtr/Ptr data descriptor of Section IV-B).
  * pitch_bytes >= width * channels * sizeof(element) and a multiple of the
- * element size; every row must be readable. */
+ * element size; every row must be readable.  Width and height are at most
+ * 65535 (larger frames are refused with FK_ERR_UNSUPPORTED: row and column
+ * indices feed 24-bit multiplies in the kernels). */
 typedef struct {
     const void *ptr;   /* device */
     int32_t width, height;
@@ -163,7 +165,9 @@ typedef struct {
  * (x, y, w, h) must lie inside `src`.  `dst` (device) receives out_w x
  * out_h x channels elements of the write dtype in the write layout,
  * densely (row pitch = out_w elements; planes of out_w*out_h).  For
- * FK_READ_PLAIN, out_w/out_h must be 0 or equal to w/h. */
+ * FK_READ_PLAIN, out_w/out_h must be 0 or equal to w/h.  A resizing read's
+ * out_w and out_h are at most 65535 each and out_w * out_h at most 2^28
+ * (else FK_ERR_UNSUPPORTED); a plain read's ROI at most 2^28 pixels. */
 typedef struct {
     fk_image src;
     int32_t x, y, w, h;
@@ -223,8 +227,9 @@ fk_status fk_items_validate(const fk_chain_desc *chain, const fk_item *items, in
 /* Create a plan for `chain` and up to `max_batch` items per run (the batch
  * capacity; each run passes its own count, Section IV-B).  `opts` may be
  * NULL (defaults).  Allocates the plan's op list on the device; the ring
- * of run tables for batches too large for the kernel arguments (and for
- * graph replays) is allocated on first use.
+ * of four run tables for batches too large for the kernel arguments (and
+ * for graph replays) is allocated whole by the first run that needs a
+ * table, so that later runs allocate no memory.
  * Selects the kernel: a compile-time composed chain when the chain matches
  * one built into the library, else the run-time op-list kernel. */
 fk_status fk_plan_create(const fk_chain_desc *chain, int32_t max_batch, const fk_plan_opts *opts,
@@ -325,11 +330,63 @@ fk_status fk_model_features(const fk_plan *plan, const fk_item *items, int32_t n
 /* Train on n samples (host arrays: features n x FK_MODEL_FEATURES, targets
  * n x FK_MODEL_OUTPUTS) for `epochs` passes of shuffled mini-batches of
  * `batch` rows, Adam (beta1 0.9, beta2 0.999, eps 1e-8) at learning rate lr,
- * MSE loss.  The first call fixes the feature normalisation from these
- * features.  loss_curve (host, may be NULL) receives each epoch's mean
- * mini-batch loss.  Synchronous. */
+ * MSE loss.  The first training call fixes the feature normalisation from
+ * these features (per-feature mean and standard deviation, fp64 sums; 1 for
+ * a constant feature).  loss_curve (host, may be NULL) receives each
+ * epoch's mean mini-batch loss.  Synchronous: copies the arrays to the
+ * device and runs fk_model_train_device on the model's stream, so both
+ * calls give the same parameters from the same inputs and seed. */
 fk_status fk_model_train(fk_model *model, const float *features, const float *targets, int32_t n,
                          int32_t epochs, int32_t batch, float lr, uint64_t seed, float *loss_curve);
+
+/* fk_model_train on device arrays, queued on `stream` (a hipStream_t; NULL
+ * = the default stream): d_features (n x FK_MODEL_FEATURES, raw features),
+ * d_targets (n x FK_MODEL_OUTPUTS) and d_loss_curve (`epochs` floats, may
+ * be NULL) are device memory that must stay valid until the stream has
+ * run the work.  The mini-batch permutations (SplitMix64-driven
+ * Fisher-Yates, one per epoch) are drawn on the host into a pinned buffer
+ * the model owns.  Returns once the work is queued, except that the first
+ * training call of a model waits for its normalisation statistics.  Any
+ * later call on the model first waits for this training to finish. */
+fk_status fk_model_train_device(fk_model *model, const float *d_features, const float *d_targets,
+                                int32_t n, int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                                float *d_loss_curve, void *stream);
+
+/* The network's kernels one by one, on device arrays, asynchronous on
+ * `stream` (used by the gradient checks and by callers that train their
+ * own way).  None of them normalises features: d_x holds the network's
+ * inputs.  Each first waits for a training run queued by
+ * fk_model_train_device.
+ *
+ * Workspace of n rows, in floats: the three hidden layers' outputs
+ * (n x hidden each, left by fk_mlp_forward for fk_mlp_backward), then two
+ * propagated-gradient buffers of n x max(hidden, FK_MODEL_OUTPUTS).  -1 on
+ * a bad argument. */
+int64_t fk_mlp_workspace_floats(const fk_model *model, int32_t n);
+
+/* Forward pass: d_x (n x FK_MODEL_FEATURES) -> d_y (n x FK_MODEL_OUTPUTS),
+ * hidden outputs kept in d_ws. */
+fk_status fk_mlp_forward(const fk_model *model, const float *d_x, int32_t n, float *d_ws,
+                         float *d_y, void *stream);
+
+/* Backward pass: the gradient of a loss with respect to every parameter
+ * (d_grad: fk_model_param_count floats, the parameter layout) from the
+ * loss's gradient d_dy (n x FK_MODEL_OUTPUTS) with respect to the outputs
+ * of the fk_mlp_forward call that filled d_ws from the same d_x.  d_dy must
+ * not lie inside d_ws. */
+fk_status fk_mlp_backward(const fk_model *model, const float *d_x, int32_t n, float *d_ws,
+                          const float *d_dy, float *d_grad, void *stream);
+
+/* Mean-squared-error loss of n x FK_MODEL_OUTPUTS outputs against targets:
+ * d_loss[0] = mean (y - t)^2 and d_dy = 2 (y - t) / (n FK_MODEL_OUTPUTS). */
+fk_status fk_mlp_mse(const float *d_y, const float *d_t, int32_t n, float *d_dy, float *d_loss,
+                     void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) of the
+ * model's parameters along d_grad (device, the parameter layout), with the
+ * model's moment estimates; advances the model's step count t (bias
+ * corrections 1 - beta^t). */
+fk_status fk_mlp_step(fk_model *model, const float *d_grad, float lr, void *stream);
 
 /* Network outputs for n feature rows (host in, host out n x
  * FK_MODEL_OUTPUTS).  Synchronous. */
@@ -427,7 +484,11 @@ fk_status fk_server_submit(fk_server *srv, const fk_request *req, uint64_t *tick
 /* Up to `max` completions (oldest first) into `out`; their count in *n. */
 fk_status fk_server_poll(fk_server *srv, fk_completion *out, int32_t max, int32_t *n);
 
-/* Return a completed request's device memory to the budget. */
+/* Return a completed request's device memory to the budget.  Only a
+ * ticket whose completion fk_server_poll has returned (and that was not
+ * released before) is accepted; any other ticket -- unknown, released
+ * before, or not yet returned by a poll (still queued, copying or
+ * running) -- gives FK_ERR_BAD_STATE and changes nothing. */
 fk_status fk_server_release(fk_server *srv, uint64_t ticket);
 
 fk_status fk_server_stats_get(fk_server *srv, fk_server_stats *out);

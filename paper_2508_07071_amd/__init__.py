@@ -176,6 +176,13 @@ def lib():
         "fk_model_features": ([P, C.POINTER(fk_item), C.c_int32, P], C.c_int32),
         "fk_model_train": ([P, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_uint64, P],
                            C.c_int32),
+        "fk_model_train_device": ([P, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_uint64,
+                                   P, P], C.c_int32),
+        "fk_mlp_workspace_floats": ([P, C.c_int32], C.c_int64),
+        "fk_mlp_forward": ([P, P, C.c_int32, P, P, P], C.c_int32),
+        "fk_mlp_backward": ([P, P, C.c_int32, P, P, P, P], C.c_int32),
+        "fk_mlp_mse": ([P, P, C.c_int32, P, P, P], C.c_int32),
+        "fk_mlp_step": ([P, P, C.c_float, P], C.c_int32),
         "fk_model_predict_batch": ([P, P, C.c_int32, P], C.c_int32),
         "fk_model_loss_grad": ([P, P, P, C.c_int32, P, P], C.c_int32),
         "fk_model_predict": ([P, P, C.POINTER(fk_item), C.c_int32, C.POINTER(fk_launch_config)],
@@ -207,7 +214,9 @@ EXPORTS = [
     "fk_autotune_space", "fk_autotune",
     "fk_model_create", "fk_model_destroy", "fk_model_param_count", "fk_model_get_params",
     "fk_model_set_params", "fk_model_get_normalization", "fk_model_set_normalization",
-    "fk_model_features", "fk_model_train", "fk_model_predict_batch", "fk_model_loss_grad",
+    "fk_model_features", "fk_model_train", "fk_model_train_device", "fk_mlp_workspace_floats",
+    "fk_mlp_forward", "fk_mlp_backward", "fk_mlp_mse", "fk_mlp_step",
+    "fk_model_predict_batch", "fk_model_loss_grad",
     "fk_model_predict", "fk_plan_use_model", "fk_model_save", "fk_model_load",
     "fk_server_clock", "fk_server_create", "fk_server_submit", "fk_server_poll", "fk_server_release",
     "fk_server_stats_get", "fk_server_destroy",
@@ -257,6 +266,12 @@ def make_items(chain: dict, frames: list, items: list, outs: list):
     receiving each item's output."""
     arr = (fk_item * max(1, len(items)))()
     nv12 = chain["read"]["kind"] in NV12
+    for fr in frames:
+        _check_frame(chain, fr)
+    for b, it in enumerate(items):
+        _check_out(chain, it, outs[b])
+    if not all(t.is_cuda for t in list(frames) + list(outs[:len(items)])):
+        raise ValueError("frames and outputs must be device tensors")
     for b, it in enumerate(items):
         fr = frames[it["frame"]]
         a = arr[b]
@@ -271,6 +286,41 @@ def make_items(chain: dict, frames: list, items: list, outs: list):
         else:
             a.out_w, a.out_h = 0, 0
     return arr
+
+
+def _check_frame(chain: dict, fr) -> None:
+    """A frame must be a device tensor of the read's dtype laid out packed
+    HWC (rows may carry padding: any stride(0)); NV12 and one-channel frames
+    may be 2-D (H, W) with unit column stride."""
+    c = chain["read"]["channels"]
+    nv12 = chain["read"]["kind"] in NV12
+    want = torch.uint8 if nv12 else TORCH_DTYPE[chain["read"]["dtype"]]
+    if fr.dim() == 3:
+        ok = fr.shape[2] == c and fr.stride(2) == 1 and fr.stride(1) == c and not nv12
+    elif fr.dim() == 2:
+        ok = (nv12 or c == 1) and fr.stride(1) == 1
+    else:
+        ok = False
+    if not ok:
+        raise ValueError(f"frame of shape {tuple(fr.shape)} and strides {fr.stride()} is not a "
+                         f"packed {'NV12' if nv12 else f'HWC x{c}'} image")
+    if fr.dtype != want:
+        raise ValueError(f"frame dtype {fr.dtype}, the chain reads {want}")
+
+
+def _check_out(chain: dict, item: dict, out) -> None:
+    """An output must be a contiguous device tensor of the write's dtype
+    holding exactly the item's output elements."""
+    want = TORCH_DTYPE[chain["write"]["dtype"]]
+    n = 1
+    for d in out_shape(chain, item):
+        n *= d
+    if not out.is_contiguous():
+        raise ValueError("outputs must be contiguous")
+    if out.dtype != want:
+        raise ValueError(f"output dtype {out.dtype}, the chain writes {want}")
+    if out.numel() != n:
+        raise ValueError(f"output holds {out.numel()} elements, the item writes {n}")
 
 
 def out_shape(chain: dict, item: dict) -> tuple:
@@ -436,6 +486,56 @@ def fk_model_train(model: int, features, targets, epochs: int, batch: int, lr: f
     check(lib().fk_model_train(model, x.ctypes.data, t.ctypes.data, x.shape[0], epochs, batch, lr, seed,
                                curve.ctypes.data))
     return curve[:epochs]
+
+
+def fk_model_train_device(model: int, d_features, d_targets, epochs: int, batch: int, lr: float,
+                          seed: int = 0, d_loss_curve=None, stream=None) -> None:
+    """Queue a training run on device tensors (fp32, contiguous) on `stream`
+    (default: torch's current stream)."""
+    for t in (d_features, d_targets) + ((d_loss_curve,) if d_loss_curve is not None else ()):
+        _check_dev_f32(t)
+    check(lib().fk_model_train_device(model, d_features.data_ptr(), d_targets.data_ptr(),
+                                      d_features.shape[0], epochs, batch, lr, seed,
+                                      d_loss_curve.data_ptr() if d_loss_curve is not None else None,
+                                      stream_handle(stream)))
+
+
+def _check_dev_f32(t) -> None:
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float32 device tensor")
+
+
+def fk_mlp_workspace_floats(model: int, n: int) -> int:
+    v = int(lib().fk_mlp_workspace_floats(model, n))
+    if v < 0:
+        raise FKError(FK_ERR_INVALID_ARG, "fk_mlp_workspace_floats: bad argument")
+    return v
+
+
+def fk_mlp_forward(model: int, d_x, d_ws, d_y, stream=None) -> None:
+    for t in (d_x, d_ws, d_y):
+        _check_dev_f32(t)
+    check(lib().fk_mlp_forward(model, d_x.data_ptr(), d_x.shape[0], d_ws.data_ptr(), d_y.data_ptr(),
+                               stream_handle(stream)))
+
+
+def fk_mlp_backward(model: int, d_x, d_ws, d_dy, d_grad, stream=None) -> None:
+    for t in (d_x, d_ws, d_dy, d_grad):
+        _check_dev_f32(t)
+    check(lib().fk_mlp_backward(model, d_x.data_ptr(), d_x.shape[0], d_ws.data_ptr(), d_dy.data_ptr(),
+                                d_grad.data_ptr(), stream_handle(stream)))
+
+
+def fk_mlp_mse(d_y, d_t, d_dy, d_loss, stream=None) -> None:
+    for t in (d_y, d_t, d_dy, d_loss):
+        _check_dev_f32(t)
+    check(lib().fk_mlp_mse(d_y.data_ptr(), d_t.data_ptr(), d_y.shape[0], d_dy.data_ptr(),
+                           d_loss.data_ptr(), stream_handle(stream)))
+
+
+def fk_mlp_step(model: int, d_grad, lr: float, stream=None) -> None:
+    _check_dev_f32(d_grad)
+    check(lib().fk_mlp_step(model, d_grad.data_ptr(), lr, stream_handle(stream)))
 
 
 def fk_model_predict_batch(model: int, features):

@@ -77,29 +77,7 @@ def label(n, seed=0, reps=3, log_every=250, start=0):
         ch = spec["chain"]
         C = ch["read"]["channels"]
         fh, fw = spec["frame_hw"]
-        es = _esize(ch["read"]["dtype"])
-        frame_bytes = fw * fh * C * es
-        fstride = (frame_bytes + 255) // 256 * 256
-        esz_out = _esize(ch["write"]["dtype"])
-        items = spec["items"]
-        B = len(items)
-        arr = (fk.fk_item * B)()
-        ooff = 0
-        for b, it in enumerate(items):
-            a = arr[b]
-            a.src.ptr = arena_in.data_ptr() + b * fstride
-            a.src.width, a.src.height, a.src.pitch_bytes = fw, fh, fw * C * es
-            a.x, a.y, a.w, a.h = it["x"], it["y"], it["w"], it["h"]
-            a.dst = arena_out.data_ptr() + ooff
-            if ch["read"]["kind"] == "crop_resize":
-                a.out_w, a.out_h = it["out_w"], it["out_h"]
-                ob = it["out_w"] * it["out_h"] * C * esz_out
-            else:
-                a.out_w, a.out_h = 0, 0
-                ob = it["w"] * it["h"] * C * esz_out
-            ooff += (ob + 255) // 256 * 256
-        assert B * fstride <= arena_in.numel() and ooff <= arena_out.numel()
-        desc = fk.chain_desc(ch)
+        desc, arr, B = batch_in_arenas(spec, arena_in, arena_out)
         plan = fk.fk_plan_create(desc, B)
         try:
             c = fk.fk_plan_get_config(plan)
@@ -116,6 +94,78 @@ def label(n, seed=0, reps=3, log_every=250, start=0):
             print(f"[label] {i + 1}/{n} chains, {time.time() - t0:.0f} s", flush=True)
     return {"features": feats, "times_ms": times, "default_idx": default_idx,
             "meta": np.array([json.dumps(m) for m in meta])}
+
+
+def batch_in_arenas(spec, arena_in, arena_out):
+    """(chain descriptor, fk_item array, batch size) of a spec's batch:
+    item b reads frame b at a 256-byte aligned offset of arena_in (whatever
+    bytes it holds) and writes its output at the next 256-byte aligned
+    offset of arena_out."""
+    import paper_2508_07071_amd as fk
+
+    ch = spec["chain"]
+    C = ch["read"]["channels"]
+    fh, fw = spec["frame_hw"]
+    es = _esize(ch["read"]["dtype"])
+    fstride = (fw * fh * C * es + 255) // 256 * 256
+    esz_out = _esize(ch["write"]["dtype"])
+    items = spec["items"]
+    B = len(items)
+    arr = (fk.fk_item * B)()
+    ooff = 0
+    for b, it in enumerate(items):
+        a = arr[b]
+        a.src.ptr = arena_in.data_ptr() + b * fstride
+        a.src.width, a.src.height, a.src.pitch_bytes = fw, fh, fw * C * es
+        a.x, a.y, a.w, a.h = it["x"], it["y"], it["w"], it["h"]
+        a.dst = arena_out.data_ptr() + ooff
+        if ch["read"]["kind"] == "crop_resize":
+            a.out_w, a.out_h = it["out_w"], it["out_h"]
+            ob = it["out_w"] * it["out_h"] * C * esz_out
+        else:
+            a.out_w, a.out_h = 0, 0
+            ob = it["w"] * it["h"] * C * esz_out
+        ooff += (ob + 255) // 256 * 256
+    assert B * fstride <= arena_in.numel() and ooff <= arena_out.numel()
+    return fk.chain_desc(ch), arr, B
+
+
+def live_quality(model, n=20, seed=20260, reps=10, max_input_bytes=1 << 28):
+    """The model's choice re-timed on this GPU: for n random chains drawn
+    from `seed` (inputs capped at max_input_bytes), the configuration that
+    fk_plan_use_model installs is compared with fk_autotune's best from one
+    sweep of all 20 configurations on this device.  Returns per-chain
+    quality t_best / t_pick and the same for the library default."""
+    import torch
+
+    import datagen
+    import paper_2508_07071_amd as fk
+
+    dev = torch.device("cuda:0")
+    arena_in = torch.full((max_input_bytes + (1 << 20),), 1, dtype=torch.uint8, device=dev)
+    arena_out = torch.empty((ARENA_OUT + (1 << 20),), dtype=torch.uint8, device=dev)
+    space = [(s.block_threads, s.coarsen) for s in fk.fk_autotune_space()]
+    g = datagen.rng(seed)
+    qs, qd, picks = [], [], []
+    for _ in range(n):
+        spec = fit_spec(datagen.random_chain_spec(g, max_input_bytes=max_input_bytes))
+        desc, arr, B = batch_in_arenas(spec, arena_in, arena_out)
+        plan = fk.fk_plan_create(desc, B)
+        try:
+            d = fk.fk_plan_get_config(plan)
+            di = space.index((d.block_threads, d.coarsen))
+            fk.fk_plan_use_model(plan, model, arr, B)
+            c = fk.fk_plan_get_config(plan)
+            pi = space.index((c.block_threads, c.coarsen))
+            _, t = fk.fk_autotune(plan, arr, B, reps)
+        finally:
+            fk.fk_plan_destroy(plan)
+        t = np.asarray(t, np.float64)
+        qs.append(float(t.min() / t[pi]))
+        qd.append(float(t.min() / t[di]))
+        picks.append(space[pi])
+    del arena_in, arena_out
+    return {"quality": qs, "picks": picks, "model": summarize(qs), "default": summarize(qd)}
 
 
 def load_shards(paths):

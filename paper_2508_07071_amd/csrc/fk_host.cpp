@@ -153,6 +153,9 @@ fk_status fk::validate_items(const fk_chain_desc *ch, const fk_item *items, int3
         if (rd_resizes(ch->read.kind)) {
             if (it.out_w < 1 || it.out_h < 1)
                 return set_error(FK_ERR_INVALID_ARG, "item %d: output size must be positive", b);
+            // output rows and columns feed 24-bit multiplies in the kernels
+            if (it.out_w > 65535 || it.out_h > 65535)
+                return set_error(FK_ERR_UNSUPPORTED, "item %d: output sides above 65535", b);
             if ((int64_t)it.out_w * it.out_h > (1LL << 28))
                 return set_error(FK_ERR_UNSUPPORTED, "item %d: output too large", b);
         } else {
@@ -702,24 +705,29 @@ fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_la
         }
     }
     fk_plan::Slot &sl = p->slots[p->next_slot];
-    p->next_slot = (p->next_slot + 1) % fk_plan::kRing;
     hipError_t e = hipSuccess;
-    if (!sl.h_stage) {  // the table ring is allocated on first use
-        // coherent: the upload kernel reads each byte once, straight from
-        // host memory, after the host has rewritten the slot
-        e = hipHostMalloc(&sl.h_stage, p->table_bytes, hipHostMallocMapped | hipHostMallocCoherent);
-        if (e == hipSuccess)
-            e = hipHostGetDevicePointer(&sl.h_dev, sl.h_stage, 0);
-        if (e == hipSuccess)
-            e = hipMalloc(&sl.d_table, p->table_bytes);
-        if (e == hipSuccess)
-            e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
-        if (e != hipSuccess) {
-            free_slot(sl);
-            return e == hipErrorOutOfMemory ? set_error(FK_ERR_OUT_OF_MEMORY, "run table")
-                                            : hip_error(e, "run table");
+    if (!sl.h_stage) {
+        // the whole table ring is allocated on the first table run, so
+        // later runs allocate nothing
+        for (fk_plan::Slot &r : p->slots) {
+            // coherent: the upload kernel reads each byte once, straight
+            // from host memory, after the host has rewritten the slot
+            e = hipHostMalloc(&r.h_stage, p->table_bytes, hipHostMallocMapped | hipHostMallocCoherent);
+            if (e == hipSuccess)
+                e = hipHostGetDevicePointer(&r.h_dev, r.h_stage, 0);
+            if (e == hipSuccess)
+                e = hipMalloc(&r.d_table, p->table_bytes);
+            if (e == hipSuccess)
+                e = hipEventCreateWithFlags(&r.done, hipEventDisableTiming);
+            if (e != hipSuccess) {
+                for (fk_plan::Slot &q : p->slots)
+                    free_slot(q);
+                return e == hipErrorOutOfMemory ? set_error(FK_ERR_OUT_OF_MEMORY, "run table")
+                                                : hip_error(e, "run table");
+            }
         }
     }
+    p->next_slot = (p->next_slot + 1) % fk_plan::kRing;
     if (graph && !p->capture_stream) {
         e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
         if (e != hipSuccess)

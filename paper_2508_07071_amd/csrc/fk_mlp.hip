@@ -163,6 +163,51 @@ __global__ __launch_bounds__(kThreads) void k_gather(const float *__restrict__ s
     dst[e] = src[(int64_t)idx[r] * cols + c];
 }
 
+// Per-column mean and standard deviation of a rows x cols matrix: sums of
+// x and x^2 in fp64 over the rows in order; var = max(0, s2/n - mu^2); a
+// column with var <= 1e-12 gets std 1.  One thread per column.
+__global__ __launch_bounds__(kThreads) void k_colstats(const float *__restrict__ X, int rows,
+                                                       int cols, float *__restrict__ mean,
+                                                       float *__restrict__ stdv)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols)
+        return;
+    double s1 = 0.0, s2 = 0.0;
+    for (int r = 0; r < rows; ++r) {
+        const double v = X[(int64_t)r * cols + c];
+        s1 += v;
+        s2 += v * v;
+    }
+    const double mu = s1 / rows;
+    double var = s2 / rows - mu * mu;
+    var = var > 0.0 ? var : 0.0;
+    mean[c] = (float)mu;
+    stdv[c] = var > 1e-12 ? (float)sqrt(var) : 1.0f;
+}
+
+// out = (X - mean[c]) / std[c], one fp32 subtraction and one IEEE division.
+__global__ __launch_bounds__(kThreads) void k_standardize(const float *__restrict__ X, int64_t rows,
+                                                          int cols, const float *__restrict__ mean,
+                                                          const float *__restrict__ stdv,
+                                                          float *__restrict__ out)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= rows * cols)
+        return;
+    const int c = (int)(e % cols);
+    out[e] = (X[e] - mean[c]) / stdv[c];
+}
+
+// out[0] = mean of x[0..n) (fp64 sum in order, one thread).
+__global__ void k_mean(const float *__restrict__ x, int n, float *__restrict__ out)
+{
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i)
+        acc += x[i];
+    out[0] = (float)(acc / n);
+}
+
 // ------------------------------------------------------------- launchers --
 
 hipError_t mlp_gemm(bool ta, bool tb, const float *A, const float *B, float *C, int M, int N, int K,
@@ -212,6 +257,29 @@ hipError_t mlp_gather(const float *src, int cols, const int32_t *idx, int rows, 
     if (n == 0)
         return hipSuccess;
     k_gather<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(src, cols, idx, rows, dst);
+    return hipGetLastError();
+}
+
+hipError_t mlp_colstats(const float *X, int rows, int cols, float *mean, float *stdv, hipStream_t s)
+{
+    k_colstats<<<(cols + kThreads - 1) / kThreads, kThreads, 0, s>>>(X, rows, cols, mean, stdv);
+    return hipGetLastError();
+}
+
+hipError_t mlp_standardize(const float *X, int64_t rows, int cols, const float *mean,
+                           const float *stdv, float *out, hipStream_t s)
+{
+    const int64_t n = rows * cols;
+    if (n == 0)
+        return hipSuccess;
+    k_standardize<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(X, rows, cols, mean,
+                                                                               stdv, out);
+    return hipGetLastError();
+}
+
+hipError_t mlp_mean(const float *x, int n, float *out, hipStream_t s)
+{
+    k_mean<<<1, 1, 0, s>>>(x, n, out);
     return hipGetLastError();
 }
 

@@ -20,5 +20,12 @@ hipError_t mlp_adam(float *p, const float *g, float *m, float *v, int64_t n, flo
                     float b2, float eps, int step, hipStream_t s);
 hipError_t mlp_gather(const float *src, int cols, const int32_t *idx, int rows, float *dst,
                       hipStream_t s);
+// per-column mean and std (fp64 sums; std 1 for a constant column)
+hipError_t mlp_colstats(const float *X, int rows, int cols, float *mean, float *stdv, hipStream_t s);
+// (X - mean[c]) / std[c]
+hipError_t mlp_standardize(const float *X, int64_t rows, int cols, const float *mean,
+                           const float *stdv, float *out, hipStream_t s);
+// out[0] = mean of x[0..n)
+hipError_t mlp_mean(const float *x, int n, float *out, hipStream_t s);
 
 }  // namespace fk

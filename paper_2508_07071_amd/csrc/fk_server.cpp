@@ -18,6 +18,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <set>
 #include <thread>
 #include <vector>
 
@@ -73,6 +74,7 @@ struct fk_server {
     std::condition_variable cv;
     std::deque<std::unique_ptr<Req>> incoming;  // submitted, not seen by the scheduler
     std::deque<fk_completion> completions;
+    std::set<uint64_t> releasable;  // completions handed out by poll, not yet released
     std::vector<uint64_t> releases;
     fk_server_stats stats{};
     bool stop = false;
@@ -494,50 +496,79 @@ extern "C" fk_status fk_server_submit(fk_server *s, const fk_request *req, uint6
 
 extern "C" fk_status fk_server_poll(fk_server *s, fk_completion *out, int32_t max, int32_t *n)
 {
-    if (!s || !n || (max > 0 && !out) || max < 0)
-        return set_error(FK_ERR_INVALID_ARG, "bad argument");
-    std::lock_guard<std::mutex> g(s->mu);
-    int32_t k = 0;
-    while (k < max && !s->completions.empty()) {
-        out[k++] = s->completions.front();
-        s->completions.pop_front();
+    try {
+        if (!s || !n || (max > 0 && !out) || max < 0)
+            return set_error(FK_ERR_INVALID_ARG, "bad argument");
+        std::lock_guard<std::mutex> g(s->mu);
+        int32_t k = 0;
+        while (k < max && !s->completions.empty()) {
+            out[k] = s->completions.front();
+            s->releasable.insert(out[k].ticket);
+            s->completions.pop_front();
+            ++k;
+        }
+        *n = k;
+        return FK_OK;
+    } catch (...) {
+        return set_error(FK_ERR_BAD_STATE, "exception");
     }
-    *n = k;
-    return FK_OK;
 }
 
 extern "C" fk_status fk_server_release(fk_server *s, uint64_t ticket)
 {
-    if (!s)
-        return set_error(FK_ERR_INVALID_ARG, "server is null");
-    {
-        std::lock_guard<std::mutex> g(s->mu);
-        s->releases.push_back(ticket);
+    try {
+        if (!s)
+            return set_error(FK_ERR_INVALID_ARG, "server is null");
+        {
+            // only a request whose completion the caller has polled may
+            // return its block to the arena: one still queued, copying or
+            // running keeps its memory
+            std::lock_guard<std::mutex> g(s->mu);
+            auto it = s->releasable.find(ticket);
+            if (it == s->releasable.end())
+                return set_error(FK_ERR_BAD_STATE,
+                                 "ticket %llu is not completed, unknown or already released",
+                                 (unsigned long long)ticket);
+            s->releasable.erase(it);
+            s->releases.push_back(ticket);
+        }
+        s->cv.notify_one();
+        return FK_OK;
+    } catch (...) {
+        return set_error(FK_ERR_OUT_OF_MEMORY, "exception");
     }
-    s->cv.notify_one();
-    return FK_OK;
 }
 
 extern "C" fk_status fk_server_stats_get(fk_server *s, fk_server_stats *out)
 {
-    if (!s || !out)
-        return set_error(FK_ERR_INVALID_ARG, "null argument");
-    std::lock_guard<std::mutex> g(s->mu);
-    *out = s->stats;
-    return FK_OK;
+    try {
+        if (!s || !out)
+            return set_error(FK_ERR_INVALID_ARG, "null argument");
+        std::lock_guard<std::mutex> g(s->mu);
+        *out = s->stats;
+        return FK_OK;
+    } catch (...) {
+        return set_error(FK_ERR_BAD_STATE, "exception");
+    }
 }
 
 extern "C" fk_status fk_server_destroy(fk_server *s)
 {
     if (!s)
         return FK_OK;
-    {
-        std::lock_guard<std::mutex> g(s->mu);
-        s->stop = true;
+    try {
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            s->stop = true;
+        }
+        s->cv.notify_one();
+        if (s->thread.joinable())
+            s->thread.join();
+    } catch (...) {
+        // the scheduler could not be joined: its thread may still use the
+        // server, so nothing is freed
+        return set_error(FK_ERR_BAD_STATE, "scheduler thread could not be joined");
     }
-    s->cv.notify_one();
-    if (s->thread.joinable())
-        s->thread.join();
     (void)hipStreamSynchronize(s->copy_stream);
     (void)hipStreamSynchronize(s->compute_stream);
     for (auto &kv : s->live)

@@ -188,3 +188,83 @@ def test_nv12_items_need_even_frames():
     assert fk.lib().fk_items_validate(C.byref(d), it, 1) == fk.FK_OK
     it[0].src.width = 63
     assert fk.lib().fk_items_validate(C.byref(d), it, 1) == fk.FK_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(out_w=65535, out_h=2), fk.FK_OK),
+    (dict(out_w=65536, out_h=1), fk.FK_ERR_UNSUPPORTED),
+    (dict(out_w=4, out_h=1 << 25), fk.FK_ERR_UNSUPPORTED),
+    (dict(width=65536, pitch_bytes=65536 * 3), fk.FK_ERR_UNSUPPORTED),
+    (dict(out_w=65535, out_h=65535), fk.FK_ERR_UNSUPPORTED),  # above 2^28 pixels
+])
+def test_resize_output_sides_are_limited(kw, status):
+    # the kernels take output rows and columns through 24-bit multiplies:
+    # sides above 65535 must be refused, not computed wrongly
+    d = fk.chain_desc(norm_chain())
+    assert fk.fk_items_validate(d, fake_items(norm_chain(), **kw), 1) == status
+
+
+def test_mlp_raw_exports_reject_bad_arguments():
+    L = fk.lib()
+    assert L.fk_mlp_workspace_floats(None, 4) == -1
+    assert L.fk_mlp_forward(None, None, 1, None, None, None) == fk.FK_ERR_INVALID_ARG
+    assert L.fk_mlp_backward(None, None, 1, None, None, None, None) == fk.FK_ERR_INVALID_ARG
+    assert L.fk_mlp_mse(None, None, 1, None, None, None) == fk.FK_ERR_INVALID_ARG
+    assert L.fk_mlp_step(None, None, 1e-3, None) == fk.FK_ERR_INVALID_ARG
+    assert L.fk_model_train_device(None, None, None, 4, 1, 4, 1e-3, 0, None, None) == fk.FK_ERR_INVALID_ARG
+
+
+def test_server_calls_reject_null():
+    L = fk.lib()
+    n = C.c_int32()
+    assert L.fk_server_poll(None, None, 0, C.byref(n)) == fk.FK_ERR_INVALID_ARG
+    assert L.fk_server_release(None, 1) == fk.FK_ERR_INVALID_ARG
+    assert L.fk_server_destroy(None) == fk.FK_OK
+
+
+class TestMakeItemsChecks:
+    """make_items refuses tensors the library would read or write wrongly
+    (checked before the device, so CPU tensors exercise each rule)."""
+
+    def cfg(self):
+        import datagen
+        chain = datagen.normalize_chain(64, 128)
+        item = {"frame": 0, "x": 0, "y": 0, "w": 32, "h": 16, "out_w": 64, "out_h": 128}
+        return chain, item
+
+    def test_strided_frame_view_is_refused(self):
+        chain, item = self.cfg()
+        fr = torch.zeros(16, 64, 3, dtype=torch.uint8)[:, ::2, :]  # column stride 6
+        out = torch.zeros(3, 128, 64)
+        with pytest.raises(ValueError, match="packed"):
+            fk.make_items(chain, [fr], [item], [out])
+
+    def test_channel_last_transposed_frame_is_refused(self):
+        chain, item = self.cfg()
+        fr = torch.zeros(3, 16, 32, dtype=torch.uint8).permute(1, 2, 0)  # (16, 32, 3), stride(2) != 1
+        out = torch.zeros(3, 128, 64)
+        with pytest.raises(ValueError, match="packed"):
+            fk.make_items(chain, [fr], [item], [out])
+
+    def test_frame_dtype_must_match_chain(self):
+        chain, item = self.cfg()
+        fr = torch.zeros(16, 32, 3, dtype=torch.float32)
+        out = torch.zeros(3, 128, 64)
+        with pytest.raises(ValueError, match="dtype"):
+            fk.make_items(chain, [fr], [item], [out])
+
+    def test_output_must_be_contiguous_and_sized(self):
+        chain, item = self.cfg()
+        fr = torch.zeros(16, 32, 3, dtype=torch.uint8)
+        with pytest.raises(ValueError, match="contiguous"):
+            fk.make_items(chain, [fr], [item], [torch.zeros(3, 64, 128).transpose(1, 2)])
+        with pytest.raises(ValueError, match="elements"):
+            fk.make_items(chain, [fr], [item], [torch.zeros(3, 127, 64)])
+        with pytest.raises(ValueError, match="dtype"):
+            fk.make_items(chain, [fr], [item], [torch.zeros(3, 128, 64, dtype=torch.float16)])
+
+    def test_host_tensors_are_refused(self):
+        chain, item = self.cfg()
+        fr = torch.zeros(16, 32, 3, dtype=torch.uint8)
+        with pytest.raises(ValueError, match="device"):
+            fk.make_items(chain, [fr], [item], [torch.zeros(3, 128, 64)])

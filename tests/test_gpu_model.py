@@ -155,3 +155,87 @@ def test_features_and_model_choice_for_a_plan():
             assert not torch.isnan(outs[0]).any()
     finally:
         fk.fk_model_destroy(m)
+
+
+def test_raw_kernels_forward_mse_backward_step_match_oracle():
+    """The network's kernels called one by one on device arrays: forward
+    (every hidden layer), MSE and its gradient, backward, and two Adam
+    steps, each against the fp64 oracle given the same inputs."""
+    say("raw forward/mse/backward/step")
+    hidden, n, lr = 48, 53, 2e-3
+    g = np.random.default_rng(12)
+    X = g.normal(size=(n, F)).astype(np.float32)
+    T = g.normal(size=(n, O)).astype(np.float32)
+    dev = torch.device("cuda:0")
+    dX, dT = torch.from_numpy(X).to(dev), torch.from_numpy(T).to(dev)
+    m = fk.fk_model_create(hidden, 13)
+    try:
+        p0 = fk.fk_model_get_params(m).astype(np.float64)
+        ws = torch.full((fk.fk_mlp_workspace_floats(m, n),), float("nan"), device=dev)
+        assert ws.numel() == n * (3 * hidden + 2 * max(hidden, O))
+        dY = torch.empty(n, O, device=dev)
+        fk.fk_mlp_forward(m, dX, ws, dY)
+        dDY = torch.empty(n, O, device=dev)
+        dL = torch.empty(1, device=dev)
+        fk.fk_mlp_mse(dY, dT, dDY, dL)
+        dG = torch.full((p0.size,), float("nan"), device=dev)
+        fk.fk_mlp_backward(m, dX, ws, dDY, dG)
+        torch.cuda.synchronize()
+        acts = mlp.forward(p0, dims(hidden), X.astype(np.float64))
+        hid = ws[:3 * n * hidden].view(3, n, hidden).cpu().numpy()
+        for l in range(3):
+            close(hid[l], acts[l + 1], rel=1e-4, what=f"hidden layer {l}")
+        close(dY.cpu().numpy(), acts[-1], rel=1e-4, what="forward")
+        rl, rg = mlp.loss_grad(p0, dims(hidden), X.astype(np.float64), T.astype(np.float64))
+        assert float(dL.item()) == pytest.approx(rl, rel=1e-5)
+        y64 = acts[-1]
+        close(dDY.cpu().numpy(), 2.0 * (y64 - T) / y64.size, rel=2e-4, what="dY")
+        grad = dG.cpu().numpy().astype(np.float64)
+        close(grad, rg, what="gradient")
+        # two Adam steps along the kernels' own gradient
+        pr, mr, vr = p0, np.zeros_like(p0), np.zeros_like(p0)
+        for t in (1, 2):
+            fk.fk_mlp_step(m, dG, lr)
+            torch.cuda.synchronize()
+            pr, mr, vr = mlp.adam_step(pr, grad, mr, vr, t, lr)
+            pg = fk.fk_model_get_params(m).astype(np.float64)
+            np.testing.assert_allclose(pg, pr, rtol=0, atol=2e-7 + 1e-4 * lr, err_msg=f"Adam step {t}")
+    finally:
+        fk.fk_model_destroy(m)
+
+
+def test_device_training_equals_host_training():
+    """fk_model_train (host arrays) and fk_model_train_device (device
+    arrays on the caller's stream) run the same steps: same normalisation,
+    same loss curve and the same parameters, bit for bit."""
+    say("train_device == train")
+    g = np.random.default_rng(14)
+    n = 700
+    X = (g.normal(size=(n, F)) * 2 + 1).astype(np.float32)
+    T = np.tanh(X[:, :O]).astype(np.float32)
+    dev = torch.device("cuda:0")
+    a = fk.fk_model_create(32, 5)
+    b = fk.fk_model_create(32, 5)
+    try:
+        curve_a = fk.fk_model_train(a, X, T, epochs=4, batch=64, lr=1e-3, seed=9)
+        dX, dT = torch.from_numpy(X).to(dev), torch.from_numpy(T).to(dev)
+        dC = torch.zeros(4, device=dev)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            fk.fk_model_train_device(b, dX, dT, epochs=4, batch=64, lr=1e-3, seed=9, d_loss_curve=dC, stream=s)
+        # reading the parameters waits for the queued training
+        pb = fk.fk_model_get_params(b)
+        s.synchronize()
+        curve_b = dC.cpu().numpy()
+        pa = fk.fk_model_get_params(a)
+        na, nb = fk.fk_model_get_normalization(a), fk.fk_model_get_normalization(b)
+    finally:
+        fk.fk_model_destroy(a)
+        fk.fk_model_destroy(b)
+    np.testing.assert_array_equal(na[0], nb[0])
+    np.testing.assert_array_equal(na[1], nb[1])
+    np.testing.assert_array_equal(curve_a, curve_b)
+    np.testing.assert_array_equal(pa, pb)
+    # the normalisation is the features' mean and (population) std
+    np.testing.assert_allclose(na[0], X.astype(np.float64).mean(axis=0), rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(na[1], X.astype(np.float64).std(axis=0), rtol=1e-5)

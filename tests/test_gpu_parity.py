@@ -101,21 +101,28 @@ def test_config2_uneven_crops_batch(batch):
     check_both_modes(cfg["chain"], cfg["frames"], cfg["items"], refs, s_floor=1.0, what=f"config2 B={batch}")
 
 
-def test_config2_batch256_one_tensor_sampled_items():
-    """B = 256 into one contiguous [B][3][128][64] tensor; 24 sampled items
-    checked against the oracle, all items checked to be written."""
-    say("config2 B=256 contiguous output")
+@pytest.mark.parametrize("strict", [True, False])
+def test_config2_batch256_one_tensor_sampled_items(strict):
+    """B = 256 into one contiguous [B][3][128][64] tensor, in the launch
+    form the benchmark times (one compact kernel-argument launch, pixel-
+    strided lanes); 24 sampled items checked against the oracle (bit-exact
+    in the strict mode, within 1e-5 relative with s = 1 in the contracted
+    mode), all items checked to be written."""
+    say("config2 B=256 contiguous output, strict", strict)
     cfg = datagen.config2(256, seed=0)
     dframes = to_dev(cfg["frames"])
     out = torch.full((256, 3, 128, 64), float("nan"), dtype=torch.float32, device="cuda:0")
-    with Plan(cfg["chain"], 256, strict=True) as p:
+    with Plan(cfg["chain"], 256, strict=strict) as p:
         p.run(dframes, cfg["items"], outs=[out[b] for b in range(256)])
         g = host([out])[0]
     assert not np.isnan(g).any()
     sample = list(range(0, 256, 11))
     refs = oracle.run_chain(cfg["chain"], cfg["frames"], [cfg["items"][b] for b in sample])
     for b, r in zip(sample, refs):
-        assert_bitexact(g[b], r["out"], f"item {b}")
+        if strict:
+            assert_bitexact(g[b], r["out"], f"item {b}")
+        else:
+            assert_close(g[b], r, s_floor=1.0, what=f"item {b}")
 
 
 def test_batched_equals_single_item_runs():

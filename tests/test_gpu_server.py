@@ -164,3 +164,44 @@ def test_release_returns_all_memory():
     reqs = requests(5, 5, max_crops=3)
     _, st = serve(reqs)
     assert st.completed == 5 and st.bytes_in_use == 0 and st.peak_bytes > 0
+
+
+def test_release_only_after_completion():
+    """A ticket's memory returns to the budget only once a poll has handed
+    out its completion: releasing an unknown ticket, a ticket not yet
+    returned by a poll (queued, running or finished unseen), or a ticket
+    twice is refused and changes nothing."""
+    say("release before completion")
+    reqs = requests(41, 3, max_crops=4)
+    desc = fk.chain_desc(CHAIN)
+    arena = torch.empty(256 << 20, dtype=torch.uint8, device="cuda:0")
+    srv = fk.fk_server_create(fk.server_opts(desc, arena, max_batch_items=64))
+    try:
+        with pytest.raises(fk.FKError) as e:
+            fk.fk_server_release(srv, 12345)
+        assert e.value.status == fk.FK_ERR_BAD_STATE
+        tickets = [fk.fk_server_submit(srv, fk.make_request(fr, cr)) for fr, cr in reqs]
+        done = set()
+        t_end = time.time() + 30
+        while len(done) < len(tickets) and time.time() < t_end:
+            for c in fk.fk_server_poll(srv, 16):
+                assert c.status == 0
+                done.add(c.ticket)
+            for t in tickets:
+                if t not in done:
+                    with pytest.raises(fk.FKError) as e:
+                        fk.fk_server_release(srv, t)
+                    assert e.value.status == fk.FK_ERR_BAD_STATE
+            time.sleep(1e-3)
+        assert done == set(tickets)
+        for t in tickets:
+            fk.fk_server_release(srv, t)
+            with pytest.raises(fk.FKError) as e:
+                fk.fk_server_release(srv, t)
+            assert e.value.status == fk.FK_ERR_BAD_STATE
+        t_end = time.time() + 5
+        while fk.fk_server_stats_get(srv).bytes_in_use and time.time() < t_end:
+            time.sleep(1e-3)
+        assert fk.fk_server_stats_get(srv).bytes_in_use == 0
+    finally:
+        fk.fk_server_destroy(srv)
