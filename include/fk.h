@@ -280,6 +280,26 @@ fk_status fk_unfused_scratch_bytes(const fk_plan *plan, const fk_item *items, in
 fk_status fk_run_unfused(fk_plan *plan, const fk_item *items, int32_t n_items, void *d_scratch,
                          int64_t scratch_bytes, void *stream);
 
+/* Workspace the library holds for fk_run_unfused_noalloc: 32 MiB per
+ * device, reserved when the library's code is loaded on that device and
+ * held until the process ends. */
+#define FK_NOALLOC_SCRATCH_BYTES (32ll << 20)
+
+/* fk_run_unfused for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, with the workspace taken from the
+ * library's own FK_NOALLOC_SCRATCH_BYTES device array instead of a caller
+ * buffer.  No hipMalloc, hipFree or other allocating call is made.  The
+ * caller still owns the frames and outputs.  Items whose workspace
+ * (fk_unfused_scratch_bytes) exceeds FK_NOALLOC_SCRATCH_BYTES are rejected
+ * with FK_ERR_UNSUPPORTED before any launch.  The first call on a device
+ * looks up the array's address there (hipGetSymbolAddress, current
+ * device).  All calls on one device share the one array and it keeps the
+ * last call's contents: calls on the same stream are ordered, calls that
+ * overlap on one device (other streams, other threads) race. */
+fk_status fk_run_unfused_noalloc(fk_plan *plan, const fk_item *items, int32_t n_items,
+                                 void *stream);
+
 /* Number of launch configurations the autotuner tries (20) and the i-th. */
 int32_t fk_autotune_space(fk_launch_config *configs, int32_t max_configs);
 

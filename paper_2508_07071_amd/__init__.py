@@ -163,6 +163,7 @@ def lib():
         "fk_unfused_scratch_bytes": ([P, C.POINTER(fk_item), C.c_int32, C.POINTER(C.c_int64)],
                                      C.c_int32),
         "fk_run_unfused": ([P, C.POINTER(fk_item), C.c_int32, P, C.c_int64, P], C.c_int32),
+        "fk_run_unfused_noalloc": ([P, C.POINTER(fk_item), C.c_int32, P], C.c_int32),
         "fk_autotune_space": ([C.POINTER(fk_launch_config), C.c_int32], C.c_int32),
         "fk_autotune": ([P, C.POINTER(fk_item), C.c_int32, C.c_int32, C.POINTER(C.c_float),
                          C.POINTER(fk_launch_config)], C.c_int32),
@@ -211,6 +212,7 @@ EXPORTS = [
     "fk_status_string", "fk_last_error", "fk_version", "fk_chain_validate", "fk_items_validate",
     "fk_plan_create", "fk_plan_destroy", "fk_plan_get_config", "fk_plan_set_config",
     "fk_plan_get_tier", "fk_run", "fk_run_timed", "fk_unfused_scratch_bytes", "fk_run_unfused",
+    "fk_run_unfused_noalloc",
     "fk_autotune_space", "fk_autotune",
     "fk_model_create", "fk_model_destroy", "fk_model_param_count", "fk_model_get_params",
     "fk_model_set_params", "fk_model_get_normalization", "fk_model_set_normalization",
@@ -407,6 +409,16 @@ def fk_unfused_scratch_bytes(plan: int, items, n: int) -> int:
 
 def fk_run_unfused(plan: int, items, n: int, scratch_ptr: int, scratch_bytes: int, stream: int) -> None:
     check(lib().fk_run_unfused(plan, items, n, scratch_ptr, scratch_bytes, stream))
+
+
+# workspace the library holds for fk_run_unfused_noalloc (include/fk.h)
+FK_NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def fk_run_unfused_noalloc(plan: int, items, n: int, stream: int) -> None:
+    """fk_run_unfused with the library's own device workspace (no device
+    allocation in the call)."""
+    check(lib().fk_run_unfused_noalloc(plan, items, n, stream))
 
 
 def fk_autotune_space() -> list:

@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 #include "fk_device.hpp"
 #include "fk_host.hpp"
@@ -391,16 +392,16 @@ static void write_out(int dt, const void *src, void *dst, int64_t npix, int C, i
         k_write<DT_F32, DTO><<<g, kUnfusedBlock, 0, st>>>((const uint8_t *)src, (uint8_t *)dst, npix, C, planar);
 }
 
-static fk_status run_item_unfused(const fk_plan *p, const fk_item &it, uint8_t *scratch,
+static fk_status run_item_unfused(const fk_plan *p, const fk_item &it, uint8_t *ws,
                                   hipStream_t st)
 {
     const int C = p->chain.read.channels;
     const int din = p->chain.read.in_dtype;
     const int es = dtype_size(din);
     const ScratchPlan sp = scratch_for(p, it);
-    uint8_t *crop = scratch;
-    float *buf[2] = {(float *)(scratch + align_up(sp.crop)),
-                     (float *)(scratch + align_up(sp.crop) + align_up(sp.buf))};
+    uint8_t *crop = ws;
+    float *buf[2] = {(float *)(ws + align_up(sp.crop)),
+                     (float *)(ws + align_up(sp.crop) + align_up(sp.buf))};
     const uint8_t *roi = (const uint8_t *)it.src.ptr + (int64_t)it.y * it.src.pitch_bytes +
                          (int64_t)it.x * C * es;
     const size_t row_bytes = (size_t)it.w * C * es;
@@ -518,7 +519,7 @@ static fk_status run_item_unfused(const fk_plan *p, const fk_item &it, uint8_t *
             cur = o;
         }
         const float *img = (const float *)cur;
-        double *part = (double *)(scratch + align_up(sp.crop) + 2 * align_up(sp.buf));
+        double *part = (double *)(ws + align_up(sp.crop) + 2 * align_up(sp.buf));
         double *out = (double *)it.dst;
         stat_pass<RED_MIN>(img, npix, C, part, out, st);
         stat_pass<RED_MAX>(img, npix, C, part, out, st);
@@ -560,29 +561,113 @@ extern "C" fk_status fk_unfused_scratch_bytes(const fk_plan *plan, const fk_item
     }
 }
 
+// Checks shared by both unfused entries; the workspace bytes the items
+// need go to `need`.
+static fk_status check_unfused(const fk_plan *plan, const fk_item *items, int32_t n_items,
+                               int64_t *need)
+{
+    if (!plan)
+        return set_error(FK_ERR_INVALID_ARG, "plan is null");
+    if (n_items < 1 || n_items > plan->max_batch)
+        return set_error(FK_ERR_INVALID_ARG, "n_items outside 1..max_batch");
+    fk_status s = validate_items(&plan->chain, items, n_items);
+    if (s)
+        return s;
+    *need = 0;
+    for (int32_t b = 0; b < n_items; ++b)
+        *need = std::max<int64_t>(*need, (int64_t)scratch_for(plan, items[b]).total());
+    return FK_OK;
+}
+
+// The items one after another, each in the whole workspace (stream order
+// keeps an item's kernels after the previous item's).
+static fk_status run_unfused_items(const fk_plan *plan, const fk_item *items, int32_t n_items,
+                                   uint8_t *ws, hipStream_t stream)
+{
+    for (int32_t b = 0; b < n_items; ++b) {
+        fk_status s = run_item_unfused(plan, items[b], ws, stream);
+        if (s)
+            return s;
+    }
+    return FK_OK;
+}
+
 extern "C" fk_status fk_run_unfused(fk_plan *plan, const fk_item *items, int32_t n_items,
                                     void *d_scratch, int64_t scratch_bytes, void *stream)
 {
     try {
-        if (!plan)
-            return set_error(FK_ERR_INVALID_ARG, "plan is null");
-        if (n_items < 1 || n_items > plan->max_batch)
-            return set_error(FK_ERR_INVALID_ARG, "n_items outside 1..max_batch");
-        fk_status s = validate_items(&plan->chain, items, n_items);
+        int64_t need = 0;
+        fk_status s = check_unfused(plan, items, n_items, &need);
         if (s)
             return s;
-        int64_t need = 0;
-        for (int32_t b = 0; b < n_items; ++b)
-            need = std::max<int64_t>(need, (int64_t)scratch_for(plan, items[b]).total());
         if (!d_scratch || scratch_bytes < need)
             return set_error(FK_ERR_INVALID_ARG, "scratch too small: %lld < %lld bytes",
                              (long long)scratch_bytes, (long long)need);
-        for (int32_t b = 0; b < n_items; ++b) {
-            s = run_item_unfused(plan, items[b], (uint8_t *)d_scratch, (hipStream_t)stream);
-            if (s)
-                return s;
-        }
-        return FK_OK;
+        return run_unfused_items(plan, items, n_items, (uint8_t *)d_scratch, (hipStream_t)stream);
+    } catch (...) {
+        return set_error(FK_ERR_INVALID_ARG, "exception");
+    }
+}
+
+// ------------------------------------------------ no-allocation variant --
+
+// Workspace of fk_run_unfused_noalloc: one copy per device, loaded with the
+// code object and held until the process ends.  Host code never passes the
+// array's name to a kernel or a copy (on the host it only names the
+// symbol); it uses the device address that hipGetSymbolAddress gives for
+// the current device.  Nothing in it has to start at zero: every
+// intermediate is written whole before it is read.
+static __device__ __align__(256) uint8_t scratch[FK_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices];  // device address of `scratch`, per device
+}  // namespace
+
+// The array's address on the current device, looked up on the first call
+// on that device.
+static fk_status scratch_address(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_error(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return set_error(FK_ERR_UNSUPPORTED, "device %d beyond the %d the workspace table holds",
+                         dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return hip_error(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr)
+            return set_error(FK_ERR_HIP, "hipGetSymbolAddress(scratch) gave a null address");
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return FK_OK;
+}
+
+extern "C" fk_status fk_run_unfused_noalloc(fk_plan *plan, const fk_item *items, int32_t n_items,
+                                            void *stream)
+{
+    try {
+        int64_t need = 0;
+        fk_status s = check_unfused(plan, items, n_items, &need);
+        if (s)
+            return s;
+        if (need > (int64_t)FK_NOALLOC_SCRATCH_BYTES)
+            return set_error(FK_ERR_UNSUPPORTED,
+                             "the items need %lld bytes of workspace; the no-allocation entry "
+                             "holds %lld",
+                             (long long)need, (long long)FK_NOALLOC_SCRATCH_BYTES);
+        void *ws = nullptr;
+        s = scratch_address(&ws);
+        if (s)
+            return s;
+        return run_unfused_items(plan, items, n_items, (uint8_t *)ws, (hipStream_t)stream);
     } catch (...) {
         return set_error(FK_ERR_INVALID_ARG, "exception");
     }
