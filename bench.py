@@ -38,10 +38,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-# fp32 FMA without packed math: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz x 2 flops
-ALU_PEAK_TFLOPS = 78.6
+# MI355X's published fp32 vector peak (packed fp32: two FMAs per lane and cycle)
+FP32_PEAK_TFLOPS = 157.3
+# This build's fp32 ceiling: the kernels are compiled without packed fp32
+# instructions, so one FMA per lane and cycle: 256 CUs x 4 SIMDs x 16 lanes
+# x 2.4 GHz x 2 flops
+FP32_ISSUE_CEILING_TFLOPS = 78.6
+# smallest HBM read request: a gather that touches one byte of a 32-byte
+# sector moves the whole sector
+SECTOR_BYTES = 32
 DEPTHS = [1, 4, 16, 64, 256]
 FRAME_HW = (2160, 3840)
+
+
+def alu_roof(tflops):
+    """Roofline record of an fp32-ALU-bound kernel: the fraction of the
+    published peak, and of this build's non-packed issue ceiling beside it."""
+    return {"bound": "alu", "achieved": round(tflops, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tflops / FP32_PEAK_TFLOPS, 4),
+            "issue_ceiling": FP32_ISSUE_CEILING_TFLOPS,
+            "frac_of_issue_ceiling": round(tflops / FP32_ISSUE_CEILING_TFLOPS, 4),
+            "peak_note": "peak = published packed-fp32 rate; the kernels are built without packed fp32 "
+                         "instructions, so issue_ceiling (one FMA per lane per cycle) is the rate they can reach"}
 
 
 def log(*a):
@@ -197,7 +215,9 @@ def vf_sweep(args):
         flops = 2.0 * (n // 2) * in_bytes + (n % 2) * in_bytes  # n element-ops per element
         d = {"n_ops": n, "kernel_ms": round(kern_ms[n], 5), "gbps": round(gbps, 1),
              "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4),
-             "alu_frac": round(flops / (kern_ms[n] * 1e-3) / 1e12 / ALU_PEAK_TFLOPS, 4),
+             "alu_frac": round(flops / (kern_ms[n] * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
+             "alu_frac_of_issue_ceiling": round(flops / (kern_ms[n] * 1e-3) / 1e12 /
+                                                FP32_ISSUE_CEILING_TFLOPS, 4),
              "launch_config": list(tuned[n][:2]), "compile_time_chain": bool(tuned[n][2])}
         if n in unfused_ms:
             ubytes = in_bytes + out_bytes + n * 2 * out_bytes  # every op reads+writes fp32
@@ -210,12 +230,10 @@ def vf_sweep(args):
 
     n = dom
     flops = 2.0 * (n // 2) * in_bytes + (n % 2) * in_bytes
-    alu_s = flops / (ALU_PEAK_TFLOPS * 1e12)
+    alu_s = flops / (FP32_PEAK_TFLOPS * 1e12)
     hbm_s = alg_bytes / (HBM_PEAK_GBPS * 1e9)
     if alu_s > hbm_s:
-        achieved = flops / (kern_ms[n] * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": ALU_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4)}
+        roof = alu_roof(flops / (kern_ms[n] * 1e-3) / 1e12)
     else:
         achieved = alg_bytes / (kern_ms[n] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
@@ -237,6 +255,10 @@ def vf_sweep(args):
                    "rotation_sets": R, "fp_mode": "strict" if args.strict else "contracted",
                    "seed": args.seed},
         "roofline": roof,
+        "hbm_bound_depths": {
+            "n_ops": [d["n_ops"] for d in per_depth if d["n_ops"] <= 16],
+            "gbps": [d["gbps"] for d in per_depth if d["n_ops"] <= 16],
+            "hbm_frac": [d["hbm_frac"] for d in per_depth if d["n_ops"] <= 16]},
         "per_depth": per_depth,
     }
     if unfused_ms:
@@ -248,6 +270,197 @@ def vf_sweep(args):
     for n in DEPTHS:
         fk.fk_plan_destroy(plans[n][0])
     return res, cfgs
+
+
+def tap_bytes(item, channels=3, pitch=None, sector=SECTOR_BYTES):
+    """Bytes the bilinear crop+resize read of one item must fetch, as
+    (distinct tapped pixels x C, the 32-byte sectors holding those bytes x
+    32), for a u8 frame with a 32-byte aligned base and the given row pitch.
+    The taps follow the read's half-pixel rule: source coordinate
+    (o + 0.5) * (w / ow) - 0.5, clamped at 0; taps at its floor and the next
+    pixel, clamped to the ROI."""
+    import numpy as np
+
+    def taps(n_out, n_in):
+        scale = np.float32(np.float32(n_in) / np.float32(n_out))
+        # (o + 0.5) * scale is exact in fp64, so one rounding to fp32 gives
+        # the fused multiply-add of the read
+        s = ((np.arange(n_out) + 0.5) * np.float64(scale) - 0.5).astype(np.float32)
+        lo = np.minimum(np.floor(np.maximum(s, 0)).astype(np.int64), n_in - 1)
+        return np.unique(np.concatenate([lo, np.minimum(lo + 1, n_in - 1)]))
+
+    X = taps(item["out_w"], item["w"])
+    Y = taps(item["out_h"], item["h"])
+    pitch = pitch or 3840 * channels
+    offs = ((item["x"] + X)[:, None] * channels + np.arange(channels)[None, :]).ravel()
+    secs = np.unique(((item["y"] + Y)[:, None] * pitch + offs[None, :]) // sector)
+    return len(X) * len(Y) * channels, len(secs) * sector
+
+
+def hot_chain_rows(args):
+    """The hot chain (crop + bilinear resize -> BGR->RGB -> fp32 -> *1/255 ->
+    -mean -> /std -> planar split) at the sizes of config 0 (one 512x512 crop
+    of a 1920x1080 frame -> 224x224) and config 2 (B uneven crops of a
+    3840x2160 frame -> 64x128 into one [B][3][128][64] tensor, B in
+    {1, 8, 50, 256}), plus a point beyond the configs: 4096 crops over 24
+    distinct 3840x2160 frames (597 MB of frames).
+
+    Per row: the autotuned launch config; the kernel's device time from the
+    events its own launch records (mean over reps), cold (each launch
+    preceded by a 512 MB read of another buffer, which evicts the frame from
+    the 256 MB Infinity Cache) and warm (back to back on one frame); the
+    time per fk_run call back to back (host launch included), the same with
+    graph replay, one fused launch per crop, and the unfused baseline;
+    algorithmic bytes (distinct tapped bytes + outputs), the 32-byte sectors
+    those taps fall in + outputs (what HBM must move), and GB/s and HBM
+    fractions of both over the cold kernel time."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2508_07071_amd as fk
+
+    dev = torch.device("cuda:0")
+    stream = fk.stream_handle()
+    gather = fk.FK_GATHER_LDS if args.gather == "lds" else fk.FK_GATHER_DIRECT
+    flush_buf = torch.ones(512 << 20, dtype=torch.uint8, device=dev)
+
+    def flush():
+        flush_buf.max()  # reads 512 MB, writes one byte
+
+    def events(k):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(k)]
+        for a, b in ev:
+            a.record()
+            b.record()
+        torch.cuda.synchronize()
+        return ev
+
+    def kernel_us(plan, arrs, n, reps, flushed=False):
+        """Mean device time of `reps` launches that record their own start
+        and end events; launch i takes argument set i % len(arrs)."""
+        ev = events(reps)
+        fk.fk_run(plan, arrs[-1], n, stream)
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(ev):
+            if flushed:
+                flush()
+            fk.fk_run_timed(plan, arrs[i % len(arrs)], n, stream, a.cuda_event, b.cuda_event)
+        torch.cuda.synchronize()
+        return 1e3 * float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    def row(name, chain, frames_np, items, out_shape, reps, baselines=True, beyond=False):
+        B = len(items)
+        # copies of the frame set (and outputs), at least 600 MB of frames in
+        # all, so that launches rotating over them read HBM, not the cache
+        set_bytes = sum(f.nbytes for f in frames_np)
+        R = max(1, min(128, -(-600_000_000 // set_bytes)))
+        arrs, keep = [], []
+        for _ in range(R):
+            frames = [torch.from_numpy(f).to(dev) for f in frames_np]
+            out = torch.empty(out_shape, dtype=torch.float32, device=dev)
+            outs = [out[b] for b in range(B)] if len(out_shape) == 4 else [out]
+            arrs.append(fk.make_items(chain, frames, items, outs))
+            keep.append((frames, out))
+        frames, out = keep[0]
+        outs = [out[b] for b in range(B)] if len(out_shape) == 4 else [out]
+        arr = arrs[0]
+        desc = fk.chain_desc(chain)
+        C = chain["read"]["channels"]
+        tb = np.array([tap_bytes(it, C, frames_np[it["frame"]].shape[1] * C) for it in items]).sum(0)
+        out_b = sum(it["out_w"] * it["out_h"] * C * 4 for it in items)
+        r = {"case": name, "batch": B, "gather": args.gather, "alg_bytes": int(tb[0]) + out_b,
+             "sector_bytes": int(tb[1]) + out_b, "rotation_sets": R,
+             "rotation_mb": round(R * set_bytes / 1e6, 1)}
+        if beyond:
+            r["beyond_configs"] = True
+        h = fk.fk_plan_create(desc, B, fk.plan_opts(gather=gather))
+        if name in fixed:
+            best = fk.fk_launch_config(*fixed[name])
+            fk.fk_plan_set_config(h, best)
+        else:
+            best, _ = fk.fk_autotune(h, arr, B, 10)
+        r["autotuned"] = [best.block_threads, best.coarsen]
+        r["kernel_us"] = round(kernel_us(h, arrs, B, reps), 2)
+        for key, b in (("gbps", r["alg_bytes"]), ("gbps_sector", r["sector_bytes"])):
+            r[key] = round(b / (r["kernel_us"] * 1e-6) / 1e9, 1)
+        r["hbm_frac"] = round(r["gbps"] / HBM_PEAK_GBPS, 4)
+        r["hbm_frac_sector"] = round(r["gbps_sector"] / HBM_PEAK_GBPS, 4)
+        if args.hot_profile:
+            fk.fk_plan_destroy(h)
+            log(r)
+            return r
+        r["kernel_us_flushed"] = round(kernel_us(h, arrs[:1], B, reps, flushed=True), 2)
+        r["kernel_us_warm"] = round(kernel_us(h, arrs[:1], B, reps), 2)
+        r["call_us"] = round(1e3 * timeit(lambda: fk.fk_run(h, arr, B, stream), reps, warm_s=2e-3), 2)
+        if baselines:
+            singles = [fk.make_items(chain, frames, [it], [outs[b]]) for b, it in enumerate(items)]
+            r["per_crop_us"] = round(1e3 * timeit(lambda: [fk.fk_run(h, s1, 1, stream) for s1 in singles],
+                                                  max(2, reps // 20)), 2)
+            nbytes = fk.fk_unfused_scratch_bytes(h, arr, B)
+            scratch = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            r["unfused_us"] = round(1e3 * timeit(
+                lambda: fk.fk_run_unfused(h, arr, B, scratch.data_ptr(), nbytes, stream),
+                max(2, reps // 40)), 2)
+            del scratch
+            r["speedup_vs_unfused"] = round(r["unfused_us"] / r["call_us"], 2)
+            r["speedup_vs_per_crop"] = round(r["per_crop_us"] / r["call_us"], 2)
+        fk.fk_plan_destroy(h)
+        if baselines:
+            hg = fk.fk_plan_create(desc, B, fk.plan_opts(use_graph=True, gather=gather))
+            fk.fk_plan_set_config(hg, best)
+            r["graph_call_us"] = round(1e3 * timeit(lambda: fk.fk_run(hg, arr, B, stream), reps,
+                                                    warm_s=2e-3), 2)
+            fk.fk_plan_destroy(hg)
+        log(r)
+        return r
+
+    # launch configs from an earlier run's JSON line (profiler runs), by case
+    fixed = {}
+    if args.hot_configs:
+        with open(args.hot_configs) as f:
+            prev = json.loads([ln for ln in f if ln.strip().startswith("{")][-1])
+        fixed = {r["case"]: tuple(r["autotuned"]) for r in prev.get("per_config", [])}
+
+    rows = []
+    c0 = datagen.config0(seed=args.seed)
+    reps = args.hot_reps
+    rows.append(row("config0: 512x512 crop of 1920x1080 -> 224x224", c0["chain"], c0["frames"],
+                    c0["items"], (3, 224, 224), reps))
+    for B in (1, 8, 50, 256):
+        c2 = datagen.config2(B, seed=args.seed)
+        rows.append(row(f"config2: B={B} crops of 3840x2160 -> 64x128", c2["chain"], c2["frames"],
+                        c2["items"], (B, 3, 128, 64), reps))
+    g = datagen.rng(args.seed + 77)
+    n_frames = 24
+    frames = [datagen.frame(g, 2160, 3840, 3) for _ in range(n_frames)]
+    items = []
+    for f in range(n_frames):
+        items += datagen.random_crops(g, 4096 // n_frames + (f < 4096 % n_frames), 3840, 2160, frame_index=f)
+    rows.append(row("4096 crops over 24 distinct 3840x2160 frames -> 64x128", datagen.normalize_chain(64, 128),
+                    frames, items, (len(items), 3, 128, 64), max(5, reps // 4), baselines=False,
+                    beyond=True))
+    return rows
+
+
+def serving_row(args, rate=1000.0, n=2000):
+    """One serving point of config 4: Poisson arrivals at `rate` req/s, n
+    requests, continuous batching and per-request fused launches, 64 GB
+    arena and budget."""
+    import torch
+
+    import paper_2508_07071_amd as fk
+    from paper_2508_07071_amd import serve
+
+    arena = torch.empty(64 << 30, dtype=torch.uint8, device=torch.device("cuda:0"))
+    pool = serve.make_pool(8, seed=args.seed)
+    out = {}
+    for mode, name in ((fk.FK_SERVER_BATCHED, "batched"), (fk.FK_SERVER_PER_REQUEST, "per_request")):
+        r = serve.run(rate, n, mode, pool, arena, seed=args.seed, budget_bytes=64 << 30)
+        log(r)
+        out[name] = r
+    del arena
+    return out
 
 
 def measured_traffic(n_ops):
@@ -268,25 +481,84 @@ def measured_traffic(n_ops):
         return None
 
 
-def cpu_baseline_vf(args, cfgs):
-    """The oracle, single-threaded, on a band of rows through the sweep."""
+def _oracle_band(job):
+    """Worker of the all-core CPU baseline: the oracle on one band of rows
+    through every depth (a separate process, no GPU)."""
     import numpy as np
 
     import datagen
     import oracle
 
-    rows = args.cpu_rows
+    band, chains = job
+    band = np.ascontiguousarray(band)
+    item = datagen.whole_frame_item(band)
+    t0 = time.perf_counter()
+    for chain in chains:
+        oracle.run_chain(chain, [band], [item], shadow=False)
+    return time.perf_counter() - t0
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_vf(args, cfgs):
+    """The oracle as it stands (per-op fp32 passes over the whole image, no
+    fp64 shadow) on the host: one thread on a band of rows, and every core
+    of this process's affinity set (at most 16 worker processes) on the
+    whole frame split into bands; the oracle's time for config 0 and for
+    config 2 at B = 256, single-threaded."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import datagen
+    import oracle
+
     frame = cfgs[DEPTHS[0]]["frames"][0]
+    H = frame.shape[0]
+    rows = min(args.cpu_rows, H)
     band = np.ascontiguousarray(frame[:rows])
     item = datagen.whole_frame_item(band)
     t0 = time.perf_counter()
     for n in DEPTHS:
-        oracle.run_chain(cfgs[n]["chain"], [band], [item], shadow=True)
-    dt = time.perf_counter() - t0
-    alg = len(DEPTHS) * band.size * (1 + 4)
-    return {"value": round(alg / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"rows 0..{rows - 1} of the 3840x2160 frame ({band.size} elements) through "
-                      f"all five depths, {dt:.1f} s; unfused per-op fp32 with fp64 shadow"}
+        oracle.run_chain(cfgs[n]["chain"], [band], [item], shadow=False)
+    dt1 = time.perf_counter() - t0
+    single = {"value": round(len(DEPTHS) * band.size * 5 / dt1 / 1e9, 4), "unit": "GB/s", "cores": 1,
+              "sample": f"rows 0..{rows - 1} of the 3840x2160 frame through all five depths, {dt1:.1f} s"}
+
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    chains = [cfgs[n]["chain"] for n in DEPTHS]
+    cuts = np.linspace(0, H, workers + 1).astype(int)
+    bands = [(frame[a:b], chains) for a, b in zip(cuts[:-1], cuts[1:])]
+    with mp.get_context("spawn").Pool(workers) as pool:
+        pool.map(_oracle_band, [(frame[:8], chains)] * workers)  # start and import in every worker
+        t0 = time.perf_counter()
+        per = pool.map(_oracle_band, bands)
+        dtn = time.perf_counter() - t0
+    res = {"value": round(len(DEPTHS) * frame.size * 5 / dtn / 1e9, 4), "unit": "GB/s", "cores": workers,
+           "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": f"the whole 3840x2160 frame in {workers} row bands, one worker process each, "
+                     f"through all five depths: {dtn:.1f} s wall ({sum(per):.1f} s of worker time); "
+                     f"unfused per-op fp32 passes, no fp64 shadow",
+           "single_thread": single}
+
+    c0 = datagen.config0(seed=args.seed)
+    t0 = time.perf_counter()
+    oracle.run_chain(c0["chain"], c0["frames"], c0["items"], shadow=False)
+    res["config0_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+    c2 = datagen.config2(256, seed=args.seed)
+    t0 = time.perf_counter()
+    oracle.run_chain(c2["chain"], c2["frames"], c2["items"], shadow=False)
+    res["config2_b256_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+    return res
 
 
 def hf_workload(args):
@@ -444,7 +716,8 @@ def loop_workload(args):
             r["speedup_vs_unfused"] = round(r["unfused_ms"] / r["fused_ms"], 1)
             del scratch
         r["tflops"] = round(flops / (r["fused_ms"] * 1e-3) / 1e12, 3)
-        r["alu_frac"] = round(r["tflops"] / ALU_PEAK_TFLOPS, 4)
+        r["alu_frac"] = round(r["tflops"] / FP32_PEAK_TFLOPS, 4)
+        r["alu_frac_of_issue_ceiling"] = round(r["tflops"] / FP32_ISSUE_CEILING_TFLOPS, 4)
         r["gbps"] = round(alg_bytes / (r["fused_ms"] * 1e-3) / 1e9, 1)
         r["speedup_hf_vs_per_image"] = round(r["per_image_ms"] / r["fused_ms"], 2)
         fk.fk_plan_destroy(plan)
@@ -463,7 +736,8 @@ def loop_workload(args):
     fk.fk_plan_destroy(plan)
     tf = 2.0 * big_p * big_b * h * w / (ms * 1e-3) / 1e12
     big = {"pairs": big_p, "batch": big_b, "beyond_configs": True, "fused_ms": round(ms, 5),
-           "tflops": round(tf, 3), "alu_frac": round(tf / ALU_PEAK_TFLOPS, 4)}
+           "tflops": round(tf, 3), "alu_frac": round(tf / FP32_PEAK_TFLOPS, 4),
+           "alu_frac_of_issue_ceiling": round(tf / FP32_ISSUE_CEILING_TFLOPS, 4)}
     log(big)
     top = rows[-1]
     tot_flops = sum(2.0 * r["pairs"] * elems for r in rows)
@@ -474,8 +748,7 @@ def loop_workload(args):
            "config": {"workload": "vf_hf_loop: 50 x 60x120 u8 images, cvt + P (mul, add) pairs via the loop op, "
                                   "packed fp32", "pairs": LOOP_PAIRS, "batch": B,
                       "fp_mode": "strict" if args.strict else "contracted", "seed": args.seed},
-           "roofline": {"bound": "alu", "achieved": top["tflops"], "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": top["alu_frac"], "traffic": None,
+           "roofline": {**alu_roof(top["tflops"]), "traffic": None,
                         "kernel": f"fused loop chain, {top['pairs']} pairs, 50 x 60x120 u8 -> packed fp32",
                         "kernel_ms": top["fused_ms"]},
            "rows": rows, "large_batch": big}
@@ -705,8 +978,7 @@ def sweeps_workload(args):
             "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "sweeps: data size (VI-G), plain-read HF (VI-C), data types (VI-I)",
                        "seed": args.seed},
-            "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                         "frac": round(tf / ALU_PEAK_TFLOPS, 4), "traffic": None,
+            "roofline": {**alu_roof(tf), "traffic": None,
                          "kernel": f"fused 100 mul+add pairs over {n} fp32 values", "kernel_ms": top["fused_ms"]},
             "data_size": data_size, "hf_plain": hf_plain, "dtypes": dtypes, "instructions_per_op": per_op}
 
@@ -882,6 +1154,31 @@ def copy_workload(args):
             "ms": round(ms, 5), "gbps": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
 
 
+def trace_summary(path, what):
+    """Markdown rows from a rocprofv3 CSV, one per (kernel, grid, block):
+    kernel durations from a kernel trace (what = "trace"), or the average
+    counter value per dispatch from a counter collection (what = "pmc")."""
+    import csv
+    from collections import defaultdict
+
+    groups = defaultdict(list)
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            key = (r["Kernel_Name"], r.get("Grid_Size", r.get("Grid_Size_X", "")),
+                   r.get("Workgroup_Size", r.get("Workgroup_Size_X", "")),
+                   r.get("Stream_Id", r.get("Queue_Id", "")), r.get("Counter_Name", ""))
+            if what == "trace":
+                groups[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+            else:
+                groups[key].append(float(r["Counter_Value"]))
+    unit = "us" if what == "trace" else "per dispatch"
+    print(f"| kernel | grid (threads) | block | stream/queue | counter | dispatches | avg {unit} | min | max |")
+    print("|---|---|---|---|---|---|---|---|---|")
+    for (k, g, b, q, c), v in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+        print(f"| `{k}` | {g} | {b} | {q} | {c} | {len(v)} | {sum(v) / len(v):.2f} | {min(v):.2f} | "
+              f"{max(v):.2f} |")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -902,8 +1199,29 @@ def main():
                     help="autotune each depth's launch config first (default: the library default)")
     ap.add_argument("--no-unfused", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=2160)
+    ap.add_argument("--cpu-rows", type=int, default=432)
+    ap.add_argument("--no-hot-chain", action="store_true",
+                    help="skip the config 0 / config 2 rows")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving row")
+    ap.add_argument("--hot-profile", action="store_true",
+                    help="config 0 / config 2 rows: autotune and the rotating timed launches only "
+                         "(for profiler runs: one kernel-trace row per batch size)")
+    ap.add_argument("--hot-configs", metavar="JSON",
+                    help="take the config 0 / config 2 launch configs from this earlier bench output "
+                         "instead of autotuning")
+    ap.add_argument("--gather", choices=["direct", "lds"], default="direct",
+                    help="config 0 / config 2 rows: the tap reads of the bilinear gather "
+                         "(direct per-pixel loads, or rows staged in LDS)")
+    ap.add_argument("--hot-reps", type=int, default=200,
+                    help="timed launches per measurement in the config 0 / config 2 rows")
+    ap.add_argument("--trace-summary", metavar="CSV",
+                    help="print a rocprofv3 kernel-trace CSV as markdown rows per kernel, grid and block")
+    ap.add_argument("--pmc-summary", metavar="CSV",
+                    help="the same for a rocprofv3 counter-collection CSV")
     args = ap.parse_args()
+    if args.trace_summary or args.pmc_summary:
+        trace_summary(args.trace_summary or args.pmc_summary, "trace" if args.trace_summary else "pmc")
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -937,6 +1255,12 @@ def main():
         print(json.dumps(copy_workload(args)))
         return
     res, cfgs = vf_sweep(args)
+    if not args.no_hot_chain:
+        log("hot chain rows ...")
+        res["per_config"] = hot_chain_rows(args)
+    if not args.no_serving:
+        log("serving row ...")
+        res["serving"] = serving_row(args)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         res["cpu_baseline"] = cpu_baseline_vf(args, cfgs)

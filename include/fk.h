@@ -205,7 +205,18 @@ typedef struct {
                                     op is one kernel applying it loop_count times
                                     (an op of that many instructions, Section
                                     VI-E); 0 = one kernel per run of the op */
+    int32_t gather;          /* FK_GATHER_*: how the compile-time normalise
+                                chain (crop + bilinear resize of a u8 BGR frame
+                                -> planar fp32) reads its taps; other chains
+                                ignore it */
 } fk_plan_opts;
+
+#define FK_GATHER_DIRECT 0   /* each lane loads its taps' byte windows from the frame */
+#define FK_GATHER_LDS 1      /* a block stages the tap rows of a band of output rows in
+                                LDS with 16-byte loads over the ROI's width, then reads
+                                the taps from LDS (same results); items whose frame base
+                                or pitch is not a multiple of 16 bytes, or whose staged
+                                rows do not fit, read directly */
 
 typedef struct fk_plan fk_plan;
 

@@ -35,6 +35,7 @@ FK_READ_PLAIN, FK_READ_CROP_RESIZE, FK_READ_CROP_NEAREST, FK_READ_NV12, FK_READ_
 FK_OP_SWAP_RB, FK_OP_CVT_F32, FK_OP_MUL, FK_OP_ADD, FK_OP_SUB, FK_OP_DIV, FK_OP_LOOP = range(7)
 FK_CONFIG_DEFAULT, FK_CONFIG_MANUAL, FK_CONFIG_AUTOTUNE, FK_CONFIG_MODEL = range(4)
 FK_TIER_AUTO, FK_TIER_RUNTIME = 0, 1
+FK_GATHER_DIRECT, FK_GATHER_LDS = 0, 1
 
 DTYPE = {"u8": FK_U8, "f16": FK_F16, "f32": FK_F32, "f64": FK_F64}
 LAYOUT = {"packed": FK_PACKED, "planar": FK_PLANAR, "stats": FK_STATS}
@@ -84,7 +85,8 @@ class fk_launch_config(C.Structure):
 
 class fk_plan_opts(C.Structure):
     _fields_ = [("config_source", C.c_int32), ("manual", fk_launch_config), ("use_graph", C.c_int32),
-                ("strict_fp", C.c_int32), ("tier", C.c_int32), ("unfused_loop_kernel", C.c_int32)]
+                ("strict_fp", C.c_int32), ("tier", C.c_int32), ("unfused_loop_kernel", C.c_int32),
+                ("gather", C.c_int32)]
 
 
 class fk_crop(C.Structure):
@@ -675,8 +677,9 @@ def output_offsets(chain: dict, crops) -> list:
 
 
 def plan_opts(config_source=FK_CONFIG_DEFAULT, manual=(256, 1), use_graph=False, strict=False,
-              tier=FK_TIER_AUTO, unfused_loop_kernel=False) -> fk_plan_opts:
+              tier=FK_TIER_AUTO, unfused_loop_kernel=False, gather=FK_GATHER_DIRECT) -> fk_plan_opts:
     o = fk_plan_opts()
+    o.gather = gather
     o.config_source = config_source
     o.manual.block_threads, o.manual.coarsen = manual
     o.use_graph = int(bool(use_graph))

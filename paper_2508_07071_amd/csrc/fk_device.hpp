@@ -232,27 +232,43 @@ struct ReadCropResize {
         int x0, x1;
         float ax;
         bilinear_coord(ox, it.sx, it.w, x0, x1, ax);
-        float p00[C], p01[C], p10[C], p11[C];
         if (DT == DT_U8 && win) {
             uint32_t t[2], b[2];
             window((uint64_t)(uintptr_t)(r0 + x0 * C), t);
             window((uint64_t)(uintptr_t)(r1 + x0 * C), b);
-            const int o1 = (x1 == x0) ? 0 : C;  // clamped tap: the same pixel
+            lerp_windows(t, b, x1 == x0, ax, ay, r);
+            return;
+        }
+        float p00[C], p01[C], p10[C], p11[C];
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                p00[c] = byte_at(t, c);
-                p01[c] = byte_at(t, o1 + c);
-                p10[c] = byte_at(b, c);
-                p11[c] = byte_at(b, o1 + c);
-            }
-        } else {
+        for (int c = 0; c < C; ++c) {
+            p00[c] = load_elem<DT>(r0 + (x0 * C + c) * ES);
+            p01[c] = load_elem<DT>(r0 + (x1 * C + c) * ES);
+            p10[c] = load_elem<DT>(r1 + (x0 * C + c) * ES);
+            p11[c] = load_elem<DT>(r1 + (x1 * C + c) * ES);
+        }
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                p00[c] = load_elem<DT>(r0 + (x0 * C + c) * ES);
-                p01[c] = load_elem<DT>(r0 + (x1 * C + c) * ES);
-                p10[c] = load_elem<DT>(r1 + (x0 * C + c) * ES);
-                p11[c] = load_elem<DT>(r1 + (x1 * C + c) * ES);
-            }
+        for (int c = 0; c < C; ++c) {
+            const float top = fmaf(ax, p01[c] - p00[c], p00[c]);
+            const float bot = fmaf(ax, p11[c] - p10[c], p10[c]);
+            r[c] = fmaf(ay, bot - top, top);
+        }
+    }
+
+    // the pixel from the byte windows of its top and bottom tap rows (tap
+    // pair at bytes [0, 2C), or one pixel at [0, C) when the right tap is
+    // clamped onto the left one)
+    __device__ __forceinline__ static void lerp_windows(const uint32_t (&t)[2], const uint32_t (&b)[2],
+                                                        bool clamped, float ax, float ay, float (&r)[C])
+    {
+        const int o1 = clamped ? 0 : C;
+        float p00[C], p01[C], p10[C], p11[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            p00[c] = byte_at(t, c);
+            p01[c] = byte_at(t, o1 + c);
+            p10[c] = byte_at(b, c);
+            p11[c] = byte_at(b, o1 + c);
         }
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -1149,10 +1165,86 @@ __global__ __launch_bounds__(kMaxBlock) void k_transform(const KArgs a)
 // instruction.  Tiles are those of k_transform (T * K units = 4 T K
 // pixels); the per-pixel planar stores of consecutive lanes are
 // consecutive.
+// Store pixel i's C channels of v to its planar output position.
+template <int DO, int C>
+__device__ __forceinline__ void store_planar_px(gdst_t dst, int64_t plane, const ItemRec &it, int oy,
+                                                int ox, const float (&v)[C])
+{
+    constexpr int ES = DSize<DO>::v;
+    // below ow * oh < 2^32
+    const uint32_t p = __umul24((uint32_t)oy, (uint32_t)it.ow) + (uint32_t)ox;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        store_elem<DO>(dst + (c * plane + (int64_t)p) * ES, v[c]);
+}
+
+// The chain on 4 gathered pixels per lane (v), then their planar stores;
+// oy[i] < 0 marks a lane's pixel outside the tile.
+template <class Compute, int DO, int C>
+__device__ __forceinline__ void chain_store_px(const KArgs &a, const ItemRec &it, float (&v)[1][kUnitPx][C],
+                                               const int (&oy)[kUnitPx], const int (&ox)[kUnitPx])
+{
+    if constexpr (C >= 3) {
+        // run-time tier: the chain's net channel swap, applied at the read
+        if (a.swap) {
+#pragma unroll
+            for (int i = 0; i < kUnitPx; ++i) {
+                const float t = v[0][i][0];
+                v[0][i][0] = v[0][i][2];
+                v[0][i][2] = t;
+            }
+        }
+    }
+
+    Compute::template apply<1, C>(a, v);
+
+    const int64_t plane = (int64_t)it.ow * it.oh;
+#pragma unroll
+    for (int i = 0; i < kUnitPx; ++i)
+        if (oy[i] >= 0)
+            store_planar_px<DO, C>((gdst_t)it.dst, plane, it, oy[i], ox[i], v[0][i]);
+}
+
+// One tile of pixel-strided lanes: output pixels [pbase, pbase + 4 T K)
+// of the item, pixel pbase + q T + t on lane t.
+template <class Read, class Compute, int DO, int C, int K>
+__device__ __forceinline__ void px_tile(const KArgs &a, const ItemRec &it, uint32_t ubase, int T, int tid)
+{
+    const uint32_t npx = (uint32_t)it.ow * (uint32_t)it.oh;  // < 2^32
+    const uint32_t pbase = ubase * kUnitPx;
+    const RowDiv rowdiv((uint32_t)it.ow);  // exact below 2^28 pixels
+    const bool big = npx >= (1u << 28);
+    const bool prep = Read::px_prep(it);
+
+    // groups of 4 pixels per lane, one after another: registers do not
+    // grow with K (K only sizes the tile)
+    for (int j = 0; j < K; ++j) {
+        float v[1][kUnitPx][C];
+        int oy[kUnitPx], ox[kUnitPx];
+#pragma unroll
+        for (int i = 0; i < kUnitPx; ++i) {
+            const uint32_t q = (uint32_t)(j * kUnitPx + i);
+            const uint32_t p = pbase + q * (uint32_t)T + (uint32_t)tid;
+            if (p < npx && p >= pbase) {
+                const uint32_t row = big ? p / (uint32_t)it.ow : rowdiv(p);
+                oy[i] = (int)row;
+                ox[i] = (int)(p - __umul24(row, (uint32_t)it.ow));
+                Read::load_px(it, prep, oy[i], ox[i], v[0][i]);
+            } else {
+                oy[i] = -1;
+                ox[i] = 0;
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    v[0][i][c] = 0.0f;
+            }
+        }
+        chain_store_px<Compute, DO, C>(a, it, v, oy, ox);
+    }
+}
+
 template <class Read, class Compute, int DO, int C, int K>
 __global__ __launch_bounds__(kMaxBlock) void k_resize_px(const KArgs a)
 {
-    constexpr int ES = DSize<DO>::v;
     const FK_CONST KArgs *ka = (const FK_CONST KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
     const bool inl = a.inl_n > 0;
     const bool compact = inl && a.inl_compact;
@@ -1164,65 +1256,150 @@ __global__ __launch_bounds__(kMaxBlock) void k_resize_px(const KArgs a)
     const int T = blockDim.x;
     const int tid = threadIdx.x;
     const uint32_t tile_units = (uint32_t)T * K;
-    const bool swap = a.swap != 0;
 
     for (uint32_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
         ItemRec it;
         uint32_t ubase;
         tile_item<Read, C>(a, ka, compact, tb, items, n_items, tile, total, tile_units, it, ubase);
-        const uint32_t npx = (uint32_t)it.ow * (uint32_t)it.oh;  // < 2^32
-        const uint32_t pbase = ubase * kUnitPx;
-        const RowDiv rowdiv((uint32_t)it.ow);  // exact below 2^28 pixels
-        const bool big = npx >= (1u << 28);
-        const bool prep = Read::px_prep(it);
+        px_tile<Read, Compute, DO, C, K>(a, it, ubase, T, tid);
+    }
+}
 
-        const int64_t plane = (int64_t)it.ow * it.oh;
-        gdst_t dst = (gdst_t)it.dst;
-        // groups of 4 pixels per lane, one after another: registers do not
-        // grow with K (K only sizes the tile)
-        for (int j = 0; j < K; ++j) {
-            float v[1][kUnitPx][C];
-            int oy[kUnitPx], ox[kUnitPx];
-#pragma unroll
-            for (int i = 0; i < kUnitPx; ++i) {
-                const uint32_t q = (uint32_t)(j * kUnitPx + i);
-                const uint32_t p = pbase + q * (uint32_t)T + (uint32_t)tid;
-                if (p < npx && p >= pbase) {
-                    const uint32_t row = big ? p / (uint32_t)it.ow : rowdiv(p);
-                    oy[i] = (int)row;
-                    ox[i] = (int)(p - __umul24(row, (uint32_t)it.ow));
-                    Read::load_px(it, prep, oy[i], ox[i], v[0][i]);
-                } else {
-                    oy[i] = -1;
-                    ox[i] = 0;
-#pragma unroll
-                    for (int c = 0; c < C; ++c)
-                        v[0][i][c] = 0.0f;
-                }
+// ------------------------------- bilinear gather from LDS-staged rows --
+// The pixel-strided pattern with the tapped source rows staged in LDS
+// (u8 frames).  A tile's output rows are taken a band at a time: the two
+// tap rows of every output row of the band are copied from the frame into
+// LDS over the ROI's whole width, in 16-byte chunks (each load instruction
+// of a wave reads up to 1 KiB of consecutive bytes), and after a barrier
+// the lanes read their taps from LDS as two aligned 8-byte reads per tap
+// row, from which the same byte window as the global read is cut out (the
+// interpolation is ReadCropResize's, so the results are the same bits).
+// Items whose frame base or pitch is not a multiple of 16, whose staged row
+// does not fit twice in the block's LDS, or whose last 16-byte chunk would
+// pass the end of the frame's last row take the direct per-pixel gathers.
+struct LdsGather {
+    uint32_t start;   // first staged byte of a row, from the row's base (16-aligned)
+    uint32_t n16;     // 16-byte chunks per staged row
+    uint32_t stride;  // LDS bytes per staged row: the chunks + 16 bytes of slack
+                      // for the 8-byte reads past the last tap
+    uint32_t band;    // output rows per band (two staged rows each)
+};
+
+template <int C>
+__device__ __forceinline__ bool lds_gather_plan(const ItemRec &it, uint32_t lds, LdsGather &g)
+{
+    if ((it.src & 15u) || (it.pitch & 15))
+        return false;
+    const uint32_t b0 = (uint32_t)it.x * C, b1 = (uint32_t)(it.x + it.w) * C;
+    g.start = b0 & ~15u;
+    const uint32_t end = (b1 + 15u) & ~15u;
+    // the chunk holding a row's last ROI byte ends inside the row's pitch;
+    // on the frame's last row it must also end inside the row's pixels
+    if (it.y + it.h >= (int)it.fh && end > (uint32_t)it.fw * C)
+        return false;
+    g.n16 = (end - g.start) >> 4;
+    g.stride = end - g.start + 16u;
+    g.band = lds / (2u * g.stride);
+    return g.band >= 1;
+}
+
+// bytes [0, 8) from LDS byte address a (any alignment), as two dwords
+__device__ __forceinline__ void lds_window(const uint8_t *lds, uint32_t a, uint32_t (&d)[2])
+{
+    const uint32_t a8 = a & ~7u;
+    const ux2 lo = *(const ux2 *)(lds + a8);
+    const ux2 hi = *(const ux2 *)(lds + a8 + 8);
+    const bool k = (a & 4u) != 0;
+    const uint32_t sh = a & 3u;
+    const uint32_t w0 = k ? lo.y : lo.x;
+    const uint32_t w1 = k ? hi.x : lo.y;
+    const uint32_t w2 = k ? hi.y : hi.x;
+    d[0] = __builtin_amdgcn_alignbyte(w1, w0, sh);
+    d[1] = __builtin_amdgcn_alignbyte(w2, w1, sh);
+}
+
+template <class Compute, int DO, int C, int K>
+__global__ __launch_bounds__(kMaxBlock) void k_resize_lds(const KArgs a)
+{
+    using Read = ReadCropResize<DT_U8, C>;
+    extern __shared__ __align__(16) uint8_t lds[];
+    const FK_CONST KArgs *ka = (const FK_CONST KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    const bool inl = a.inl_n > 0;
+    const bool compact = inl && a.inl_compact;
+    const FK_CONST uint32_t *tb =
+        inl ? (const FK_CONST uint32_t *)(ka->inl + kInlineTileBegin) : cptr(a.tile_begin);
+    const FK_CONST ItemRec *items = inl ? (const FK_CONST ItemRec *)ka->inl : cptr(a.items);
+    const int n_items = inl ? a.inl_n : cptr(a.hdr)->n_items;
+    const uint32_t total = inl ? a.inl_total_tiles : cptr(a.hdr)->total_tiles;
+    const int T = blockDim.x;
+    const int tid = threadIdx.x;
+    const uint32_t tile_units = (uint32_t)T * K;
+    const uint32_t lds_bytes = lds_gather_bytes((uint32_t)T);
+
+    for (uint32_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        ItemRec it;
+        uint32_t ubase;
+        tile_item<Read, C>(a, ka, compact, tb, items, n_items, tile, total, tile_units, it, ubase);
+        LdsGather g;
+        const uint32_t npx = (uint32_t)it.ow * (uint32_t)it.oh;
+        // uniform over the block: every lane takes the same branch
+        if (npx >= (1u << 28) || !lds_gather_plan<C>(it, lds_bytes, g)) {
+            px_tile<Read, Compute, DO, C, K>(a, it, ubase, T, tid);
+            continue;
+        }
+        const uint32_t ow = (uint32_t)it.ow;
+        const uint32_t pbase = ubase * kUnitPx;
+        const uint32_t pend = min(pbase + (uint32_t)kUnitPx * tile_units, npx);
+        const RowDiv rowdiv(ow);
+        const RowDiv chunkdiv(g.n16);
+        const uint32_t r_last = rowdiv(pend - 1);
+        gsrc_t rowbase = (gsrc_t)it.src + g.start;
+        for (uint32_t r0 = rowdiv(pbase); r0 <= r_last; r0 += g.band) {
+            const uint32_t nr = min(g.band, r_last + 1 - r0);
+            __syncthreads();  // every lane is done with the previous band (or tile)
+            for (uint32_t i = tid; i < 2u * nr * g.n16; i += (uint32_t)T) {
+                const uint32_t slot = chunkdiv(i);
+                const uint32_t c = i - slot * g.n16;
+                int y0, y1;
+                float ay;
+                bilinear_coord((int)(r0 + (slot >> 1)), it.sy, it.h, y0, y1, ay);
+                const int sy = it.y + ((slot & 1u) ? y1 : y0);
+                const ux4 v = *(const FK_GLOBAL ux4 *)(rowbase + (int64_t)sy * it.pitch + c * 16u);
+                *(ux4 *)(lds + slot * g.stride + c * 16u) = v;
             }
-            if constexpr (C >= 3) {
-                // run-time tier: the chain's net channel swap, applied at the read
-                if (swap) {
+            __syncthreads();
+            const uint32_t p0 = max(pbase, r0 * ow);
+            const uint32_t p1 = min(pend, (r0 + nr) * ow);
+            for (uint32_t pb = p0; pb < p1; pb += (uint32_t)kUnitPx * (uint32_t)T) {
+                float v[1][kUnitPx][C];
+                int oy[kUnitPx], ox[kUnitPx];
 #pragma unroll
-                    for (int i = 0; i < kUnitPx; ++i) {
-                        const float t = v[0][i][0];
-                        v[0][i][0] = v[0][i][2];
-                        v[0][i][2] = t;
+                for (int i = 0; i < kUnitPx; ++i) {
+                    const uint32_t p = pb + (uint32_t)(i * T + tid);
+                    if (p < p1) {
+                        const uint32_t row = rowdiv(p);
+                        oy[i] = (int)row;
+                        ox[i] = (int)(p - __umul24(row, ow));
+                        int x0, x1, y0, y1;
+                        float ax, ay;
+                        bilinear_coord(ox[i], it.sx, it.w, x0, x1, ax);
+                        bilinear_coord(oy[i], it.sy, it.h, y0, y1, ay);
+                        const uint32_t off = (uint32_t)(it.x + x0) * C - g.start;
+                        const uint32_t top = 2u * (row - r0) * g.stride + off;
+                        uint32_t tw[2], bw[2];
+                        lds_window(lds, top, tw);
+                        lds_window(lds, top + g.stride, bw);
+                        Read::lerp_windows(tw, bw, x1 == x0, ax, ay, v[0][i]);
+                    } else {
+                        oy[i] = -1;
+                        ox[i] = 0;
+#pragma unroll
+                        for (int c = 0; c < C; ++c)
+                            v[0][i][c] = 0.0f;
                     }
                 }
+                chain_store_px<Compute, DO, C>(a, it, v, oy, ox);
             }
-
-            Compute::template apply<1, C>(a, v);
-
-#pragma unroll
-            for (int i = 0; i < kUnitPx; ++i)
-                if (oy[i] >= 0) {
-                    // below ow * oh < 2^32
-                    const uint32_t p = __umul24((uint32_t)oy[i], (uint32_t)it.ow) + (uint32_t)ox[i];
-#pragma unroll
-                    for (int c = 0; c < C; ++c)
-                        store_elem<DO>(dst + (c * plane + (int64_t)p) * ES, v[0][i][c]);
-                }
         }
     }
 }

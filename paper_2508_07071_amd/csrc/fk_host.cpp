@@ -229,6 +229,8 @@ const void *fk::plan_kernel(const fk_plan *p, const fk_launch_config &cfg, bool 
     }
     switch (p->family) {
     case FAM_NORMALIZE:
+        if (p->opts.gather == FK_GATHER_LDS)
+            return kernel_normalize_lds(cfg.coarsen, p->opts.strict_fp);
         // measured: 4-pixel units win on small, latency-bound launches
         // (B <= 50 crops of 64x128); pixel-strided lanes from about 1M
         // output pixels on (B = 256: 16.0 vs 20.1 us)
@@ -260,6 +262,8 @@ bool fk::per_pixel(const fk_plan *p)
 
 size_t fk::lds_bytes(const fk_plan *p, const fk_launch_config &cfg)
 {
+    if (p->family == FAM_NORMALIZE && p->opts.gather == FK_GATHER_LDS)
+        return lds_gather_bytes((uint32_t)cfg.block_threads);
     if (p->chain.write.layout != FK_PACKED || per_pixel(p))
         return 0;
     const int ub = kUnitPx * p->chain.read.channels * dtype_size(p->chain.write.out_dtype);
@@ -315,7 +319,7 @@ extern "C" fk_status fk_plan_create(const fk_chain_desc *chain, int32_t max_batc
         const bool stats = chain->write.layout == FK_STATS;
         if (stats && max_batch > kStatCapacity)
             return set_error(FK_ERR_UNSUPPORTED, "stats write: max_batch above %d", kStatCapacity);
-        fk_plan_opts o = {FK_CONFIG_DEFAULT, kDefaultConfig, 0, 0, FK_TIER_AUTO, 0};
+        fk_plan_opts o = {FK_CONFIG_DEFAULT, kDefaultConfig, 0, 0, FK_TIER_AUTO, 0, FK_GATHER_DIRECT};
         if (opts)
             o = *opts;
         if (o.config_source == FK_CONFIG_MANUAL && !config_valid(o.manual))
@@ -325,6 +329,8 @@ extern "C" fk_status fk_plan_create(const fk_chain_desc *chain, int32_t max_batc
             return set_error(FK_ERR_INVALID_ARG, "unknown config source");
         if (o.tier != FK_TIER_AUTO && o.tier != FK_TIER_RUNTIME)
             return set_error(FK_ERR_INVALID_ARG, "unknown tier");
+        if (o.gather != FK_GATHER_DIRECT && o.gather != FK_GATHER_LDS)
+            return set_error(FK_ERR_INVALID_ARG, "unknown gather mode %d", o.gather);
 
         fk_plan *p = new (std::nothrow) fk_plan();
         if (!p)

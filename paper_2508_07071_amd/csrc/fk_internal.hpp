@@ -147,6 +147,10 @@ const void *kernel_runtime(int read_kind, int in_dt, int channels, int out_dt, i
 // output pixels), else 4-pixel units
 const void *kernel_normalize(int coarsen, int strict, int strided);
 constexpr uint64_t kStridedMinPixels = 1u << 20;
+// crop+resize of a u8 frame with the tapped rows staged in LDS
+const void *kernel_normalize_lds(int coarsen, int strict);
+// LDS of a staged-row gather block of T threads (dynamic shared memory)
+constexpr uint32_t lds_gather_bytes(uint32_t T) { return T * 128u < 65536u ? T * 128u : 65536u; }
 const void *kernel_muladd(int n_ops, int coarsen, int strict);
 const void *kernel_muladd_loop(int in_dt, int channels, int coarsen, int strict);
 const void *kernel_loop_px(int in_dt, int channels, int coarsen, int strict);

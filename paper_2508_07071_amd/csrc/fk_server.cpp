@@ -394,7 +394,8 @@ extern "C" fk_status fk_server_create(const fk_server_opts *opts, fk_server **ou
             e = hipStreamCreateWithFlags(&s->compute_stream, hipStreamNonBlocking);
         if (e != hipSuccess)
             return hip_error(e, "server streams");
-        fk_plan_opts po = {FK_CONFIG_DEFAULT, {256, 1}, 0, opts->strict_fp, FK_TIER_AUTO, 0};
+        fk_plan_opts po = {FK_CONFIG_DEFAULT, {256, 1}, 0, opts->strict_fp, FK_TIER_AUTO, 0,
+                           FK_GATHER_DIRECT};
         if (opts->config.block_threads != 0) {
             po.config_source = FK_CONFIG_MANUAL;
             po.manual = opts->config;

@@ -78,6 +78,23 @@ static const void *norm_ptr(bool strided)
                                       WritePlanar<DT_F32, 3>, 3, K>;
 }
 
+template <bool Strict, int K>
+static const void *norm_lds_ptr()
+{
+    return (const void *)&k_resize_lds<StaticCompute<NormalizeChain<Strict>>, DT_F32, 3, K>;
+}
+
+const void *kernel_normalize_lds(int coarsen, int strict)
+{
+    switch (coarsen) {
+    case 1: return strict ? norm_lds_ptr<true, 1>() : norm_lds_ptr<false, 1>();
+    case 2: return strict ? norm_lds_ptr<true, 2>() : norm_lds_ptr<false, 2>();
+    case 4: return strict ? norm_lds_ptr<true, 4>() : norm_lds_ptr<false, 4>();
+    case 8: return strict ? norm_lds_ptr<true, 8>() : norm_lds_ptr<false, 8>();
+    }
+    return nullptr;
+}
+
 const void *kernel_normalize(int coarsen, int strict, int strided)
 {
     switch (coarsen) {
