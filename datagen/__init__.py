@@ -34,7 +34,7 @@ import math
 
 import numpy as np
 
-DTYPES = {"u8": np.uint8, "f16": np.float16, "f32": np.float32}
+DTYPES = {"u8": np.uint8, "f16": np.float16, "f32": np.float32, "f64": np.float64}
 
 # ImageNet-style normalisation constants of the hot chain, RGB order.
 NORM_SCALE = float(np.float32(1.0) / np.float32(255.0))
@@ -53,7 +53,7 @@ def rng(seed: int) -> np.random.Generator:
 
 def frame(g: np.random.Generator, h: int, w: int, c: int = 3, dtype: str = "u8") -> np.ndarray:
     """Uniform random packed HWC frame.  u8: every byte uniform in 0..255;
-    f16/f32: uniform in [0, 255) rounded to the storage type."""
+    f16/f32/f64: uniform in [0, 255) rounded to the storage type."""
     if dtype == "u8":
         return g.integers(0, 256, size=(h, w, c), dtype=np.uint8)
     vals = g.uniform(0.0, 255.0, size=(h, w, c))

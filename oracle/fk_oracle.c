@@ -17,7 +17,7 @@
  * resized buffer).
  *
  * Next to the fp32 result it carries, per element, an fp64 shadow of the
- * same operation sequence (no intermediate rounding) and the largest
+ * same operation sequence (each op rounded to fp64, never to fp32) and the largest
  * magnitude the element took along the chain; tests use both to bound
  * rounding error.
  *
@@ -58,6 +58,16 @@
  *    minNum/maxNum over the values in row-major order (a NaN value is
  *    skipped); sum adds the values converted to fp64 in row-major order;
  *    mean = sum / (number of pixels), in fp64.
+ *  - Double-precision chains (the data-type experiment of Section VI-I
+ *    names float->double and double->double, whose kernels compute in
+ *    double): a chain whose write is fp64 (packed or planar) runs in fp64
+ *    from the read on.  The read takes u8, fp16 and fp32 elements exactly
+ *    and fp64 elements as they are; the cast is the identity; every
+ *    Mul/Add/Sub/Div is one IEEE fp64 operation with the op's fp32 constant
+ *    taken exactly as a double; the write stores the fp64 value.  Only the
+ *    plain read takes such chains, and an fp64 frame only with an fp64
+ *    write.  The fp64 value held next to each fp32 value (below) is that
+ *    chain: it already rounds every op to fp64.
  *  - Loop (the repeat op of Section VI-B, which applies one op many times
  *    without spending kernel parameters on each copy): the `span` ops just
  *    before it run `count` times in all, in order, before the chain goes
@@ -102,7 +112,8 @@ typedef struct {
     int32_t channels;
     const orc_op *ops;
     int32_t n_ops;
-    int32_t out_dtype; /* ORC_F32 or ORC_F16; ORC_F64 with ORC_STATS */
+    int32_t out_dtype; /* ORC_F32 or ORC_F16; ORC_F64 with ORC_STATS, or with a
+                          plain read for a double-precision chain */
     int32_t layout;    /* ORC_PACKED, ORC_PLANAR or ORC_STATS */
 } orc_chain;
 
@@ -179,7 +190,16 @@ uint16_t orc_float_to_half(float f)
 
 static size_t dtype_size(int32_t dt)
 {
-    return dt == ORC_U8 ? 1u : dt == ORC_F16 ? 2u : 4u;
+    return dt == ORC_U8 ? 1u : dt == ORC_F16 ? 2u : dt == ORC_F64 ? 8u : 4u;
+}
+
+/* Element (x, y, c) of a packed fp64 frame. */
+static double frame_elem64(const orc_item *it, int32_t C, int32_t x, int32_t y, int32_t c)
+{
+    const uint8_t *row = (const uint8_t *)it->src + (int64_t)y * it->pitch;
+    double v;
+    memcpy(&v, row + ((size_t)x * (size_t)C + (size_t)c) * 8, 8);
+    return v;
 }
 
 /* Element (x, y, c) of a packed HWC frame, converted to fp32 (exact). */
@@ -245,6 +265,13 @@ static int step_crop(const orc_chain *ch, const orc_item *it, img *out)
         for (int32_t i = 0; i < it->w; ++i)
             for (int32_t c = 0; c < C; ++c) {
                 size_t o = ((size_t)j * (size_t)it->w + (size_t)i) * (size_t)C + (size_t)c;
+                if (ch->in_dtype == ORC_F64) {
+                    double d = frame_elem64(it, C, it->x + i, it->y + j, c);
+                    out->v[o] = (float)d;
+                    out->d[o] = d;
+                    out->s[o] = fabsf((float)d);
+                    continue;
+                }
                 float v = frame_elem(it, ch->in_dtype, C, it->x + i, it->y + j, c);
                 out->v[o] = v;
                 out->d[o] = (double)v;
@@ -429,6 +456,8 @@ static void step_write(const orc_chain *ch, const img *m, const orc_item *it)
                                : i;
                 if (ch->out_dtype == ORC_F16)
                     ((uint16_t *)it->dst)[o] = orc_float_to_half(m->v[i]);
+                else if (ch->out_dtype == ORC_F64)
+                    ((double *)it->dst)[o] = m->d[i];  /* the fp64 chain */
                 else
                     ((float *)it->dst)[o] = m->v[i];
                 if (it->v64)
@@ -471,7 +500,7 @@ static int chain_ok(const orc_chain *ch)
     if ((ch->read_kind == ORC_READ_NV12 || ch->read_kind == ORC_READ_NV12_RESIZE) &&
         (ch->in_dtype != ORC_U8 || ch->channels != 3))
         return 0;
-    if (ch->in_dtype < ORC_U8 || ch->in_dtype > ORC_F32)
+    if (ch->in_dtype < ORC_U8 || ch->in_dtype > ORC_F64)
         return 0;
     if (ch->channels != 1 && ch->channels != 3 && ch->channels != 4)
         return 0;
@@ -479,11 +508,17 @@ static int chain_ok(const orc_chain *ch)
         if (ch->out_dtype != ORC_F64)
             return 0;
     } else {
-        if (ch->out_dtype != ORC_F32 && ch->out_dtype != ORC_F16)
+        if (ch->out_dtype != ORC_F32 && ch->out_dtype != ORC_F16 && ch->out_dtype != ORC_F64)
             return 0;
         if (ch->layout != ORC_PACKED && ch->layout != ORC_PLANAR)
             return 0;
+        /* double-precision chains: plain reads only */
+        if (ch->out_dtype == ORC_F64 && ch->read_kind != ORC_READ_PLAIN)
+            return 0;
     }
+    /* an fp64 frame feeds a double-precision chain only */
+    if (ch->in_dtype == ORC_F64 && (ch->layout == ORC_STATS || ch->out_dtype != ORC_F64))
+        return 0;
     for (int32_t i = 0; i < ch->n_ops; ++i) {
         const orc_op *op = &ch->ops[i];
         if (op->kind < ORC_SWAP || op->kind > ORC_LOOP)

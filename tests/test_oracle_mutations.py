@@ -9,6 +9,7 @@ import tempfile
 import pytest
 
 import oracle
+import test_oracle_f64_pins as dpins
 import test_oracle_pins as pins
 import test_oracle_read_pins as rpins
 import test_oracle_stats_pins as spins
@@ -42,6 +43,11 @@ MUTATIONS = [
     ("stats min takes the maximum", "mn = fminf(mn, v);", "mn = fmaxf(mn, v);"),
     ("stats read channel 0 only", "float v = m->v[p * (size_t)C + (size_t)c];", "float v = m->v[p * (size_t)C];"),
     ("stats mean over one row", "out[4 * c + 3] = sum / (double)npix;", "out[4 * c + 3] = sum / (double)m->w;"),
+    ("fp64 write stores the fp32 chain", "((double *)it->dst)[o] = m->d[i];",
+     "((double *)it->dst)[o] = (double)m->v[i];"),
+    ("fp64 frame read through fp32", "out->d[o] = d;", "out->d[o] = (double)(float)d;"),
+    ("fp64 multiply rounded to fp32", "case ORC_MUL: r = v * k; rd = d * (double)k;",
+     "case ORC_MUL: r = v * k; rd = (double)(float)(d * (double)k);"),
     ("loop skips the first op of its body",
      "for (int32_t j = i - op->span; j < i; ++j)\n                        step_arith",
      "for (int32_t j = i - op->span + 1; j < i; ++j)\n                        step_arith"),
@@ -69,6 +75,7 @@ PINS = [
     ("test_nv12_chroma_pair_serves_a_2x2_block", {}),
     ("test_division_is_true_division_not_reciprocal", {}),
     ("test_float_to_half_round_to_nearest_even_matches_numpy", {}),
+    ("test_each_op_rounds_once_to_double", {"in_dtype": "f64"}),
 ]
 
 
@@ -93,7 +100,8 @@ def load_as_oracle(path, monkeypatch):
 def caught_by_pins():
     for name, kw in PINS:
         try:
-            (getattr(pins, name, None) or getattr(spins, name, None) or getattr(rpins, name))(**kw)
+            (getattr(pins, name, None) or getattr(spins, name, None) or getattr(dpins, name, None) or
+             getattr(rpins, name))(**kw)
         except AssertionError:
             return name
     return None
