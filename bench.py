@@ -443,22 +443,25 @@ def hot_chain_rows(args):
     return rows
 
 
-def serving_row(args, rate=1000.0, n=2000):
-    """One serving point of config 4: Poisson arrivals at `rate` req/s, n
-    requests, continuous batching and per-request fused launches, 64 GB
-    arena and budget."""
+def serving_row(args, rate=1000.0, n=2000, device_rate=20000.0):
+    """One serving point of config 4 (Poisson arrivals at `rate` req/s, n
+    requests, host frames copied per request) and one beyond it (frames
+    already on the device, at `device_rate`), each with continuous batching
+    and with per-request fused launches; 64 GB arena and budget."""
     import torch
 
     import paper_2508_07071_amd as fk
     from paper_2508_07071_amd import serve
 
     arena = torch.empty(64 << 30, dtype=torch.uint8, device=torch.device("cuda:0"))
-    pool = serve.make_pool(8, seed=args.seed)
     out = {}
-    for mode, name in ((fk.FK_SERVER_BATCHED, "batched"), (fk.FK_SERVER_PER_REQUEST, "per_request")):
-        r = serve.run(rate, n, mode, pool, arena, seed=args.seed, budget_bytes=64 << 30)
-        log(r)
-        out[name] = r
+    for frames, r_hz in (("host", rate), ("device", device_rate)):
+        pool = serve.make_pool(8, seed=args.seed, device=frames == "device")
+        for mode, name in ((fk.FK_SERVER_BATCHED, "batched"), (fk.FK_SERVER_PER_REQUEST, "per_request")):
+            r = serve.run(r_hz, n, mode, pool, arena, seed=args.seed, budget_bytes=64 << 30)
+            log(r)
+            out[name if frames == "host" else f"device_frames_{name}"] = r
+        del pool
     del arena
     return out
 
@@ -849,7 +852,11 @@ def stats_workload(args):
 DATA_SIZES = [100, 1000, 10000, 100000, 282370, 1000000, 4000000, 9032740, 16654030]
 HF_PLAIN_BATCHES = [1, 10, 50, 100, 300, 600, 1191]
 IPO_SIZES = [1, 5, 10, 25, 50, 100, 250, 500]
-DTYPE_PAIRS = [("u8", "f32"), ("u8", "f16"), ("f16", "f32"), ("f16", "f16"), ("f32", "f32"), ("f32", "f16")]
+DTYPE_PAIRS = [("u8", "f32"), ("u8", "f16"), ("f16", "f32"), ("f16", "f16"), ("f32", "f32"), ("f32", "f16"),
+               ("f32", "f64"), ("f64", "f64")]
+# fp32 vs fp64 arithmetic on a whole frame: one 3840x2160 single-channel fp32
+# frame, cvt then N alternating mul/add through the run-time op list
+PRECISION_DEPTHS = [4, 64, 256]
 
 
 def sweeps_workload(args):
@@ -863,7 +870,10 @@ def sweeps_workload(args):
                  through the device run table (one output tensor per item),
                  and the autotuner's own time for its choice and for the
                  default;
-      dtypes:    the same chain at B = 50 for six input -> output types;
+      dtypes:    the same chain at B = 50 for eight input -> output types,
+                 two of them (f32 -> f64, f64 -> f64) computing in fp64;
+      precision: cvt + N mul/add (N in 4, 64, 256) over one 3840x2160 fp32
+                 frame, computed in fp32 and in fp64;
       instructions_per_op: 500 multiplications as ops of M instructions
                  over 66,355,200 fp32 values, fused vs one kernel per op."""
     import numpy as np
@@ -950,6 +960,30 @@ def sweeps_workload(args):
         fk.fk_plan_destroy(plan)
         log("dtypes", r)
         dtypes.append(r)
+    # Section VI-I's remark that double precision turns the kernel compute-
+    # bound, checked at a size where arithmetic can show: the same op list in
+    # fp32 (fp32 write) and in fp64 (fp64 write) over one 3840x2160 fp32 frame
+    precision = []
+    g = datagen.rng(args.seed + 5)
+    pframe = torch.from_numpy(datagen.frame(g, 2160, 3840, 1, dtype="f32")).to(dev)
+    for n_ops in PRECISION_DEPTHS:
+        base = datagen.muladd_chain(n_ops, datagen.rng(args.seed + n_ops), channels=1)
+        for dout in ("f32", "f64"):
+            ch = dict(base, read=dict(base["read"], dtype="f32"), write={"dtype": dout, "layout": "packed"})
+            out = torch.empty((2160, 3840, 1), dtype=fk.TORCH_DTYPE[dout], device=dev)
+            it = {"frame": 0, "x": 0, "y": 0, "w": 3840, "h": 2160}
+            arr = fk.make_items(ch, [pframe], [it], [out])
+            plan = fk.fk_plan_create(fk.chain_desc(ch), 1, fk.plan_opts(tier=fk.FK_TIER_RUNTIME))
+            best, times = fk.fk_autotune(plan, arr, 1, 5)
+            ms = min(times)
+            nbytes = 2160 * 3840 * (4 + out.element_size())
+            r = {"n_ops": n_ops, "out": dout, "autotuned": [best.block_threads, best.coarsen],
+                 "fused_ms": round(ms, 5), "gbps": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                 "gflops": round(n_ops * 2160 * 3840 / (ms * 1e-3) / 1e9, 1)}
+            fk.fk_plan_destroy(plan)
+            log("precision", r)
+            precision.append(r)
+
     # Section VI-E: 500 fp32 multiplications split into ops of M instructions
     # over 66,355,200 values (the paper's 259,200 blocks of 256 threads):
     # one fused kernel vs the unfused baseline with one kernel per op, each
@@ -980,7 +1014,8 @@ def sweeps_workload(args):
                        "seed": args.seed},
             "roofline": {**alu_roof(tf), "traffic": None,
                          "kernel": f"fused 100 mul+add pairs over {n} fp32 values", "kernel_ms": top["fused_ms"]},
-            "data_size": data_size, "hf_plain": hf_plain, "dtypes": dtypes, "instructions_per_op": per_op}
+            "data_size": data_size, "hf_plain": hf_plain, "dtypes": dtypes, "precision": precision,
+            "instructions_per_op": per_op}
 
 
 def reads_workload(args):
@@ -1067,27 +1102,48 @@ def serve_workload(args):
     modes = [fk.FK_SERVER_BATCHED, fk.FK_SERVER_PER_REQUEST, fk.FK_SERVER_UNFUSED]
     for rate in args.rates:
         for mode in modes:
-            n = max(200, int(rate * args.serve_seconds))
-            if mode == fk.FK_SERVER_UNFUSED:
-                n = min(n, 400)  # the baseline saturates: bound its backlog
+            n = max(args.serve_requests, int(rate * args.serve_seconds))
+            if mode == fk.FK_SERVER_UNFUSED and rate > 1000:
+                n = min(n, 1000)  # past its capacity the baseline's backlog only grows
             log(f"serve rate={rate} mode={mode} n={n}")
             r = serve.run(rate, n, mode, pool, arena, seed=args.seed, budget_bytes=args.budget_gb << 30)
             log(r)
             rows.append(r)
+    # beyond config 4: the same requests on frames already on the device (no
+    # PCIe copy), at rates where the fused launches, not the copies, load
+    # the GPU
+    dpool = serve.make_pool(8, seed=args.seed, device=True)
+    # heavier requests: 640x480 frames, 48-64 crops each resized to 224x224
+    heavy = {"w_range": (640, 640), "h_range": (480, 480), "min_crops": 48, "max_crops": 64,
+             "out_size": (224, 224)}
+    for kind, rates, kw in (("config-4 requests", args.device_rates, None),
+                            ("640x480 frames, 48-64 crops of 224x224", args.heavy_rates, heavy)):
+        for rate in rates:
+            for mode in modes[:2]:
+                n = max(args.serve_requests, int(rate * args.serve_seconds))
+                log(f"serve device frames, {kind}, rate={rate} mode={mode} n={n}")
+                r = serve.run(rate, n, mode, dpool, arena, seed=args.seed,
+                              budget_bytes=args.budget_gb << 30, request_kw=kw)
+                r["beyond_configs"] = True
+                r["requests_kind"] = kind
+                log(r)
+                rows.append(r)
+    del dpool
     out = {"workload": "serving: Poisson arrivals, 640x480..3840x2160 u8 frames, 1-64 crops -> "
                        "224x224 or 64x128 normalised planar fp32", "arena_gb": args.arena_gb,
-           "budget_gb": args.budget_gb, "rows": rows}
+           "budget_gb": args.budget_gb or args.arena_gb, "rows": rows}
     if not args.no_cpu_baseline:
         import datagen
         import oracle
         g = datagen.rng(args.seed)
         reqs = datagen.poisson_requests(g, 200.0, 10)
         chain = datagen.normalize_chain(224, 224)
+        big = datagen.frame(datagen.rng(args.seed + 1), 2160, 3840, 3)
         t0 = time.perf_counter()
-        for i, r in enumerate(reqs):
+        for r in reqs:
             fh, fw = r["frame_hw"]
-            frame = pool[i % len(pool)].numpy().reshape(-1)[:fh * fw * 3].reshape(fh, fw, 3)
-            oracle.run_chain(chain, [frame], [dict(c, frame=0) for c in r["crops"]], shadow=True)
+            frame = big.reshape(-1)[:fh * fw * 3].reshape(fh, fw, 3)
+            oracle.run_chain(chain, [frame], [dict(c, frame=0) for c in r["crops"]], shadow=False)
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": round(len(reqs) / dt, 2), "unit": "req/s", "cores": 1, "kind": "oracle",
                                "sample": f"10 requests of the same distribution, {dt:.2f} s single-threaded"}
@@ -1190,7 +1246,12 @@ def main():
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--rates", type=float, nargs="+", default=[200, 500, 1000, 2000])
     ap.add_argument("--serve-seconds", type=float, default=2.0)
-    ap.add_argument("--arena-gb", type=int, default=16)
+    ap.add_argument("--serve-requests", type=int, default=2000, help="at least this many requests per rate")
+    ap.add_argument("--device-rates", type=float, nargs="+", default=[2000, 10000, 20000],
+                    help="serving rates with frames already on the device")
+    ap.add_argument("--heavy-rates", type=float, nargs="+", default=[5000, 10000, 20000],
+                    help="device-frame rates for 640x480 frames with 48-64 crops of 224x224")
+    ap.add_argument("--arena-gb", type=int, default=64)
     ap.add_argument("--budget-gb", type=int, default=0, help="0 = the whole arena")
     ap.add_argument("--rotate", type=int, default=4)
     ap.add_argument("--seed", type=int, default=0)

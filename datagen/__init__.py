@@ -336,18 +336,20 @@ def random_chain_spec(g: np.random.Generator, max_ops: int = 64,
 # --- serving workload ------------------------------------------------------
 
 def poisson_requests(g: np.random.Generator, rate_hz: float, n: int,
-                     w_range=(640, 3840), h_range=(480, 2160), max_crops: int = 64) -> list:
+                     w_range=(640, 3840), h_range=(480, 2160), max_crops: int = 64,
+                     min_crops: int = 1, out_size=None) -> list:
     """Open-loop Poisson arrivals (exponential gaps) of requests, each one
-    uint8 BGR frame with uniform sides and 1..max_crops crops; each crop's
-    sides are uniform in 60..min(600, W, H) and its output is 224x224 or
-    64 wide x 128 high with probability 1/2 each."""
+    uint8 BGR frame with uniform sides and min_crops..max_crops crops; each
+    crop's sides are uniform in 60..min(600, W, H) and its output is
+    224x224 or 64 wide x 128 high with probability 1/2 each, or `out_size`
+    (width, height) for every crop when given."""
     t = 0.0
     reqs = []
     for i in range(n):
         t += float(g.exponential(1.0 / rate_hz))
         fw = int(g.integers(w_range[0], w_range[1] + 1))
         fh = int(g.integers(h_range[0], h_range[1] + 1))
-        n_crops = int(g.integers(1, max_crops + 1))
+        n_crops = int(g.integers(min_crops, max_crops + 1))
         hi = min(600, fw, fh)
         crops = []
         for _ in range(n_crops):
@@ -355,7 +357,10 @@ def poisson_requests(g: np.random.Generator, rate_hz: float, n: int,
             h = int(g.integers(60, hi + 1))
             x = int(g.integers(0, fw - w + 1))
             y = int(g.integers(0, fh - h + 1))
-            out = (224, 224) if g.uniform() < 0.5 else (64, 128)
+            if out_size is not None:
+                out = tuple(out_size)
+            else:
+                out = (224, 224) if g.uniform() < 0.5 else (64, 128)
             crops.append({"x": x, "y": y, "w": w, "h": h, "out_w": out[0], "out_h": out[1]})
         reqs.append({"id": i, "t_arrival": t, "frame_hw": (fh, fw), "crops": crops,
                      "frame_seed": int(g.integers(0, 2**31 - 1))})

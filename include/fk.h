@@ -45,7 +45,8 @@ typedef int32_t fk_status;
 #define FK_ERR_BAD_STATE (-5)    /* call not allowed in the object's current state */
 #define FK_ERR_BUDGET (-6)       /* request exceeds a memory budget */
 
-/* Element types.  FK_F64 is the output type of the stats write only. */
+/* Element types.  FK_F64 is the output type of the stats write, and the
+ * input and output type of double-precision chains (below). */
 #define FK_U8 0
 #define FK_F16 1
 #define FK_F32 2
@@ -123,7 +124,8 @@ typedef int32_t fk_status;
 
 typedef struct {
     int32_t kind;      /* FK_READ_* */
-    int32_t in_dtype;  /* FK_U8, FK_F16, FK_F32 */
+    int32_t in_dtype;  /* FK_U8, FK_F16, FK_F32; FK_F64 for a plain read whose
+                          write is FK_F64 */
     int32_t channels;  /* 1, 3 or 4, packed in the source frame */
 } fk_read_desc;
 
@@ -136,9 +138,21 @@ typedef struct {
 } fk_op_desc;
 
 typedef struct {
-    int32_t out_dtype; /* FK_F32 or FK_F16 (round to nearest even); FK_F64 with FK_STATS */
+    int32_t out_dtype; /* FK_F32 or FK_F16 (round to nearest even); FK_F64 with FK_STATS,
+                          or a double-precision chain */
     int32_t layout;    /* FK_PACKED, FK_PLANAR or FK_STATS */
 } fk_write_desc;
+
+/* Double-precision chains (the data-type experiment of Section VI-I, whose
+ * float->double and double->double kernels compute in double): a plain read
+ * with an FK_F64 packed or planar write computes in fp64 from the read on.
+ * The read takes FK_U8/FK_F16/FK_F32 elements exactly and FK_F64 elements
+ * as they are; CVT_F32 is then the identity; each MUL/ADD/SUB/DIV is one
+ * IEEE fp64 operation with the op's fp32 constant taken exactly; strict_fp
+ * = 0 fuses a MUL followed by ADD/SUB into one fp64 FMA.  Other read kinds
+ * with an FK_F64 image write, and an FK_F64 frame with any other write,
+ * are refused with FK_ERR_UNSUPPORTED.  The cost model does not cover these
+ * chains (fk_model_features returns FK_ERR_UNSUPPORTED). */
 
 /* A chain: read -> ops[0..n_ops) -> write.  `ops` is copied at plan
  * creation. */
@@ -456,14 +470,19 @@ typedef struct {
 } fk_crop;
 
 typedef struct {
-    const void *frame;   /* host, packed HWC of the chain's read dtype/channels;
-                            valid until the request completes (pinned memory
-                            gives an asynchronous copy) */
+    const void *frame;   /* packed HWC of the chain's read dtype/channels, valid
+                            until the request completes: host memory (pinned
+                            memory gives an asynchronous copy), or device memory
+                            when frame_on_device is 1 */
     int32_t width, height;
     int64_t pitch_bytes;
     const fk_crop *crops; /* copied by fk_server_submit */
     int32_t n_crops;      /* 1..max_batch_items */
     double t_arrival;     /* fk_server_clock() seconds; latency starts here */
+    int32_t frame_on_device; /* 1: `frame` is already on the device (e.g. a
+                                decoder's output): no copy, and the request's
+                                budget block holds only its outputs (and the
+                                unfused baseline's scratch) */
 } fk_request;
 
 #define FK_SERVER_BATCHED 0      /* continuous batching across requests */

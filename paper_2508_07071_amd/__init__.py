@@ -97,7 +97,7 @@ class fk_crop(C.Structure):
 class fk_request(C.Structure):
     _fields_ = [("frame", C.c_void_p), ("width", C.c_int32), ("height", C.c_int32),
                 ("pitch_bytes", C.c_int64), ("crops", C.POINTER(fk_crop)), ("n_crops", C.c_int32),
-                ("t_arrival", C.c_double)]
+                ("t_arrival", C.c_double), ("frame_on_device", C.c_int32)]
 
 
 class fk_server_opts(C.Structure):
@@ -648,8 +648,9 @@ def server_opts(desc, arena, budget_bytes=0, max_batch_items=1024, max_inflight=
 
 
 def make_request(frame, crops, t_arrival=None) -> fk_request:
-    """fk_request for a host frame tensor (H, W, C) (pinned for async copies)
-    and a list of crop dicts; keeps the crop array alive."""
+    """fk_request for a frame tensor (H, W, C) and a list of crop dicts; keeps
+    the crop array alive.  A host frame (pinned for async copies) is copied
+    by the server; a device frame is read in place (frame_on_device)."""
     arr = (fk_crop * len(crops))()
     for i, c in enumerate(crops):
         arr[i].x, arr[i].y, arr[i].w, arr[i].h = c["x"], c["y"], c["w"], c["h"]
@@ -661,6 +662,7 @@ def make_request(frame, crops, t_arrival=None) -> fk_request:
     r.crops = arr
     r.n_crops = len(crops)
     r.t_arrival = fk_server_clock() if t_arrival is None else t_arrival
+    r.frame_on_device = 1 if frame.is_cuda else 0
     r._crops = arr
     return r
 

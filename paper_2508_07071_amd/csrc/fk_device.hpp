@@ -66,6 +66,8 @@ template <>
 struct DSize<DT_F16> { static constexpr int v = 2; };
 template <>
 struct DSize<DT_F32> { static constexpr int v = 4; };
+template <>
+struct DSize<DT_F64> { static constexpr int v = 8; };
 
 // ------------------------------------------------------------ elements --
 
@@ -754,9 +756,15 @@ struct LoopMulAddCompute {
 // makes that record run `count` times in a register loop; a longer LOOP
 // jumps back over its body until the body has run `count` times (bodies
 // hold no loops, so one counter serves every loop of the list).
+// fused multiply-add in the running value's precision
+__device__ __forceinline__ float fma_v(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_v(double a, double b, double c) { return fma(a, b, c); }
+
+// The run-time op list on fp32 values, or on fp64 values for a chain with
+// an fp64 write (the op's fp32 constants taken exactly).
 struct RuntimeCompute {
-    template <int K, int C>
-    __device__ __forceinline__ static void apply(const KArgs &a, float (&v)[K][kUnitPx][C])
+    template <int K, int C, typename V>
+    __device__ __forceinline__ static void apply(const KArgs &a, V (&v)[K][kUnitPx][C])
     {
         const FK_CONST OpRec *ops = cptr(a.ops);
         int runs = 1;  // runs of the current loop body so far
@@ -778,11 +786,11 @@ struct RuntimeCompute {
             int reps = 1;
             if (o + 1 < a.n_ops && ops[o + 1].code == OPC_LOOP && ops[o + 1].span == 1)
                 reps = ops[o + 1].count;
-            float ka[C], kb[C];
+            V ka[C], kb[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                ka[c] = ops[o].a[c];
-                kb[c] = ops[o].b[c];
+                ka[c] = (V)ops[o].a[c];
+                kb[c] = (V)ops[o].b[c];
             }
             if (code == OPC_FMA) {
                 for (int r = 0; r < reps; ++r)
@@ -792,7 +800,7 @@ struct RuntimeCompute {
                         for (int i = 0; i < kUnitPx; ++i)
 #pragma unroll
                             for (int c = 0; c < C; ++c)
-                                v[j][i][c] = fmaf(v[j][i][c], ka[c], kb[c]);
+                                v[j][i][c] = fma_v(v[j][i][c], ka[c], kb[c]);
             } else if (code == OPC_MUL) {
                 for (int r = 0; r < reps; ++r)
 #pragma unroll

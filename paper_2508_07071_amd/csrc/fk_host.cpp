@@ -73,7 +73,7 @@ fk_status fk::validate_chain(const fk_chain_desc *ch)
     if ((r.kind == FK_READ_NV12 || r.kind == FK_READ_NV12_RESIZE) &&
         (r.in_dtype != FK_U8 || r.channels != 3))
         return set_error(FK_ERR_INVALID_ARG, "NV12 reads take FK_U8 frames and give 3 channels");
-    if (r.in_dtype != FK_U8 && r.in_dtype != FK_F16 && r.in_dtype != FK_F32)
+    if (r.in_dtype != FK_U8 && r.in_dtype != FK_F16 && r.in_dtype != FK_F32 && r.in_dtype != FK_F64)
         return set_error(FK_ERR_INVALID_ARG, "unknown input dtype %d", r.in_dtype);
     if (r.channels != 1 && r.channels != 3 && r.channels != 4)
         return set_error(FK_ERR_UNSUPPORTED, "channels must be 1, 3 or 4 (got %d)", r.channels);
@@ -81,11 +81,16 @@ fk_status fk::validate_chain(const fk_chain_desc *ch)
         if (ch->write.out_dtype != FK_F64)
             return set_error(FK_ERR_UNSUPPORTED, "the stats write produces FK_F64 only");
     } else {
-        if (ch->write.out_dtype != FK_F32 && ch->write.out_dtype != FK_F16)
-            return set_error(FK_ERR_UNSUPPORTED, "output dtype must be FK_F32 or FK_F16");
+        if (ch->write.out_dtype != FK_F32 && ch->write.out_dtype != FK_F16 &&
+            ch->write.out_dtype != FK_F64)
+            return set_error(FK_ERR_UNSUPPORTED, "output dtype must be FK_F32, FK_F16 or FK_F64");
         if (ch->write.layout != FK_PACKED && ch->write.layout != FK_PLANAR)
             return set_error(FK_ERR_INVALID_ARG, "unknown layout %d", ch->write.layout);
+        if (ch->write.out_dtype == FK_F64 && r.kind != FK_READ_PLAIN)
+            return set_error(FK_ERR_UNSUPPORTED, "fp64 chains take the plain read only");
     }
+    if (r.in_dtype == FK_F64 && (ch->write.layout == FK_STATS || ch->write.out_dtype != FK_F64))
+        return set_error(FK_ERR_UNSUPPORTED, "an FK_F64 frame needs an FK_F64 packed or planar write");
     if (ch->n_ops < 0 || ch->n_ops > FK_MAX_OPS)
         return set_error(FK_ERR_INVALID_ARG, "n_ops %d outside 0..%d", ch->n_ops, FK_MAX_OPS);
     if (ch->n_ops > 0 && !ch->ops)
@@ -228,6 +233,9 @@ const void *fk::plan_kernel(const fk_plan *p, const fk_launch_config &cfg, bool 
                             cfg.coarsen);
     }
     switch (p->family) {
+    case FAM_F64:
+        return kernel_f64(p->chain.read.in_dtype, p->chain.read.channels, p->chain.write.layout,
+                          cfg.coarsen);
     case FAM_NORMALIZE:
         if (p->opts.gather == FK_GATHER_LDS)
             return kernel_normalize_lds(cfg.coarsen, p->opts.strict_fp);
@@ -255,6 +263,11 @@ const void *fk::plan_kernel(const fk_plan *p, const fk_launch_config &cfg, bool 
     }
 }
 
+bool fk::runs_op_list(const fk_plan *p)
+{
+    return p->family == FAM_RUNTIME || p->family == FAM_F64;
+}
+
 bool fk::per_pixel(const fk_plan *p)
 {
     return p->family == FAM_MULADD_LOOP && p->static_n >= kLoopPxMinPairs;
@@ -262,6 +275,8 @@ bool fk::per_pixel(const fk_plan *p)
 
 size_t fk::lds_bytes(const fk_plan *p, const fk_launch_config &cfg)
 {
+    if (p->family == FAM_F64)
+        return 0;
     if (p->family == FAM_NORMALIZE && p->opts.gather == FK_GATHER_LDS)
         return lds_gather_bytes((uint32_t)cfg.block_threads);
     if (p->chain.write.layout != FK_PACKED || per_pixel(p))
@@ -352,12 +367,14 @@ extern "C" fk_status fk_plan_create(const fk_chain_desc *chain, int32_t max_batc
 
         std::vector<float> consts;
         int sn = 0;
-        p->family = o.tier == FK_TIER_AUTO && !stats ? match_static(&p->chain, consts, sn)
-                                                     : FAM_RUNTIME;
+        const bool f64 = chain->write.out_dtype == FK_F64 && !stats;
+        p->family = f64 ? FAM_F64
+                        : o.tier == FK_TIER_AUTO && !stats ? match_static(&p->chain, consts, sn)
+                                                           : FAM_RUNTIME;
         p->static_n = sn;
         normalise_chain(&p->chain, o.strict_fp != 0, p->ops, p->swap);
         p->cfg = o.config_source == FK_CONFIG_MANUAL ? o.manual : default_config(p);
-        if (p->family != FAM_RUNTIME) {
+        if (!runs_op_list(p)) {
             e = hipMalloc(&p->d_consts, std::max<size_t>(consts.size(), 1) * sizeof(float));
             if (e == hipSuccess)
                 e = hipMemcpy(p->d_consts, consts.data(), consts.size() * sizeof(float),
@@ -437,7 +454,7 @@ extern "C" fk_status fk_plan_get_tier(const fk_plan *plan, int32_t *is_static)
 {
     if (!plan || !is_static)
         return set_error(FK_ERR_INVALID_ARG, "null argument");
-    *is_static = plan->family != FAM_RUNTIME ? 1 : 0;
+    *is_static = runs_op_list(plan) ? 0 : 1;
     return FK_OK;
 }
 
@@ -541,7 +558,7 @@ KArgs fk::make_args(const fk_plan *p, void *d_table)
     a.ops = (const OpRec *)p->d_ops;
     a.consts = (const float *)p->d_consts;
     a.n_ops = (int32_t)p->ops.size();
-    a.swap = p->family == FAM_RUNTIME ? p->swap : 0;
+    a.swap = runs_op_list(p) ? p->swap : 0;
     a.strict = p->opts.strict_fp;
     a.loop_count = p->family == FAM_MULADD_LOOP ? p->static_n : 0;
     a.st_part = p->d_st_part;

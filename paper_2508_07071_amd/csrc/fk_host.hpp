@@ -52,6 +52,8 @@ fk_status validate_chain(const fk_chain_desc *ch);
 fk_status validate_items(const fk_chain_desc *ch, const fk_item *items, int32_t n);
 bool config_valid(const fk_launch_config &c);
 bool per_pixel(const fk_plan *p);
+// the plan's kernel runs the run-time op list (not a compile-time chain)
+bool runs_op_list(const fk_plan *p);
 // The plan's kernel for a launch configuration; `large`: the launch covers
 // at least kStridedMinPixels output pixels.
 const void *plan_kernel(const fk_plan *p, const fk_launch_config &cfg, bool large = true);

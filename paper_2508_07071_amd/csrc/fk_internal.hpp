@@ -19,7 +19,7 @@ enum : int32_t {
 constexpr bool rd_resizes(int rk) { return rk == RD_CROP_RESIZE || rk == RD_CROP_NEAREST || rk == RD_NV12_RESIZE; }
 // read kinds whose kernels use the fp32 scales w/ow and h/oh
 constexpr bool rd_bilinear(int rk) { return rk == RD_CROP_RESIZE || rk == RD_NV12_RESIZE; }
-enum : int32_t { DT_U8 = 0, DT_F16 = 1, DT_F32 = 2 };
+enum : int32_t { DT_U8 = 0, DT_F16 = 1, DT_F32 = 2, DT_F64 = 3 };
 enum : int32_t { LY_PACKED = 0, LY_PLANAR = 1, LY_STATS = 2 };
 // Kernel selection only: a planar write from pixel-strided lanes (bilinear
 // reads on launches of at least kStridedMinPixels output pixels).
@@ -136,6 +136,7 @@ enum : int32_t {
     FAM_NORMALIZE = 1,     // crop+resize u8x3 -> swap,cvt,mul,sub,div -> planar f32
     FAM_MULADD = 2,        // plain u8x3 -> cvt, N x (mul, add) -> packed f32
     FAM_MULADD_LOOP = 3,   // plain u8/f32 x1/x3 -> [cvt,] mul, add, loop(2, P) -> packed f32
+    FAM_F64 = 4,           // plain read -> run-time op list in fp64 -> fp64 packed/planar
 };
 
 // Kernel lookup (defined by the kernel translation units).  Returns the
@@ -152,6 +153,8 @@ const void *kernel_normalize_lds(int coarsen, int strict);
 // LDS of a staged-row gather block of T threads (dynamic shared memory)
 constexpr uint32_t lds_gather_bytes(uint32_t T) { return T * 128u < 65536u ? T * 128u : 65536u; }
 const void *kernel_muladd(int n_ops, int coarsen, int strict);
+// plain read of in_dt elements -> run-time op list in fp64 -> fp64 write
+const void *kernel_f64(int in_dt, int channels, int layout, int coarsen);
 const void *kernel_muladd_loop(int in_dt, int channels, int coarsen, int strict);
 const void *kernel_loop_px(int in_dt, int channels, int coarsen, int strict);
 // The compile-time loop chain runs per pixel (k_loop_px, a tile = T*K

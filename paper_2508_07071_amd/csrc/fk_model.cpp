@@ -401,6 +401,8 @@ extern "C" fk_status fk_model_features(const fk_plan *p, const fk_item *items, i
         fk_status s = validate_items(&p->chain, items, n);
         if (s)
             return s;
+        if (p->family == FAM_F64)
+            return set_error(FK_ERR_UNSUPPORTED, "the cost model covers fp32 and fp16 writes only");
         const fk_chain_desc &ch = p->chain;
         const int C = ch.read.channels;
         const int es_in = dtype_size(ch.read.in_dtype), es_out = dtype_size(ch.write.out_dtype);

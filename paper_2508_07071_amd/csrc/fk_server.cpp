@@ -41,7 +41,8 @@ struct Req {
     int64_t frame_bytes = 0, out_bytes = 0, scratch_bytes = 0, block_bytes = 0;
     int64_t dev_pitch = 0;         // row pitch of the frame on the device
     int64_t off = -1;              // block offset in the arena
-    hipEvent_t ready = nullptr;    // frame copy done
+    const uint8_t *dev_frame = nullptr;  // the frame on the device (arena copy or caller's)
+    hipEvent_t ready = nullptr;    // frame copy done (none for a frame already on the device)
     int launched = 0, done = 0;
     double t_admit = 0, t_launch = 0;
 };
@@ -141,7 +142,7 @@ fk_item crop_item(fk_server *s, Req *r, int i)
     const fk_crop &c = r->crops[(size_t)i];
     fk_item it{};
     uint8_t *base = (uint8_t *)s->opts.arena + r->off;
-    it.src.ptr = base + r->out_bytes;  // the frame follows the outputs
+    it.src.ptr = r->dev_frame;
     it.src.width = r->desc.width;
     it.src.height = r->desc.height;
     it.src.pitch_bytes = r->dev_pitch;
@@ -153,6 +154,26 @@ fk_item crop_item(fk_server *s, Req *r, int i)
     it.out_w = c.out_w;
     it.out_h = c.out_h;
     return it;
+}
+
+// Queue the copy of a host frame into its block (after the outputs) on the
+// copy stream, then the request's ready event.
+hipError_t copy_frame(fk_server *s, Req *r)
+{
+    uint8_t *dframe = (uint8_t *)s->opts.arena + r->off + r->out_bytes;
+    r->dev_frame = dframe;
+    const int64_t row = (int64_t)r->desc.width * s->C * s->es_in;
+    hipError_t e;
+    if (r->dev_pitch == r->desc.pitch_bytes)  // one contiguous copy, rows keep their pitch
+        e = hipMemcpyAsync(dframe, r->desc.frame, (size_t)((r->desc.height - 1) * r->dev_pitch + row),
+                           hipMemcpyHostToDevice, s->copy_stream);
+    else
+        e = hipMemcpy2DAsync(dframe, (size_t)row, r->desc.frame, (size_t)r->desc.pitch_bytes,
+                             (size_t)row, (size_t)r->desc.height, hipMemcpyHostToDevice,
+                             s->copy_stream);
+    if (e == hipSuccess && r->ready)
+        e = hipEventRecord(r->ready, s->copy_stream);
+    return e;
 }
 
 // Admit pending requests in order while memory allows; queue their copies.
@@ -168,21 +189,14 @@ bool admit(fk_server *s)
             break;
         r->off = off;
         r->t_admit = now_s();
-        r->ready = get_event(s);
-        uint8_t *dframe = (uint8_t *)s->opts.arena + off + r->out_bytes;
-        const int64_t row = (int64_t)r->desc.width * s->C * s->es_in;
-        hipError_t e;
-        if (r->dev_pitch == r->desc.pitch_bytes)  // one contiguous copy, rows keep their pitch
-            e = hipMemcpyAsync(dframe, r->desc.frame,
-                               (size_t)((r->desc.height - 1) * r->dev_pitch + row),
-                               hipMemcpyHostToDevice, s->copy_stream);
-        else
-            e = hipMemcpy2DAsync(dframe, (size_t)row, r->desc.frame, (size_t)r->desc.pitch_bytes,
-                                 (size_t)row, (size_t)r->desc.height, hipMemcpyHostToDevice,
-                                 s->copy_stream);
-        if (e == hipSuccess && r->ready)
-            e = hipEventRecord(r->ready, s->copy_stream);
-        if (e != hipSuccess || !r->ready) {
+        hipError_t e = hipSuccess;
+        if (r->desc.frame_on_device) {
+            r->dev_frame = (const uint8_t *)r->desc.frame;  // read in place
+        } else {
+            r->ready = get_event(s);
+            e = copy_frame(s, r);
+        }
+        if (e != hipSuccess || (!r->desc.frame_on_device && !r->ready)) {
             fail(s, "frame copy", e);
             return progress;
         }
@@ -211,8 +225,8 @@ bool launch_one(fk_server *s)
     for (Req *r : s->admitted) {
         if (r->launched == (int)r->crops.size())
             continue;
-        if (hipEventQuery(r->ready) != hipSuccess)
-            break;  // copies complete in order: later frames are not ready either
+        if (r->ready && hipEventQuery(r->ready) != hipSuccess)
+            break;  // first in, first out: later requests wait for this frame
         if (s->opts.mode != FK_SERVER_BATCHED && !items.empty())
             break;  // one request per launch
         const int take = std::min((int)r->crops.size() - r->launched, cap - (int)items.size());
@@ -342,10 +356,12 @@ void scheduler(fk_server *s)
         progress |= admit(s);
         while (launch_one(s))
             progress = true;
-        if (!progress && !s->inflight.empty())
-            std::this_thread::sleep_for(std::chrono::microseconds(10));
-        else if (!progress && !s->admitted.empty())
-            std::this_thread::sleep_for(std::chrono::microseconds(10));
+        // with launches in flight or frames copying, poll again at once
+        // (a short sleep lasts the kernel's timer slack, ~50 us, which would
+        // add that much to a request's latency); the thread gives up its
+        // core to other threads between polls
+        if (!progress && (!s->inflight.empty() || !s->admitted.empty()))
+            std::this_thread::yield();
     }
 }
 
@@ -443,11 +459,19 @@ extern "C" fk_status fk_server_submit(fk_server *s, const fk_request *req, uint6
             off = align256(off + (int64_t)c.out_w * c.out_h * s->C * s->es_out);
         }
         r->out_bytes = off;
-        // a pitched frame is copied in one piece (rows keep the host pitch)
-        // unless its padding would more than double the bytes moved
+        if (req->frame_on_device != 0 && req->frame_on_device != 1)
+            return set_error(FK_ERR_INVALID_ARG, "frame_on_device must be 0 or 1");
         const int64_t row = (int64_t)req->width * s->C * s->es_in;
-        r->dev_pitch = req->pitch_bytes <= 2 * row ? req->pitch_bytes : row;
-        r->frame_bytes = align256((int64_t)(req->height - 1) * r->dev_pitch + row);
+        if (req->frame_on_device) {
+            // read in place: no copy, no frame bytes in the block
+            r->dev_pitch = req->pitch_bytes;
+            r->frame_bytes = 0;
+        } else {
+            // a pitched frame is copied in one piece (rows keep the host
+            // pitch) unless its padding would more than double the bytes moved
+            r->dev_pitch = req->pitch_bytes <= 2 * row ? req->pitch_bytes : row;
+            r->frame_bytes = align256((int64_t)(req->height - 1) * r->dev_pitch + row);
+        }
         if (s->opts.mode == FK_SERVER_UNFUSED) {
             int64_t need = 0;
             for (int i = 0; i < req->n_crops; ++i) {

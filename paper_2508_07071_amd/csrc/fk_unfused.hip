@@ -181,6 +181,77 @@ __global__ __launch_bounds__(kUnfusedBlock) void k_elem4(const uint8_t *src, flo
     }
 }
 
+// ---- double-precision chains: the same ops on fp64 images ----
+
+template <int DT>
+__device__ __forceinline__ double uload_d(gsrc_t s, int64_t e)
+{
+    if constexpr (DT == DT_F64)
+        return ((const FK_GLOBAL double *)s)[e];
+    else
+        return (double)uload<DT>(s, e);  // u8, fp16, fp32: exact
+}
+
+// One elementwise op in fp64 over a packed image of n elements: TIn -> fp64
+// (code and reps as in k_elem; the constants are the ops' fp32 values).
+template <int DT>
+__global__ __launch_bounds__(kUnfusedBlock) void k_elem_d(const uint8_t *src, double *dst, int64_t n,
+                                                         int C, int code, double k0, double k1,
+                                                         double k2, double k3, int reps)
+{
+    gsrc_t s = (gsrc_t)src;
+    FK_GLOBAL double *d = (FK_GLOBAL double *)dst;
+    const double kk[4] = {k0, k1, k2, k3};
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        double r = uload_d<DT>(s, e);
+        const double k = kk[(int)(e % C)];
+        if (code == OPC_MUL) {
+            for (int q = 0; q < reps; ++q)
+                r = r * k;
+        } else if (code == OPC_ADD) {
+            for (int q = 0; q < reps; ++q)
+                r = r + k;
+        } else if (code == OPC_DIV) {
+            for (int q = 0; q < reps; ++q)
+                r = r / k;
+        }
+        d[e] = r;
+    }
+}
+
+// BGR <-> RGB in fp64: TIn -> fp64.
+template <int DT>
+__global__ __launch_bounds__(kUnfusedBlock) void k_swap_d(const uint8_t *src, double *dst,
+                                                         int64_t npix, int C)
+{
+    gsrc_t s = (gsrc_t)src;
+    FK_GLOBAL double *d = (FK_GLOBAL double *)dst;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npix;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        for (int c = 0; c < C; ++c) {
+            const int sc = (C >= 3 && c != 1 && c != 3) ? 2 - c : c;
+            d[p * C + c] = uload_d<DT>(s, p * C + sc);
+        }
+    }
+}
+
+// Final fp64 write: packed TIn image -> fp64, packed or planar.
+template <int DT>
+__global__ __launch_bounds__(kUnfusedBlock) void k_write_d(const uint8_t *src, double *dst,
+                                                          int64_t npix, int C, int planar)
+{
+    gsrc_t s = (gsrc_t)src;
+    FK_GLOBAL double *d = (FK_GLOBAL double *)dst;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npix;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        for (int c = 0; c < C; ++c) {
+            const int64_t o = planar ? (int64_t)c * npix + p : p * C + c;
+            d[o] = uload_d<DT>(s, p * C + c);
+        }
+    }
+}
+
 // BGR <-> RGB over a packed image of npix pixels: TIn -> fp32.
 template <int DT>
 __global__ __launch_bounds__(kUnfusedBlock) void k_swap(const uint8_t *src, float *dst,
@@ -337,7 +408,8 @@ static ScratchPlan scratch_for(const fk_plan *p, const fk_item &it)
     size_t npix = (size_t)it.w * it.h;
     if (rd_resizes(p->chain.read.kind))
         npix = std::max(npix, (size_t)it.out_w * it.out_h);
-    s.buf = npix * C * sizeof(float);
+    // intermediates hold the running value: fp64 for a double-precision chain
+    s.buf = npix * C * (p->family == FAM_F64 ? sizeof(double) : sizeof(float));
     if (p->chain.write.layout == FK_STATS)
         s.part = (size_t)kRedBlocks * 4 * sizeof(double);
     return s;
@@ -392,9 +464,148 @@ static void write_out(int dt, const void *src, void *dst, int64_t npix, int C, i
         k_write<DT_F32, DTO><<<g, kUnfusedBlock, 0, st>>>((const uint8_t *)src, (uint8_t *)dst, npix, C, planar);
 }
 
+// One kernel per op as the chain executes: a loop's body once per run; with
+// unfused_loop_kernel, a loop over one op is that op's kernel applying it
+// loop_count times.  seq[s] = op index, reps[s] = applications in its kernel.
+static void op_sequence(const fk_plan *p, std::vector<int> &seq, std::vector<int> &reps)
+{
+    const int C = p->chain.read.channels;
+    for (int i = 0; i < p->chain.n_ops; ++i) {
+        const fk_op_desc &d = p->chain.ops[i];
+        if (d.kind == FK_OP_LOOP) {
+            if (p->opts.unfused_loop_kernel && d.loop_span == 1) {
+                reps.back() = d.loop_count;  // the body: the entry just pushed
+                continue;
+            }
+            for (int r = 1; r < d.loop_count; ++r)
+                for (int j = i - d.loop_span; j < i; ++j) {
+                    seq.push_back(j);
+                    reps.push_back(1);
+                }
+        } else if (d.kind != FK_OP_SWAP_RB || C >= 3) {  // a 1-channel swap is no kernel
+            seq.push_back(i);
+            reps.push_back(1);
+        }
+    }
+}
+
+// Kernel code and per-channel constants of an arithmetic op (SUB as ADD of
+// the negated constant: exact).
+static int op_code(const fk_op_desc &d, int C, float (&k)[4])
+{
+    for (int c = 0; c < 4; ++c)
+        k[c] = d.n_consts == 1 ? d.consts[0] : (c < C ? d.consts[c] : 0.0f);
+    if (d.kind == FK_OP_MUL)
+        return OPC_MUL;
+    if (d.kind == FK_OP_ADD)
+        return OPC_ADD;
+    if (d.kind == FK_OP_SUB) {
+        for (int c = 0; c < 4; ++c)
+            k[c] = -k[c];
+        return OPC_ADD;
+    }
+    if (d.kind == FK_OP_DIV)
+        return OPC_DIV;
+    return -1;
+}
+
+static void elem_d(int dt, const void *src, double *dst, int64_t n, int C, int code,
+                   const float (&k)[4], int reps, hipStream_t st)
+{
+    const unsigned g = grid_for(n);
+    const uint8_t *s = (const uint8_t *)src;
+    const double k0 = k[0], k1 = k[1], k2 = k[2], k3 = k[3];
+    switch (dt) {
+    case DT_U8: k_elem_d<DT_U8><<<g, kUnfusedBlock, 0, st>>>(s, dst, n, C, code, k0, k1, k2, k3, reps); break;
+    case DT_F16: k_elem_d<DT_F16><<<g, kUnfusedBlock, 0, st>>>(s, dst, n, C, code, k0, k1, k2, k3, reps); break;
+    case DT_F32: k_elem_d<DT_F32><<<g, kUnfusedBlock, 0, st>>>(s, dst, n, C, code, k0, k1, k2, k3, reps); break;
+    default: k_elem_d<DT_F64><<<g, kUnfusedBlock, 0, st>>>(s, dst, n, C, code, k0, k1, k2, k3, reps); break;
+    }
+}
+
+static void swap_d(int dt, const void *src, double *dst, int64_t npix, int C, hipStream_t st)
+{
+    const unsigned g = grid_for(npix);
+    const uint8_t *s = (const uint8_t *)src;
+    switch (dt) {
+    case DT_U8: k_swap_d<DT_U8><<<g, kUnfusedBlock, 0, st>>>(s, dst, npix, C); break;
+    case DT_F16: k_swap_d<DT_F16><<<g, kUnfusedBlock, 0, st>>>(s, dst, npix, C); break;
+    case DT_F32: k_swap_d<DT_F32><<<g, kUnfusedBlock, 0, st>>>(s, dst, npix, C); break;
+    default: k_swap_d<DT_F64><<<g, kUnfusedBlock, 0, st>>>(s, dst, npix, C); break;
+    }
+}
+
+static void write_d(int dt, const void *src, double *dst, int64_t npix, int C, int planar,
+                    hipStream_t st)
+{
+    const unsigned g = grid_for(npix);
+    const uint8_t *s = (const uint8_t *)src;
+    switch (dt) {
+    case DT_U8: k_write_d<DT_U8><<<g, kUnfusedBlock, 0, st>>>(s, dst, npix, C, planar); break;
+    case DT_F16: k_write_d<DT_F16><<<g, kUnfusedBlock, 0, st>>>(s, dst, npix, C, planar); break;
+    case DT_F32: k_write_d<DT_F32><<<g, kUnfusedBlock, 0, st>>>(s, dst, npix, C, planar); break;
+    default: k_write_d<DT_F64><<<g, kUnfusedBlock, 0, st>>>(s, dst, npix, C, planar); break;
+    }
+}
+
+// A double-precision chain (plain read, fp64 write): the ROI in place when
+// its rows are contiguous (else one 2-D copy), one kernel per op writing an
+// fp64 image, and the fp64 write (the last op writes a packed output
+// directly).
+static fk_status run_item_unfused_f64(const fk_plan *p, const fk_item &it, uint8_t *ws,
+                                      hipStream_t st)
+{
+    const int C = p->chain.read.channels;
+    const int din = p->chain.read.in_dtype;
+    const int es = dtype_size(din);
+    const ScratchPlan sp = scratch_for(p, it);
+    double *buf[2] = {(double *)(ws + align_up(sp.crop)),
+                      (double *)(ws + align_up(sp.crop) + align_up(sp.buf))};
+    const uint8_t *roi = (const uint8_t *)it.src.ptr + (int64_t)it.y * it.src.pitch_bytes +
+                         (int64_t)it.x * C * es;
+    const size_t row_bytes = (size_t)it.w * C * es;
+    const void *cur = roi;
+    if ((size_t)it.src.pitch_bytes != row_bytes && it.h > 1) {
+        hipError_t e = hipMemcpy2DAsync(ws, row_bytes, roi, it.src.pitch_bytes, row_bytes, it.h,
+                                        hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess)
+            return hip_error(e, "crop copy");
+        cur = ws;
+    }
+    int cur_dt = din;
+    int nb = 0;
+    const int64_t npix = (int64_t)it.w * it.h;
+    const bool direct = p->chain.write.layout == FK_PACKED;
+    std::vector<int> seq, reps;
+    op_sequence(p, seq, reps);
+    for (size_t s = 0; s < seq.size(); ++s) {
+        const fk_op_desc &d = p->chain.ops[seq[s]];
+        double *o = (direct && s + 1 == seq.size()) ? (double *)it.dst : buf[nb];
+        if (o != (double *)it.dst)
+            nb ^= 1;
+        if (d.kind == FK_OP_SWAP_RB) {
+            swap_d(cur_dt, cur, o, npix, C, st);
+        } else {
+            float k[4];
+            const int code = op_code(d, C, k);
+            elem_d(cur_dt, cur, o, npix * C, C, code, k, reps[s], st);
+        }
+        cur = o;
+        cur_dt = DT_F64;
+    }
+    if (!(direct && !seq.empty()))
+        write_d(cur_dt, cur, (double *)it.dst, npix, C, p->chain.write.layout == FK_PLANAR, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_error(e, "unfused launch");
+    return FK_OK;
+}
+
 static fk_status run_item_unfused(const fk_plan *p, const fk_item &it, uint8_t *ws,
                                   hipStream_t st)
 {
+    if (p->family == FAM_F64)
+        return run_item_unfused_f64(p, it, ws, st);
     const int C = p->chain.read.channels;
     const int din = p->chain.read.in_dtype;
     const int es = dtype_size(din);
@@ -462,27 +673,8 @@ static fk_status run_item_unfused(const fk_plan *p, const fk_item &it, uint8_t *
         cur_dt = DT_F32;
     }
     const bool direct = p->chain.write.layout == FK_PACKED && p->chain.write.out_dtype == FK_F32;
-    // one kernel per op as the chain executes: a loop's body once per run;
-    // with unfused_loop_kernel, a loop over one op is that op's kernel
-    // applying it loop_count times
     std::vector<int> seq, reps;
-    for (int i = 0; i < p->chain.n_ops; ++i) {
-        const fk_op_desc &d = p->chain.ops[i];
-        if (d.kind == FK_OP_LOOP) {
-            if (p->opts.unfused_loop_kernel && d.loop_span == 1) {
-                reps.back() = d.loop_count;  // the body: the entry just pushed
-                continue;
-            }
-            for (int r = 1; r < d.loop_count; ++r)
-                for (int j = i - d.loop_span; j < i; ++j) {
-                    seq.push_back(j);
-                    reps.push_back(1);
-                }
-        } else if (d.kind != FK_OP_SWAP_RB || C >= 3) {  // a 1-channel swap is no kernel
-            seq.push_back(i);
-            reps.push_back(1);
-        }
-    }
+    op_sequence(p, seq, reps);
     for (size_t s = 0; s < seq.size(); ++s) {
         const fk_op_desc &d = p->chain.ops[seq[s]];
         const bool last = s + 1 == seq.size();
@@ -493,20 +685,7 @@ static fk_status run_item_unfused(const fk_plan *p, const fk_item &it, uint8_t *
             swap_any(cur_dt, cur, o, npix, C, st);
         } else {
             float k[4];
-            for (int c = 0; c < 4; ++c)
-                k[c] = d.n_consts == 1 ? d.consts[0] : (c < C ? d.consts[c] : 0.0f);
-            int code = -1;
-            if (d.kind == FK_OP_MUL) {
-                code = OPC_MUL;
-            } else if (d.kind == FK_OP_ADD) {
-                code = OPC_ADD;
-            } else if (d.kind == FK_OP_SUB) {
-                code = OPC_ADD;
-                for (int c = 0; c < 4; ++c)
-                    k[c] = -k[c];
-            } else if (d.kind == FK_OP_DIV) {
-                code = OPC_DIV;
-            }
+            const int code = op_code(d, C, k);
             elem_any(cur_dt, cur, o, npix * C, C, code, k, reps[s], st);
         }
         cur = o;

@@ -5,33 +5,41 @@ Poisson arrivals at a fixed rate; each request is one uint8 BGR frame
 224x224 or 64x128 (width x height) and normalised to planar fp32.  Frames
 come from a pool of pinned host buffers: a request's W x H frame is a dense
 image over the first W*H*3 bytes of a pool frame.  Latency = completion time -
-scheduled arrival time on the server's monotonic clock.
+scheduled arrival time on the server's monotonic clock.  With a device pool
+the frames are already on the device (as a GPU decoder would leave them) and
+the server reads them in place.
 """
 from __future__ import annotations
 
+import gc
 import time
 
 import numpy as np
 
 
-def make_pool(n_frames=8, seed=0, max_hw=(2160, 3840)):
+def make_pool(n_frames=8, seed=0, max_hw=(2160, 3840), device=False):
+    """Frames of random bytes: pinned host tensors, or device tensors."""
     import torch
     g = np.random.default_rng(seed)
     pool = []
     for _ in range(n_frames):
         f = torch.from_numpy(g.integers(0, 256, size=(max_hw[0], max_hw[1], 3), dtype=np.uint8))
-        pool.append(f.pin_memory())
+        pool.append(f.to("cuda:0") if device else f.pin_memory())
     return pool
 
 
 def run(rate_hz, n_requests, mode, pool, arena, seed=0, warmup_frac=0.1, max_batch_items=2048,
-        max_inflight=3, budget_bytes=0, deadline_s=60.0, config=(0, 0)):
-    """Serve n_requests arrivals at rate_hz; returns a stats dict."""
+        max_inflight=3, budget_bytes=0, deadline_s=60.0, config=(0, 0), request_kw=None):
+    """Serve n_requests arrivals at rate_hz; returns a stats dict.  Frames
+    come from `pool` (host frames are copied, device frames read in place);
+    `request_kw` goes to datagen.poisson_requests (frame sizes, crop counts,
+    output size)."""
     import datagen
     import paper_2508_07071_amd as fk
 
     g = datagen.rng(seed)
-    reqs = datagen.poisson_requests(g, rate_hz, n_requests)
+    reqs = datagen.poisson_requests(g, rate_hz, n_requests, **(request_kw or {}))
+    on_device = pool[0].is_cuda
     chain = datagen.normalize_chain(224, 224)
     desc = fk.chain_desc(chain)
     srv = fk.fk_server_create(fk.server_opts(desc, arena, budget_bytes=budget_bytes,
@@ -46,9 +54,15 @@ def run(rate_hz, n_requests, mode, pool, arena, seed=0, warmup_frac=0.1, max_bat
             # a dense fh x fw x 3 image over the pool frame's (random) bytes
             frame = pool[i % len(pool)].view(-1)[:fh * fw * 3].view(fh, fw, 3)
             built.append(fk.make_request(frame, r["crops"], 0.0))
-            in_bytes += fh * fw * 3
+            in_bytes += 0 if on_device else fh * fw * 3
             crops += len(r["crops"])
             out_bytes += sum(c["out_w"] * c["out_h"] * 12 for c in r["crops"])
+        # the load generator must not pause: a collection over tens of
+        # thousands of request objects would hold back later arrivals (and
+        # count as their latency, which starts at the scheduled arrival)
+        gc.collect()
+        gc.freeze()
+        gc.disable()
         t0 = fk.fk_server_clock() + 0.05
         tickets = {}
 
@@ -74,6 +88,8 @@ def run(rate_hz, n_requests, mode, pool, arena, seed=0, warmup_frac=0.1, max_bat
             time.sleep(2e-4)
         st = fk.fk_server_stats_get(srv)
     finally:
+        gc.enable()
+        gc.unfreeze()
         fk.fk_server_destroy(srv)
     if len(done) < len(reqs):
         return {"rate_hz": rate_hz, "mode": mode, "error": f"only {len(done)}/{len(reqs)} completed"}
@@ -84,6 +100,7 @@ def run(rate_hz, n_requests, mode, pool, arena, seed=0, warmup_frac=0.1, max_bat
     span = rows[:, 3].max() - rows[:, 0].min()
     return {
         "rate_hz": rate_hz, "mode": ["batched", "per_request", "unfused"][mode],
+        "frames": "device" if on_device else "host",
         "requests": len(reqs), "failed": bad, "crops": crops,
         "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
         "mean_ms": round(float(lat.mean()), 3),

@@ -68,14 +68,13 @@ def assert_bitexact(g, r, what=""):
     g = np.asarray(g)
     r = np.asarray(r)
     assert g.shape == r.shape, (what, g.shape, r.shape)
-    if g.dtype == np.float16:
-        gv, rv = g.view(np.uint16), r.view(np.uint16)
-    else:
-        gv, rv = g.view(np.uint32), r.view(np.uint32)
+    assert g.dtype == r.dtype, (what, g.dtype, r.dtype)
+    bits = {np.dtype(np.float16): np.uint16, np.dtype(np.float32): np.uint32, np.dtype(np.float64): np.uint64}
+    gv, rv = g.view(bits[g.dtype]), r.view(bits[r.dtype])
     bad = np.flatnonzero(gv.ravel() != rv.ravel())
     # NaN == NaN regardless of payload
     if bad.size:
-        both_nan = np.isnan(g.ravel()[bad].astype(np.float32)) & np.isnan(r.ravel()[bad].astype(np.float32))
+        both_nan = np.isnan(g.ravel()[bad]) & np.isnan(r.ravel()[bad])
         bad = bad[~both_nan]
     assert bad.size == 0, f"{what}: {bad.size} elements differ, first at {bad[:5]}: " \
                           f"{g.ravel()[bad[:5]]} vs {r.ravel()[bad[:5]]}"

@@ -205,3 +205,33 @@ def test_release_only_after_completion():
         assert fk.fk_server_stats_get(srv).bytes_in_use == 0
     finally:
         fk.fk_server_destroy(srv)
+
+
+def test_device_frames_match_host_frames_and_merge_into_launches():
+    """Requests whose frames are already on the device (no copy) give the
+    bits of the same frames sent from the host and of the oracle; their
+    budget blocks hold only outputs, and a burst of them submitted while
+    the GPU is busy is merged into launches carrying several requests."""
+    say("device-resident frames")
+    reqs = requests(5, 16, min_crops=8, max_crops=24, hw=((480, 640), (720, 1280)))
+    host_out, st_host = serve(reqs)
+    dev_reqs = [(f.to("cuda:0"), c) for f, c in reqs]
+    torch.cuda.synchronize()
+    dev_out, st_dev = serve(dev_reqs, max_inflight=1)
+    for i in range(len(reqs)):
+        for j, (a, b) in enumerate(zip(host_out[i], dev_out[i])):
+            assert_bitexact(b, a, f"request {i} crop {j}")
+    assert st_dev.peak_bytes < st_host.peak_bytes
+    assert st_dev.launches < len(reqs), (st_dev.launches, len(reqs))
+    # a mix of host and device frames
+    mix = [r if i % 2 else dev_reqs[i] for i, r in enumerate(reqs)]
+    mix_out, _ = serve(mix)
+    for i in range(len(reqs)):
+        for j, (a, b) in enumerate(zip(host_out[i], mix_out[i])):
+            assert_bitexact(b, a, f"mixed request {i} crop {j}")
+    # the oracle, for two requests
+    for i in (0, 9):
+        frame, crops = reqs[i]
+        refs = oracle.run_chain(CHAIN, [frame.numpy()], [dict(c, frame=0) for c in crops])
+        for j, r in enumerate(refs):
+            assert_bitexact(dev_out[i][j], r["out"], f"oracle request {i} crop {j}")

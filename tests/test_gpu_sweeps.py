@@ -1,7 +1,8 @@
 """Parity with the oracle at the shapes of the paper's parameter sweeps:
 1-D fp32 arrays with 100 Mul+Add pairs through the loop op (data size),
 batches of 60x120 single-channel images through Read -> Cast -> Mul -> Sub
--> Div -> Write for six input/output types (data type) and up to 1191
+-> Div -> Write for eight input/output types, two of them computing in
+double (data type) and up to 1191
 images (plain-read horizontal fusion)."""
 import numpy as np
 import pytest
@@ -18,7 +19,7 @@ def say(*a):
     print("[case]", *a, flush=True)
 
 
-def both_modes(cfg, what, sample=None, static=None):
+def both_modes(cfg, what, sample=None, static=None, rel=1e-5):
     items = cfg["items"]
     idx = list(range(len(items))) if sample is None else sample
     refs = oracle.run_chain(cfg["chain"], cfg["frames"], [items[i] for i in idx])
@@ -32,7 +33,7 @@ def both_modes(cfg, what, sample=None, static=None):
             if strict:
                 assert_bitexact(outs[i], r["out"], f"{what} strict item {i}")
             else:
-                assert_close(outs[i], r, what=f"{what} item {i}")
+                assert_close(outs[i], r, rel=rel, what=f"{what} item {i}")
 
 
 @pytest.mark.parametrize("n", [100, 4096, 282370])
@@ -42,10 +43,11 @@ def test_data_size_fp32_loop_chain(n):
 
 
 @pytest.mark.parametrize("din,dout", [("u8", "f32"), ("u8", "f16"), ("f16", "f32"), ("f16", "f16"),
-                                      ("f32", "f32"), ("f32", "f16")])
+                                      ("f32", "f32"), ("f32", "f16"), ("f32", "f64"), ("f64", "f64")])
 def test_cast_chain_data_types_batch50(din, dout):
     say("data types", din, "->", dout)
-    both_modes(datagen.cast_chain_batch(50, din, dout, seed=3), f"{din}->{dout}")
+    both_modes(datagen.cast_chain_batch(50, din, dout, seed=3), f"{din}->{dout}",
+               rel=1e-13 if dout == "f64" else 1e-5)
 
 
 def test_plain_batch_1191_images_sampled():

@@ -95,13 +95,18 @@ def test_stats_skip_nan_in_min_max_and_propagate_into_sum():
     assert out[0, 0] == -2.0 and out[0, 1] == np.inf and out[0, 2] == np.inf
 
 
-def test_stats_write_requires_f64_and_f64_requires_stats():
+def test_stats_write_requires_f64_and_f64_images_need_a_plain_read():
+    """The stats write produces fp64 only; an fp64 image write is a
+    double-precision chain, which only the plain read takes."""
     fr = np.zeros((4, 4, 3), np.uint8)
-    it = [{"frame": 0, "x": 0, "y": 0, "w": 4, "h": 4}]
+    it = [{"frame": 0, "x": 0, "y": 0, "w": 4, "h": 4, "out_w": 2, "out_h": 2}]
     assert oracle.validate(stats_chain(), [fr], it) == 0
     bad = stats_chain()
     bad["write"]["dtype"] = "f32"
     assert oracle.validate(bad, [fr], it) < 0
-    bad = image_chain(stats_chain())
+    dbl = image_chain(stats_chain())
+    dbl["write"]["dtype"] = "f64"
+    assert oracle.validate(dbl, [fr], it) == 0
+    bad = image_chain(stats_chain(kind="crop_resize", ow=2, oh=2))
     bad["write"]["dtype"] = "f64"
     assert oracle.validate(bad, [fr], it) < 0
