@@ -412,6 +412,22 @@ def hot_chain_rows(args):
             r["graph_call_us"] = round(1e3 * timeit(lambda: fk.fk_run(hg, arr, B, stream), reps,
                                                     warm_s=2e-3), 2)
             fk.fk_plan_destroy(hg)
+            # the caller's own capture of 10 runs (kernel-argument batches
+            # are captured as their launches): per-run time of the replays
+            hc = fk.fk_plan_create(desc, B, fk.plan_opts(gather=gather))
+            fk.fk_plan_set_config(hc, best)
+            cs = torch.cuda.Stream()
+            graph = torch.cuda.CUDAGraph()
+            try:
+                with torch.cuda.graph(graph, stream=cs):
+                    for _ in range(10):
+                        fk.fk_run(hc, arr, B, fk.stream_handle(cs))
+                r["graph_10_runs_us_per_run"] = round(
+                    1e3 * timeit(graph.replay, max(2, reps // 10), warm_s=2e-3) / 10, 2)
+            except fk.FKError:
+                r["graph_10_runs_us_per_run"] = None  # a table batch: not capturable
+            del graph
+            fk.fk_plan_destroy(hc)
         log(r)
         return r
 

@@ -279,7 +279,16 @@ fk_status fk_plan_get_tier(const fk_plan *plan, int32_t *is_static);
  * more than 312 items (not a stats write) goes out as consecutive launches
  * of up to 312 items.  `items` is copied before the call returns; a
  * table run first waits for the run that used the same table slot four
- * table runs earlier. */
+ * table runs earlier.
+ *
+ * Under the caller's stream capture (hipStreamBeginCapture on `stream`,
+ * e.g. to replay several runs as one graph: a graph launch costs about as
+ * much host time as several direct launches, so one graph per run does not
+ * pay), a run whose items travel in the kernel arguments is captured as
+ * its kernel launches, parameters included; any other run returns
+ * FK_ERR_UNSUPPORTED before touching the stream (its table is staged in
+ * host memory that later runs rewrite), and so does a plan with use_graph
+ * or a timed run. */
 fk_status fk_run(fk_plan *plan, const fk_item *items, int32_t n_items, void *stream);
 
 /* fk_run with the launch's device time: `start_event` and `stop_event`

@@ -695,9 +695,47 @@ static hipError_t upload_table(const fk_plan *p, const fk_plan::Slot &sl, int32_
                            stream);
 }
 
+// The batch travels in kernel arguments only (no run table): up to
+// kInlineItems items, or items of one frame, one output size and a constant
+// output stride (consecutive launches of kCompactItems beyond that, except
+// for a stats write).
+static bool argument_form(const fk_plan *p, const fk_item *items, int32_t n)
+{
+    if (n <= kInlineItems)
+        return true;
+    return compact_batch(p, items, n) && (n <= kCompactItems || p->chain.write.layout != FK_STATS);
+}
+
+// Under the caller's stream capture only argument-form batches may run: a
+// table batch's parameters are staged in host memory that later runs
+// rewrite, and a plan's own graph replay is a graph launch.
+static fk_status check_capture(const fk_plan *p, const fk_item *items, int32_t n, bool graph,
+                               bool timed, hipStream_t stream)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(stream, &cs);
+    if (e != hipSuccess)
+        return hip_error(e, "hipStreamIsCapturing");
+    if (cs == hipStreamCaptureStatusNone)
+        return FK_OK;
+    if (graph || timed)
+        return set_error(FK_ERR_UNSUPPORTED,
+                         "under stream capture: no plan graph replay and no timed run");
+    if (!argument_form(p, items, n))
+        return set_error(FK_ERR_UNSUPPORTED,
+                         "under stream capture only batches carried in kernel arguments can run "
+                         "(up to %d items, or items of one frame, one output size and a constant "
+                         "output stride)",
+                         kInlineItems);
+    return FK_OK;
+}
+
 fk_status fk::run_fused(fk_plan *p, const fk_item *items, int32_t n, const fk_launch_config &cfg,
                         bool graph, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1)
 {
+    fk_status cs = check_capture(p, items, n, graph, ev0 || ev1, stream);
+    if (cs)
+        return cs;
     if (!graph && n <= kInlineItems) {
         // small batch: the parameters travel in the kernel arguments
         KArgs a = make_args(p, nullptr);

@@ -91,19 +91,24 @@ def serve(reqs, mode=fk.FK_SERVER_BATCHED, budget=0, strict=True, arena_mb=512, 
 
 def test_alone_and_in_the_mix_give_the_same_bits():
     say("alone vs mix")
-    # small frames (fast copies) with many 224x224 crops (slow launches), one
-    # launch in flight: frames land while the GPU is busy, so later launches
-    # carry crops of several requests
+    # 640x480 frames with 48-64 crops of 224x224 each.  Frames already on
+    # the device, submitted in a burst with one launch in flight: the
+    # requests that arrive while it runs are merged into the next launches.
     reqs = requests(1, 24, min_crops=48, max_crops=64, hw=((480, 640), (480, 640)), big=True)
+    dev = [(f.to("cuda:0"), c) for f, c in reqs]
+    torch.cuda.synchronize()
     target = reqs[7]
     alone, _ = serve([target], max_inflight=1)
-    mixed, st = serve(reqs, max_inflight=1)
+    mixed, st = serve(dev, max_inflight=1)
     assert st.launches < len(reqs), st.launches  # launches shared between requests
     for a, b in zip(alone[0], mixed[7]):
         assert_bitexact(b, a, "request 7 in the mix")
-    mixed3, _ = serve(reqs, max_inflight=3, stagger=0.0005)
-    for a, b in zip(alone[0], mixed3[7]):
-        assert_bitexact(b, a, "request 7 in a staggered mix")
+    # host frames: each copy (~40 us) outlasts a launch, so requests mostly
+    # launch alone; still the same bits, staggered or not
+    for kw in ({"max_inflight": 1}, {"max_inflight": 3, "stagger": 0.0005}):
+        mixed_h, _ = serve(reqs, **kw)
+        for a, b in zip(alone[0], mixed_h[7]):
+            assert_bitexact(b, a, f"request 7 among host frames {kw}")
 
 
 def test_server_outputs_match_oracle():
