@@ -1,48 +1,14 @@
-// fk_rt_plain_f16.hip -- instantiations of the fused transform kernel: run-time op list, plain read of f16 frames.
-#include "fk_device.hpp"
+// fk_rt_plain_f16.hip -- run-time tier kernels: plain read of f16 frames.
+#include "fk_rt_dispatch.hpp"
 
 namespace fk {
 
-template <int RK, int DI, int C>
-using ReadOf = typename std::conditional<RK == RD_PLAIN, ReadPlain<DI, C>, ReadCropResize<DI, C>>::type;
-template <int DO, int C, int LY>
-using WriteOf = typename std::conditional<LY == LY_PLANAR, WritePlanar<DO, C>, WritePacked<DO, C>>::type;
-
-template <int RK, int DI, int C, int DO, int LY>
-static const void *pick_k(int k)
-{
-    switch (k) {
-    case 1: return (const void *)&k_transform<ReadOf<RK, DI, C>, RuntimeCompute, WriteOf<DO, C, LY>, C, 1>;
-    case 2: return (const void *)&k_transform<ReadOf<RK, DI, C>, RuntimeCompute, WriteOf<DO, C, LY>, C, 2>;
-    case 4: return (const void *)&k_transform<ReadOf<RK, DI, C>, RuntimeCompute, WriteOf<DO, C, LY>, C, 4>;
-    case 8: return (const void *)&k_transform<ReadOf<RK, DI, C>, RuntimeCompute, WriteOf<DO, C, LY>, C, 8>;
-    }
-    return nullptr;
-}
-template <int RK, int DI, int C, int DO>
-static const void *pick_ly(int ly, int k)
-{
-    return ly == LY_PLANAR ? pick_k<RK, DI, C, DO, LY_PLANAR>(k) : pick_k<RK, DI, C, DO, LY_PACKED>(k);
-}
-template <int RK, int DI, int C>
-static const void *pick_do(int dout, int ly, int k)
-{
-    return dout == DT_F16 ? pick_ly<RK, DI, C, DT_F16>(ly, k) : pick_ly<RK, DI, C, DT_F32>(ly, k);
-}
-template <int RK, int DI>
-static const void *pick_c(int c, int dout, int ly, int k)
-{
-    switch (c) {
-    case 1: return pick_do<RK, DI, 1>(dout, ly, k);
-    case 3: return pick_do<RK, DI, 3>(dout, ly, k);
-    case 4: return pick_do<RK, DI, 4>(dout, ly, k);
-    }
-    return nullptr;
-}
+template <int C>
+using ReadPlainF16 = ReadPlain<DT_F16, C>;
 
 const void *kernel_runtime_plain_f16(int channels, int out_dt, int layout, int coarsen)
 {
-    return pick_c<RD_PLAIN, DT_F16>(channels, out_dt, layout, coarsen);
+    return RuntimeTable<ReadPlainF16, false, kChannels134>::get(channels, out_dt, layout, coarsen);
 }
 
 }  // namespace fk
