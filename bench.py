@@ -1180,6 +1180,11 @@ def costmodel_workload(args):
     data = cm.load_shards(shards)
     model, rep = cm.fit(data, epochs=args.epochs)
     out = {"workload": "cost model: 20,000 training / 2,000 held-out random chains", "report": rep}
+    # the model's choice re-timed on this GPU against a fresh exhaustive
+    # autotune, on chains the dataset never saw (another seed)
+    live = cm.live_quality(model, n=args.live_chains, seed=20260, reps=10, max_input_bytes=1 << 28)
+    out["live"] = {"chains": args.live_chains, "model": live["model"], "default": live["default"]}
+    log("live", out["live"])
     if not args.no_cpu_baseline:
         from oracle import mlp
         X = data["features"][:rep["n_train"]]
@@ -1260,6 +1265,8 @@ def main():
     ap.add_argument("--data", nargs="+", default=[],
                     help="cost-model label shards (default: the committed dataset)")
     ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--live-chains", type=int, default=100,
+                    help="cost model: unseen chains re-timed against a fresh autotune on this GPU")
     ap.add_argument("--rates", type=float, nargs="+", default=[200, 500, 1000, 2000])
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--serve-requests", type=int, default=2000, help="at least this many requests per rate")
