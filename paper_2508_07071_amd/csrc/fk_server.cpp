@@ -461,6 +461,17 @@ extern "C" fk_status fk_server_submit(fk_server *s, const fk_request *req, uint6
         r->out_bytes = off;
         if (req->frame_on_device != 0 && req->frame_on_device != 1)
             return set_error(FK_ERR_INVALID_ARG, "frame_on_device must be 0 or 1");
+        if (req->frame_on_device) {
+            // the kernels read the frame in place: it must be device memory
+            hipPointerAttribute_t attr;
+            std::memset(&attr, 0, sizeof attr);
+            const hipError_t e = hipPointerGetAttributes(&attr, req->frame);
+            if (e != hipSuccess ||
+                (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)) {
+                (void)hipGetLastError();  // clear the failed query's error
+                return set_error(FK_ERR_INVALID_ARG, "frame_on_device: the frame is not device memory");
+            }
+        }
         const int64_t row = (int64_t)req->width * s->C * s->es_in;
         if (req->frame_on_device) {
             // read in place: no copy, no frame bytes in the block

@@ -240,3 +240,23 @@ def test_device_frames_match_host_frames_and_merge_into_launches():
         refs = oracle.run_chain(CHAIN, [frame.numpy()], [dict(c, frame=0) for c in crops])
         for j, r in enumerate(refs):
             assert_bitexact(dev_out[i][j], r["out"], f"oracle request {i} crop {j}")
+
+
+def test_device_flag_on_a_host_frame_is_refused():
+    """A request that says its frame is on the device must point at device
+    memory: a pinned host frame with the flag set is refused at submit."""
+    say("device flag on a host frame")
+    frame, crops = requests(6, 1)[0]
+    desc = fk.chain_desc(CHAIN)
+    arena = torch.empty(64 << 20, dtype=torch.uint8, device="cuda:0")
+    srv = fk.fk_server_create(fk.server_opts(desc, arena))
+    try:
+        req = fk.make_request(frame, crops)
+        assert req.frame_on_device == 0
+        req.frame_on_device = 1
+        with pytest.raises(fk.FKError) as e:
+            fk.fk_server_submit(srv, req)
+        assert e.value.status == fk.FK_ERR_INVALID_ARG
+        assert fk.fk_server_stats_get(srv).submitted == 0
+    finally:
+        fk.fk_server_destroy(srv)
