@@ -1118,6 +1118,8 @@ def serve_workload(args):
     modes = [fk.FK_SERVER_BATCHED, fk.FK_SERVER_PER_REQUEST, fk.FK_SERVER_UNFUSED]
     for rate in args.rates:
         for mode in modes:
+            if mode == fk.FK_SERVER_UNFUSED and rate > 2000:
+                continue  # saturated from about 1,200 req/s on
             n = max(args.serve_requests, int(rate * args.serve_seconds))
             if mode == fk.FK_SERVER_UNFUSED and rate > 1000:
                 n = min(n, 1000)  # past its capacity the baseline's backlog only grows
@@ -1267,7 +1269,9 @@ def main():
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--live-chains", type=int, default=100,
                     help="cost model: unseen chains re-timed against a fresh autotune on this GPU")
-    ap.add_argument("--rates", type=float, nargs="+", default=[200, 500, 1000, 2000])
+    ap.add_argument("--rates", type=float, nargs="+", default=[200, 500, 1000, 2000, 4000, 6000],
+                    help="serving rates with host frames (config 4 is 200..2000; 4000 and 6000 "
+                         "find where the frame copies saturate PCIe)")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--serve-requests", type=int, default=2000, help="at least this many requests per rate")
     ap.add_argument("--device-rates", type=float, nargs="+", default=[2000, 10000, 20000],
