@@ -129,3 +129,39 @@ def test_refused_double_chains():
         with pytest.raises(fk.FKError) as e:
             fk.fk_model_features(p.h, arr, 2)
         assert e.value.status == fk.FK_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_random_double_chains_match_oracle(seed):
+    """Random op lists (up to 48 ops of swap, cvt, mul, add, sub, div, scalar
+    or per-channel constants) on plain reads of every input type with an fp64
+    write, packed or planar, 1-4 frames of 16-200 px sides."""
+    say("random fp64 chains, seed", seed)
+    g = datagen.rng(900 + seed)
+    for k in range(8):
+        spec = datagen.random_chain_spec(g, max_ops=48, side=(16, 200), max_batch=4)
+        ch = spec["chain"]
+        ch["read"].update(kind="plain", dtype=["u8", "f16", "f32", "f64"][k % 4], out_w=0, out_h=0)
+        ch["write"]["dtype"] = "f64"
+        fh, fw = spec["frame_hw"]
+        frames = [datagen.frame(g, fh, fw, ch["read"]["channels"], dtype=ch["read"]["dtype"])
+                  for _ in range(spec["batch"])]
+        items = []
+        for b in range(spec["batch"]):
+            # odd items read a random sub-rectangle of their frame
+            w = int(g.integers(1, fw + 1)) if b % 2 else fw
+            h = int(g.integers(1, fh + 1)) if b % 2 else fh
+            items.append({"frame": b, "x": int(g.integers(0, fw - w + 1)),
+                          "y": int(g.integers(0, fh - h + 1)), "w": w, "h": h})
+        refs = oracle.run_chain(ch, frames, items)
+        dframes = to_dev(frames)
+        for strict in (True, False):
+            with Plan(ch, len(items), strict=strict) as p:
+                outs = host(p.run(dframes, items))
+            for b, (o, r) in enumerate(zip(outs, refs)):
+                what = (f"chain {k} item {b} ({ch['read']['dtype']}x{ch['read']['channels']} "
+                        f"{len(ch['ops'])} ops -> f64 {ch['write']['layout']})")
+                if strict:
+                    assert_bitexact(o, r["out"], what)
+                else:
+                    assert_close(o, r, rel=REL64, what=what)

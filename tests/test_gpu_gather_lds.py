@@ -145,6 +145,43 @@ def test_table_path_and_graph_replay():
                     assert_bitexact(gg, r["out"], f"graph={graph} item {b}")
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_random_rois_and_output_sizes(seed):
+    """Random geometry through the staged gather: frames 16-1024 px wide in
+    multiples of 16 px (16-byte-aligned rows, so items may stage), ROIs of
+    1 px up to the whole frame, outputs of 1-300 px per side (down- and
+    upsampling, per item), in one run over several frames (the run table);
+    strict bits against the oracle, contracted bits against the direct
+    gather."""
+    say("LDS gather, random ROIs, seed", seed)
+    g = datagen.rng(1400 + seed)
+    frames = []
+    for _ in range(3):
+        w = 16 * int(g.integers(1, 65))
+        h = int(g.integers(2, 400))
+        frames.append(datagen.frame(g, h, w, 3))
+    items = []
+    for _ in range(24):
+        f = int(g.integers(0, 3))
+        fh, fw = frames[f].shape[:2]
+        w = datagen.log_uniform_int(g, 1, fw)
+        h = datagen.log_uniform_int(g, 1, fh)
+        items.append({"frame": f, "x": int(g.integers(0, fw - w + 1)), "y": int(g.integers(0, fh - h + 1)),
+                      "w": w, "h": h, "out_w": datagen.log_uniform_int(g, 1, 300),
+                      "out_h": datagen.log_uniform_int(g, 1, 300)})
+    chain = datagen.normalize_chain(0, 0)
+    refs = oracle.run_chain(chain, frames, items)
+    dframes = to_dev(frames)
+    cfg = [(64, 1), (256, 2), (1024, 1), (128, 4)][seed]
+    got = run(chain, dframes, items, True, fk.FK_GATHER_LDS, cfg)
+    for b, (gg, r) in enumerate(zip(got, refs)):
+        assert_bitexact(gg, r["out"], f"{cfg} item {items[b]}")
+    lds = run(chain, dframes, items, False, fk.FK_GATHER_LDS, cfg)
+    direct = run(chain, dframes, items, False, fk.FK_GATHER_DIRECT, cfg)
+    for b, (x, y) in enumerate(zip(lds, direct)):
+        assert_bitexact(x, y, f"contracted {cfg} item {items[b]}")
+
+
 def test_unknown_gather_mode_is_refused():
     chain = datagen.normalize_chain(64, 128)
     with pytest.raises(fk.FKError) as e:
