@@ -93,6 +93,27 @@ def timeit(fn, reps=50, warm_s=0.0):
     return e0.elapsed_time(e1) / reps
 
 
+ROTATE_BYTES = 600 << 20  # frames a rotating measurement cycles through
+
+
+def rotation_sets(frame_bytes):
+    """How many copies of a frame a rotating measurement cycles through so
+    that a frame has left the 256 MB Infinity Cache before it is read
+    again."""
+    return max(2, -(-ROTATE_BYTES // frame_bytes))
+
+
+def rotating_ms(run, sets, reps=50, warm_s=0.0):
+    """Mean ms per call of run(set) over `reps` back-to-back calls that cycle
+    through `sets` (timeit's bracketing)."""
+    turn = [0]
+
+    def one():
+        run(sets[turn[0] % len(sets)])
+        turn[0] += 1
+    return timeit(one, reps, warm_s)
+
+
 def vf_sweep(args):
     import numpy as np
     import torch
@@ -586,7 +607,10 @@ def cpu_baseline_vf(args, cfgs):
 
 def hf_workload(args):
     """Batched uneven crops (config 2 sizes): fused single launch vs per-crop
-    launches vs unfused per-op per-crop, eager and hipGraph."""
+    launches vs unfused per-op per-crop, eager and hipGraph.  Runs are back
+    to back on one frame, which stays in the Infinity Cache; the default
+    run's per_config rows time the same batches with the frames read from
+    HBM."""
     import numpy as np
     import torch
 
@@ -903,7 +927,8 @@ def sweeps_workload(args):
       dtypes:    the same chain at B = 50 for eight input -> output types,
                  two of them (f32 -> f64, f64 -> f64) computing in fp64;
       precision: cvt + N mul/add (N in 4, 64, 256) over one 3840x2160 fp32
-                 frame, computed in fp32 and in fp64;
+                 frame, computed in fp32 and in fp64 (timed over rotating
+                 copies of the frame, read from HBM);
       instructions_per_op: 500 multiplications as ops of M instructions
                  over 66,355,200 fp32 values, fused vs one kernel per op."""
     import numpy as np
@@ -993,26 +1018,33 @@ def sweeps_workload(args):
     # Section VI-I's remark that double precision turns the kernel compute-
     # bound, checked at a size where arithmetic can show: the same op list in
     # fp32 (fp32 write) and in fp64 (fp64 write) over one 3840x2160 fp32 frame
+    # (autotuned on one frame, then timed over rotating frame copies, so the
+    # frames come from HBM)
     precision = []
     g = datagen.rng(args.seed + 5)
     pframe = torch.from_numpy(datagen.frame(g, 2160, 3840, 1, dtype="f32")).to(dev)
+    pframes = [pframe] + [pframe.clone() for _ in range(rotation_sets(pframe.numel() * 4) - 1)]
+    it = {"frame": 0, "x": 0, "y": 0, "w": 3840, "h": 2160}
     for n_ops in PRECISION_DEPTHS:
         base = datagen.muladd_chain(n_ops, datagen.rng(args.seed + n_ops), channels=1)
         for dout in ("f32", "f64"):
             ch = dict(base, read=dict(base["read"], dtype="f32"), write={"dtype": dout, "layout": "packed"})
-            out = torch.empty((2160, 3840, 1), dtype=fk.TORCH_DTYPE[dout], device=dev)
-            it = {"frame": 0, "x": 0, "y": 0, "w": 3840, "h": 2160}
-            arr = fk.make_items(ch, [pframe], [it], [out])
+            outs = [torch.empty((2160, 3840, 1), dtype=fk.TORCH_DTYPE[dout], device=dev) for _ in pframes]
+            arrs = [fk.make_items(ch, [f], [it], [o]) for f, o in zip(pframes, outs)]
             plan = fk.fk_plan_create(fk.chain_desc(ch), 1, fk.plan_opts(tier=fk.FK_TIER_RUNTIME))
-            best, times = fk.fk_autotune(plan, arr, 1, 5)
-            ms = min(times)
-            nbytes = 2160 * 3840 * (4 + out.element_size())
+            best, times = fk.fk_autotune(plan, arrs[0], 1, 5)
+            ms = rotating_ms(lambda a: fk.fk_run(plan, a, 1, stream), arrs, 50, warm_s=2e-3)
+            nbytes = 2160 * 3840 * (4 + outs[0].element_size())
             r = {"n_ops": n_ops, "out": dout, "autotuned": [best.block_threads, best.coarsen],
-                 "fused_ms": round(ms, 5), "gbps": round(nbytes / (ms * 1e-3) / 1e9, 1),
-                 "gflops": round(n_ops * 2160 * 3840 / (ms * 1e-3) / 1e9, 1)}
+                 "rotation_sets": len(pframes), "fused_ms": round(ms, 5),
+                 "gbps": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                 "gflops": round(n_ops * 2160 * 3840 / (ms * 1e-3) / 1e9, 1),
+                 "autotune_one_frame_ms": round(min(times), 5)}
             fk.fk_plan_destroy(plan)
+            del outs, arrs
             log("precision", r)
             precision.append(r)
+    del pframes
 
     # Section VI-E: 500 fp32 multiplications split into ops of M instructions
     # over 66,355,200 values (the paper's 259,200 blocks of 256 threads):
@@ -1050,7 +1082,7 @@ def sweeps_workload(args):
 
 def reads_workload(args):
     """The other read ops (nearest-neighbour and NV12), fused vs the unfused
-    baseline:
+    baseline (fused times over rotating copies of the frame, read from HBM):
       nv12_full:   a 3840x2160 NV12 frame (12.4 MB) converted to planar fp32
                    B, G, R (99.5 MB written): HBM-bound, algorithmic bytes =
                    frame + output;
@@ -1070,14 +1102,23 @@ def reads_workload(args):
 
 
     def measure(ch, frame, items, alg, name, reps=50):
-        outs = [torch.empty(fk.out_shape(ch, it), dtype=fk.TORCH_DTYPE[ch["write"]["dtype"]], device=dev)
-                for it in items]
-        arr = fk.make_items(ch, [frame], items, outs)
+        # autotuned on the frame, then timed over rotating (frame copy,
+        # outputs) sets, so the frames come from HBM
+        R = rotation_sets(frame.numel() * frame.element_size())
+        frames = [frame] + [frame.clone() for _ in range(R - 1)]
+        arrs = []
+        for f in frames:
+            outs = [torch.empty(fk.out_shape(ch, it), dtype=fk.TORCH_DTYPE[ch["write"]["dtype"]], device=dev)
+                    for it in items]
+            arrs.append((fk.make_items(ch, [f], items, outs), outs))
+        arr = arrs[0][0]
         n = len(items)
         plan = fk.fk_plan_create(fk.chain_desc(ch), n, fk.plan_opts())
         best, _ = fk.fk_autotune(plan, arr, n, 5)
-        r = {"case": name, "items": n, "alg_bytes": alg, "autotuned": [best.block_threads, best.coarsen]}
-        r["fused_ms"] = round(timeit(lambda: fk.fk_run(plan, arr, n, stream), reps, warm_s=2e-3), 5)
+        r = {"case": name, "items": n, "alg_bytes": alg, "autotuned": [best.block_threads, best.coarsen],
+             "rotation_sets": R}
+        r["fused_ms"] = round(rotating_ms(lambda a: fk.fk_run(plan, a[0], n, stream), arrs, reps,
+                                          warm_s=2e-3), 5)
         r["gbps"] = round(alg / (r["fused_ms"] * 1e-3) / 1e9, 1)
         r["hbm_frac"] = round(r["gbps"] / HBM_PEAK_GBPS, 4)
         if not args.no_unfused:
@@ -1087,6 +1128,7 @@ def reads_workload(args):
                                                                    stream), 3), 4)
             r["speedup_vs_unfused"] = round(r["unfused_ms"] / r["fused_ms"], 1)
         fk.fk_plan_destroy(plan)
+        del frames, arrs
         log(r)
         return r
 

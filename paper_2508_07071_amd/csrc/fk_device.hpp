@@ -31,6 +31,7 @@
 
 #include <stdint.h>
 
+#include <type_traits>
 #include <utility>
 
 #include "fk_internal.hpp"
@@ -849,6 +850,7 @@ struct RuntimeCompute {
 template <int DT, int C>
 struct WritePlanar {
     static constexpr int layout = LY_PLANAR;
+    static constexpr int dtype = DT;
     static constexpr int lds_bytes_per_thread = 0;
     __device__ __forceinline__ static void store(const ItemRec &it, int oy, int ox0, int n,
                                                  const float (&r)[kUnitPx][C], uint8_t *, bool)
@@ -888,6 +890,7 @@ struct WritePlanar {
 template <int DT, int C>
 struct WritePacked {
     static constexpr int layout = LY_PACKED;
+    static constexpr int dtype = DT;
     static constexpr int ES = DSize<DT>::v;
     static constexpr int UB = kUnitPx * C * ES;                 // bytes per unit
     static constexpr bool kStage = (UB != 16 && UB != 8);       // else already lane-contiguous
@@ -1084,6 +1087,30 @@ __device__ __forceinline__ void tile_item(const KArgs &a, const FK_CONST KArgs *
     ubase = (tile - first_tile) * tile_units;
 }
 
+// Units of a thread's K that k_transform holds in registers at once.  A
+// block of up to 1024 threads leaves each lane 128 VGPRs; past that the
+// compiler spills the register tile to scratch, and such launches ran 4-5x
+// slower than unspilled ones (a plain u8 read into packed fp32: 103 us at
+// K = 8 against 24 us at K <= 4).  So the K units go through in groups of
+// G, each loaded, computed and stored before the next: G = K where the
+// whole tile fits, else the largest group that compiles without scratch
+// (from the kernels' scratch sizes): 4 units of 3 channels, 2 of 4, and
+// half that for the run-time op list into planar fp32, whose per-channel
+// 16-byte stores gather each value anew (once more halved for fp32 plain
+// reads).
+template <class Read, class Compute, class Write, int C, int K>
+constexpr int unit_group()
+{
+    constexpr bool rt = std::is_same<Compute, RuntimeCompute>::value;
+    constexpr bool planar32 = Write::layout == LY_PLANAR && Write::dtype == DT_F32;
+    int g = C == 1 ? 8 : C == 3 ? 4 : 2;
+    if (rt && planar32 && C == 3)
+        g = 2;
+    if (rt && planar32 && Read::kind == RD_PLAIN && Read::elem_size == 4)
+        g /= 2;
+    return K < g ? K : g;
+}
+
 template <class Read, class Compute, class Write, int C, int K>
 __global__ __launch_bounds__(kMaxBlock) void k_transform(const KArgs a)
 {
@@ -1117,57 +1144,61 @@ __global__ __launch_bounds__(kMaxBlock) void k_transform(const KArgs a)
         bool contig = false;
         if constexpr (Read::kind == RD_PLAIN)
             contig = it.flags & IF_CONTIG;
-        float v[K][kUnitPx][C];
-        int oy[K], ox0[K], nv[K];
+        constexpr int G = unit_group<Read, Compute, Write, C, K>();
+#pragma unroll 1
+        for (int g0 = 0; g0 < K; g0 += G) {
+            float v[G][kUnitPx][C];
+            int oy[G], ox0[G], nv[G];
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const uint32_t u = ubase + (uint32_t)(j * T + tid);
-            if (u < units) {
-                if (contig) {
-                    oy[j] = 0;
-                    ox0[j] = (int)(u * kUnitPx);
-                    nv[j] = kUnitPx;
-                } else {
-                    const uint32_t row = rowdiv(u);
-                    oy[j] = (int)row;
-                    ox0[j] = (int)(u - row * upr) * kUnitPx;
-                    const int left = it.ow - ox0[j];
-                    nv[j] = left < kUnitPx ? left : kUnitPx;
-                }
-                Read::load(it, oy[j], ox0[j], nv[j], v[j]);
-            } else {
-                oy[j] = 0;
-                ox0[j] = 0;
-                nv[j] = 0;
-#pragma unroll
-                for (int i = 0; i < kUnitPx; ++i)
-#pragma unroll
-                    for (int c = 0; c < C; ++c)
-                        v[j][i][c] = 0.0f;
-            }
-        }
-        if constexpr (C >= 3) {
-            // run-time tier: the chain's net channel swap, applied at the read
-            if (swap) {
-#pragma unroll
-                for (int j = 0; j < K; ++j)
-#pragma unroll
-                    for (int i = 0; i < kUnitPx; ++i) {
-                        const float t = v[j][i][0];
-                        v[j][i][0] = v[j][i][2];
-                        v[j][i][2] = t;
+            for (int j = 0; j < G; ++j) {
+                const uint32_t u = ubase + (uint32_t)((g0 + j) * T + tid);
+                if (u < units) {
+                    if (contig) {
+                        oy[j] = 0;
+                        ox0[j] = (int)(u * kUnitPx);
+                        nv[j] = kUnitPx;
+                    } else {
+                        const uint32_t row = rowdiv(u);
+                        oy[j] = (int)row;
+                        ox0[j] = (int)(u - row * upr) * kUnitPx;
+                        const int left = it.ow - ox0[j];
+                        nv[j] = left < kUnitPx ? left : kUnitPx;
                     }
+                    Read::load(it, oy[j], ox0[j], nv[j], v[j]);
+                } else {
+                    oy[j] = 0;
+                    ox0[j] = 0;
+                    nv[j] = 0;
+#pragma unroll
+                    for (int i = 0; i < kUnitPx; ++i)
+#pragma unroll
+                        for (int c = 0; c < C; ++c)
+                            v[j][i][c] = 0.0f;
+                }
             }
-        }
+            if constexpr (C >= 3) {
+                // run-time tier: the chain's net channel swap, applied at the read
+                if (swap) {
+#pragma unroll
+                    for (int j = 0; j < G; ++j)
+#pragma unroll
+                        for (int i = 0; i < kUnitPx; ++i) {
+                            const float t = v[j][i][0];
+                            v[j][i][0] = v[j][i][2];
+                            v[j][i][2] = t;
+                        }
+                }
+            }
 
-        Compute::template apply<K, C>(a, v);
+            Compute::template apply<G, C>(a, v);
 
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const bool whole = nv[j] == kUnitPx && (it.flags & IF_DST_VEC);
-            const bool wave_whole = __all(whole ? 1 : 0);
-            if (nv[j] > 0)
-                Write::store(it, oy[j], ox0[j], nv[j], v[j], wave_lds, wave_whole);
+            for (int j = 0; j < G; ++j) {
+                const bool whole = nv[j] == kUnitPx && (it.flags & IF_DST_VEC);
+                const bool wave_whole = __all(whole ? 1 : 0);
+                if (nv[j] > 0)
+                    Write::store(it, oy[j], ox0[j], nv[j], v[j], wave_lds, wave_whole);
+            }
         }
     }
 }
@@ -1599,8 +1630,25 @@ __device__ __forceinline__ void block_reduce(StatAcc<C> &acc, StatPartial (*lds)
 }
 
 // One tile of a plain read whose units are all whole and dword-aligned:
-// the K units' raw dwords are fetched first (K loads in flight per lane),
-// then each unit is unpacked, run through the ops and accumulated.
+// a group of the K units' raw dwords is fetched first (GW loads in flight
+// per lane), then each unit is unpacked, run through the ops and
+// accumulated.  All K units form one group while their words fit in 48
+// dwords for up to 3 channels (28 for 4, whose accumulators take more
+// registers); past that, groups of at most 24 (16) dwords.  With all K
+// units' words live, fp32 frames of 3 channels at K = 8 and of 4 channels
+// at K >= 4 spilled to scratch and took 2-3x longer.
+template <int NW, int C, int K>
+constexpr int stats_group()
+{
+    if (NW * K <= (C <= 3 ? 48 : 28))
+        return K;
+    const int budget = C <= 3 ? 24 : 16;
+    int g = 1;
+    while (g * 2 * NW <= budget)
+        g *= 2;
+    return g;
+}
+
 template <class Read, class Compute, int C, int K>
 __device__ __forceinline__ void stats_tile_vec(const KArgs &a, const ItemRec &it, uint32_t ubase,
                                                uint32_t units, const RowDiv &rowdiv, int T, int tid,
@@ -1608,52 +1656,56 @@ __device__ __forceinline__ void stats_tile_vec(const KArgs &a, const ItemRec &it
 {
     constexpr int DT = Read::dtype;
     constexpr int NW = kUnitPx * C * DSize<DT>::v / 4;
-    uint32_t w[K][NW];
-    bool ok[K];
+    constexpr int GW = stats_group<NW, C, K>();
+#pragma unroll 1
+    for (int g0 = 0; g0 < K; g0 += GW) {
+        uint32_t w[GW][NW];
+        bool ok[GW];
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const uint32_t u = ubase + (uint32_t)(j * T + tid);
-        ok[j] = u < units;
-        if (ok[j]) {
-            const uint32_t row = rowdiv(u);
-            const int ox0 = (int)(u - row * rowdiv.upr) * kUnitPx;
-            const FK_GLOBAL uint32_t *p =
-                (const FK_GLOBAL uint32_t *)((gsrc_t)it.src + (int64_t)(it.y + (int)row) * it.pitch +
-                                             (int64_t)(it.x + ox0) * (C * DSize<DT>::v));
+        for (int j = 0; j < GW; ++j) {
+            const uint32_t u = ubase + (uint32_t)((g0 + j) * T + tid);
+            ok[j] = u < units;
+            if (ok[j]) {
+                const uint32_t row = rowdiv(u);
+                const int ox0 = (int)(u - row * rowdiv.upr) * kUnitPx;
+                const FK_GLOBAL uint32_t *p =
+                    (const FK_GLOBAL uint32_t *)((gsrc_t)it.src + (int64_t)(it.y + (int)row) * it.pitch +
+                                                 (int64_t)(it.x + ox0) * (C * DSize<DT>::v));
 #pragma unroll
-            for (int i = 0; i < NW; ++i)
-                w[j][i] = p[i];
+                for (int i = 0; i < NW; ++i)
+                    w[j][i] = p[i];
+            }
         }
-    }
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        if (!ok[j])
-            continue;
-        float v[1][kUnitPx][C];
+        for (int j = 0; j < GW; ++j) {
+            if (!ok[j])
+                continue;
+            float v[1][kUnitPx][C];
 #pragma unroll
-        for (int i = 0; i < kUnitPx; ++i)
+            for (int i = 0; i < kUnitPx; ++i)
 #pragma unroll
-            for (int c = 0; c < C; ++c)
-                v[0][i][c] = unpack_elem<DT, NW>(w[j], i * C + c);
-        if constexpr (C >= 3) {
-            if (swap) {
+                for (int c = 0; c < C; ++c)
+                    v[0][i][c] = unpack_elem<DT, NW>(w[j], i * C + c);
+            if constexpr (C >= 3) {
+                if (swap) {
 #pragma unroll
-                for (int i = 0; i < kUnitPx; ++i) {
-                    const float s = v[0][i][0];
-                    v[0][i][0] = v[0][i][2];
-                    v[0][i][2] = s;
+                    for (int i = 0; i < kUnitPx; ++i) {
+                        const float s = v[0][i][0];
+                        v[0][i][0] = v[0][i][2];
+                        v[0][i][2] = s;
+                    }
                 }
             }
+            Compute::template apply<1, C>(a, v);
+#pragma unroll
+            for (int i = 0; i < kUnitPx; ++i)
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    acc.mn[c] = fminf(acc.mn[c], v[0][i][c]);
+                    acc.mx[c] = fmaxf(acc.mx[c], v[0][i][c]);
+                    acc.sum[c] += (double)v[0][i][c];
+                }
         }
-        Compute::template apply<1, C>(a, v);
-#pragma unroll
-        for (int i = 0; i < kUnitPx; ++i)
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                acc.mn[c] = fminf(acc.mn[c], v[0][i][c]);
-                acc.mx[c] = fmaxf(acc.mx[c], v[0][i][c]);
-                acc.sum[c] += (double)v[0][i][c];
-            }
     }
 }
 
