@@ -436,9 +436,27 @@ struct ReadNV12 {
         nv12_pixel(it, it.x + ox, it.y + oy, r);
     }
 
+    // A whole unit of a frame whose base, pitch and ROI column are
+    // multiples of 4 (IF_SRC_VEC) reads its 4 luma bytes and the 2 chroma
+    // pairs serving them as one dword each; otherwise byte by byte.
     __device__ __forceinline__ static void load(const ItemRec &it, int oy, int ox0, int n,
                                                 float (&r)[kUnitPx][C])
     {
+        if (n == kUnitPx && (it.flags & IF_SRC_VEC)) {
+            gsrc_t base = (gsrc_t)it.src;
+            const int x = it.x + ox0;
+            const int y = it.y + oy;
+            const uint32_t yw = *(const FK_GLOBAL uint32_t *)(base + (int64_t)y * it.pitch + x);
+            const uint32_t cw =
+                *(const FK_GLOBAL uint32_t *)(base + ((int64_t)it.fh + (y >> 1)) * it.pitch + x);
+#pragma unroll
+            for (int i = 0; i < kUnitPx; ++i) {
+                const int k = i & ~1;  // the chroma pair of pixel i
+                nv12_to_bgr((float)((yw >> (8 * i)) & 0xffu), (float)((cw >> (8 * k)) & 0xffu),
+                            (float)((cw >> (8 * k + 8)) & 0xffu), r[i]);
+            }
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < kUnitPx; ++i) {
             if (i < n) {

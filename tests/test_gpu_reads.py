@@ -75,6 +75,36 @@ def test_nv12_reads_match_oracle(kind, out_dtype, layout):
     both_modes(ch, [fr], items, f"{kind} {out_dtype} {layout}", unfused=out_dtype == "f32")
 
 
+def test_nv12_dword_units_and_byte_units():
+    """The 1:1 NV12 read takes a whole unit as one luma and one chroma dword
+    when the frame base, pitch and ROI column are multiples of 4, byte by
+    byte otherwise: ROIs at columns 0, 4, 8, 636 (dwords) and 1, 2, 6
+    (bytes), odd and even first rows, ragged widths; a batch of equal-sized
+    crops (the compact kernel-argument form) mixing both; and a frame base
+    2 bytes past a dword boundary (bytes everywhere)."""
+    say("nv12 dword and byte units")
+    g = datagen.rng(19)
+    fr = datagen.nv12_frame(g, 60, 640)
+    ch = {"read": {"kind": "nv12", "dtype": "u8", "channels": 3, "out_w": 0, "out_h": 0},
+          "ops": norm_ops(3), "write": {"dtype": "f32", "layout": "planar"}}
+    rois = [(0, 0, 640, 60), (4, 3, 21, 9), (8, 1, 100, 50), (636, 59, 4, 1), (1, 2, 33, 7), (2, 5, 64, 4),
+            (6, 7, 11, 13)]
+    items = [{"frame": 0, "x": x, "y": y, "w": w, "h": h, "out_w": w, "out_h": h} for x, y, w, h in rois]
+    both_modes(ch, [fr], items, "nv12 mixed", unfused=True)
+    same = [{"frame": 0, "x": x, "y": y, "w": 24, "h": 6, "out_w": 24, "out_h": 6}
+            for x, y in ((0, 0), (4, 1), (5, 2), (12, 9), (600, 54), (3, 3))]
+    both_modes(ch, [fr], same, "nv12 compact")
+    # a frame 2 bytes past a dword boundary
+    buf = torch.zeros(fr.size + 64, dtype=torch.uint8, device="cuda:0")
+    buf[2:2 + fr.size] = torch.from_numpy(fr.reshape(-1)).to("cuda:0")
+    dfr = buf[2:2 + fr.size].view(fr.shape)
+    refs = oracle.run_chain(ch, [fr], items[:3])
+    with Plan(ch, 3, strict=True) as p:
+        outs = host(p.run([dfr], items[:3]))
+    for b, (o, r) in enumerate(zip(outs, refs)):
+        assert_bitexact(o, r["out"], f"nv12 offset base item {b}")
+
+
 def test_nv12_frame_with_row_padding():
     """An NV12 frame whose rows are padded (pitch 704 for 640 pixels): both
     planes follow the pitch."""
