@@ -792,8 +792,8 @@ __device__ __forceinline__ double fma_v(double a, double b, double c) { return f
 // The run-time op list on fp32 values, or on fp64 values for a chain with
 // an fp64 write (the op's fp32 constants taken exactly).
 struct RuntimeCompute {
-    template <int K, int C, typename V>
-    __device__ __forceinline__ static void apply(const KArgs &a, V (&v)[K][kUnitPx][C])
+    template <int K, int C, typename V, int P>
+    __device__ __forceinline__ static void apply(const KArgs &a, V (&v)[K][P][C])
     {
         const FK_CONST OpRec *ops = cptr(a.ops);
         int runs = 1;  // runs of the current loop body so far
@@ -826,7 +826,7 @@ struct RuntimeCompute {
 #pragma unroll
                     for (int j = 0; j < K; ++j)
 #pragma unroll
-                        for (int i = 0; i < kUnitPx; ++i)
+                        for (int i = 0; i < P; ++i)
 #pragma unroll
                             for (int c = 0; c < C; ++c)
                                 v[j][i][c] = fma_v(v[j][i][c], ka[c], kb[c]);
@@ -835,7 +835,7 @@ struct RuntimeCompute {
 #pragma unroll
                     for (int j = 0; j < K; ++j)
 #pragma unroll
-                        for (int i = 0; i < kUnitPx; ++i)
+                        for (int i = 0; i < P; ++i)
 #pragma unroll
                             for (int c = 0; c < C; ++c)
                                 v[j][i][c] = v[j][i][c] * ka[c];
@@ -844,7 +844,7 @@ struct RuntimeCompute {
 #pragma unroll
                     for (int j = 0; j < K; ++j)
 #pragma unroll
-                        for (int i = 0; i < kUnitPx; ++i)
+                        for (int i = 0; i < P; ++i)
 #pragma unroll
                             for (int c = 0; c < C; ++c)
                                 v[j][i][c] = v[j][i][c] + ka[c];
@@ -853,7 +853,7 @@ struct RuntimeCompute {
 #pragma unroll
                     for (int j = 0; j < K; ++j)
 #pragma unroll
-                        for (int i = 0; i < kUnitPx; ++i)
+                        for (int i = 0; i < P; ++i)
 #pragma unroll
                             for (int c = 0; c < C; ++c)
                                 v[j][i][c] = v[j][i][c] / ka[c];

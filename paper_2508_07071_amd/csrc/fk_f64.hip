@@ -53,60 +53,53 @@ __global__ __launch_bounds__(kMaxBlock) void k_f64(const KArgs a)
         const RowDiv rowdiv((uint32_t)it.ow);
         gsrc_t roi = (gsrc_t)it.src + (int64_t)it.y * it.pitch + (int64_t)it.x * (C * ES);
         FK_GLOBAL double *dst = (FK_GLOBAL double *)it.dst;
-        // the lane's pixels in chunks of G groups of 4: one pass of the op
-        // list serves G * 4 * C values (its constants are scalar loads); G
-        // keeps at most 12 doubles live (8 for one channel), so the fp64
-        // divisions' temporaries fit the 128 VGPRs of a 1024-thread block
-        // (four channels, 16 values in one group, spill a little)
-        constexpr int G0 = C == 1 ? 2 : 1;
-        constexpr int G = G0 < K ? G0 : K;
-        for (int j0 = 0; j0 < K; j0 += G) {
-            double v[G][kUnitPx][C];
+        // the lane's 4K pixels in chunks of P: one pass of the op list
+        // serves P * C values (its constants are scalar loads); P keeps at
+        // most 12 doubles live (8 for one channel), so the fp64 divisions'
+        // temporaries fit the 128 VGPRs of a 1024-thread block
+        constexpr int P0 = C == 1 ? 8 : C == 3 ? 4 : 2;
+        constexpr int P = P0 < 4 * K ? P0 : 4 * K;
+        for (int q0 = 0; q0 < 4 * K; q0 += P) {
+            double v[1][P][C];
 #pragma unroll
-            for (int j = 0; j < G; ++j)
+            for (int i = 0; i < P; ++i) {
+                const uint32_t p = pbase + (uint32_t)((q0 + i) * T + tid);
+                if (p < npx) {
+                    const uint32_t row = rowdiv(p);
+                    const uint32_t col = p - row * (uint32_t)it.ow;
+                    gsrc_t s = roi + (int64_t)row * it.pitch + (int64_t)col * (C * ES);
 #pragma unroll
-                for (int i = 0; i < kUnitPx; ++i) {
-                    const uint32_t p = pbase + (uint32_t)(((j0 + j) * kUnitPx + i) * T + tid);
-                    if (p < npx) {
-                        const uint32_t row = rowdiv(p);
-                        const uint32_t col = p - row * (uint32_t)it.ow;
-                        gsrc_t s = roi + (int64_t)row * it.pitch + (int64_t)col * (C * ES);
+                    for (int c = 0; c < C; ++c)
+                        v[0][i][c] = load_f64<DI>(s + c * ES);
+                } else {
 #pragma unroll
-                        for (int c = 0; c < C; ++c)
-                            v[j][i][c] = load_f64<DI>(s + c * ES);
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < C; ++c)
-                            v[j][i][c] = 0.0;
-                    }
+                    for (int c = 0; c < C; ++c)
+                        v[0][i][c] = 0.0;
                 }
+            }
             if constexpr (C >= 3) {
                 if (a.swap) {  // the chain's net channel swap, at the read
 #pragma unroll
-                    for (int j = 0; j < G; ++j)
-#pragma unroll
-                        for (int i = 0; i < kUnitPx; ++i) {
-                            const double t = v[j][i][0];
-                            v[j][i][0] = v[j][i][2];
-                            v[j][i][2] = t;
-                        }
-                }
-            }
-            RuntimeCompute::template apply<G, C>(a, v);
-#pragma unroll
-            for (int j = 0; j < G; ++j)
-#pragma unroll
-                for (int i = 0; i < kUnitPx; ++i) {
-                    const uint32_t p = pbase + (uint32_t)(((j0 + j) * kUnitPx + i) * T + tid);
-                    if (p < npx) {
-#pragma unroll
-                        for (int c = 0; c < C; ++c) {
-                            // planar: plane c; packed: channel c of the pixel
-                            const int64_t o = Planar ? (int64_t)c * npx + p : (int64_t)p * C + c;
-                            __builtin_nontemporal_store(v[j][i][c], dst + o);
-                        }
+                    for (int i = 0; i < P; ++i) {
+                        const double t = v[0][i][0];
+                        v[0][i][0] = v[0][i][2];
+                        v[0][i][2] = t;
                     }
                 }
+            }
+            RuntimeCompute::template apply<1, C>(a, v);
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                const uint32_t p = pbase + (uint32_t)((q0 + i) * T + tid);
+                if (p < npx) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        // planar: plane c; packed: channel c of the pixel
+                        const int64_t o = Planar ? (int64_t)c * npx + p : (int64_t)p * C + c;
+                        __builtin_nontemporal_store(v[0][i][c], dst + o);
+                    }
+                }
+            }
         }
     }
 }
