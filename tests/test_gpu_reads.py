@@ -127,10 +127,19 @@ def test_stats_over_nearest_and_nv12_reads():
     say("stats over nearest / nv12")
     g = datagen.rng(14)
     cases = [({"kind": "crop_nearest", "dtype": "u8", "channels": 3}, datagen.frame(g, 200, 300, 3)),
-             ({"kind": "nv12_resize", "dtype": "u8", "channels": 3}, datagen.nv12_frame(g, 200, 300))]
+             ({"kind": "nv12_resize", "dtype": "u8", "channels": 3}, datagen.nv12_frame(g, 200, 300)),
+             ({"kind": "nv12", "dtype": "u8", "channels": 3}, datagen.nv12_frame(g, 200, 300))]
     for read, fr in cases:
         read = dict(read, out_w=0, out_h=0)
         items = datagen.random_crops(g, 5, 300, 200, lo=10, hi=180, out=(50, 70))
+        if read["kind"] == "nv12":
+            # 1:1 reads: ROIs at dword columns (whole units as dwords) and not
+            one = []
+            for b, it in enumerate(items):
+                x = it["x"] & ~3 if b % 2 else it["x"] | 1
+                w = min(it["w"], 300 - x)
+                one.append(dict(it, x=x, w=w, out_w=w, out_h=it["h"]))
+            items = one
         img = {"read": read, "ops": norm_ops(3), "write": {"dtype": "f32", "layout": "packed"}}
         st = dict(img, write={"dtype": "f64", "layout": "stats"})
         imgs = oracle.run_chain(img, [fr], items)
