@@ -44,7 +44,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 # MI355X's published fp32 vector peak (packed fp32: two FMAs per lane and cycle)
 FP32_PEAK_TFLOPS = 157.3
-# This build's fp32 ceiling: the kernels are compiled without packed fp32
+# The library's fp32 ceiling: its kernels are compiled without packed fp32
 # instructions, so one FMA per lane and cycle: 256 CUs x 4 SIMDs x 16 lanes
 # x 2.4 GHz x 2 flops
 FP32_ISSUE_CEILING_TFLOPS = 78.6
@@ -57,7 +57,7 @@ FRAME_HW = (2160, 3840)
 
 def alu_roof(tflops):
     """Roofline record of an fp32-ALU-bound kernel: the fraction of the
-    published peak, and of this build's non-packed issue ceiling beside it."""
+    published peak, and of the library's non-packed issue ceiling beside it."""
     return {"bound": "alu", "achieved": round(tflops, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(tflops / FP32_PEAK_TFLOPS, 4),
             "issue_ceiling": FP32_ISSUE_CEILING_TFLOPS,
@@ -1381,7 +1381,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(items and frames shard across GPUs with no exchange; see the design notes).",
               file=sys.stderr)
         sys.exit(2)

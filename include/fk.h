@@ -39,7 +39,7 @@ extern "C" {
 typedef int32_t fk_status;
 #define FK_OK 0
 #define FK_ERR_INVALID_ARG (-1)  /* null pointer, bad size, ROI outside its frame, ... */
-#define FK_ERR_UNSUPPORTED (-2)  /* valid request this build does not implement */
+#define FK_ERR_UNSUPPORTED (-2)  /* valid request the library does not implement */
 #define FK_ERR_OUT_OF_MEMORY (-3)
 #define FK_ERR_HIP (-4)          /* a HIP runtime call failed; see fk_last_error() */
 #define FK_ERR_BAD_STATE (-5)    /* call not allowed in the object's current state */
@@ -238,7 +238,7 @@ typedef struct fk_plan fk_plan;
 const char *fk_status_string(fk_status s);
 const char *fk_last_error(void);
 
-/* Library version and the device architecture this build targets. */
+/* Library version and the device architecture the library is compiled for. */
 const char *fk_version(void);
 
 /* Check a chain without touching the device.  FK_OK or FK_ERR_INVALID_ARG /
@@ -334,8 +334,9 @@ fk_status fk_run_unfused(fk_plan *plan, const fk_item *items, int32_t n_items, v
 fk_status fk_run_unfused_noalloc(fk_plan *plan, const fk_item *items, int32_t n_items,
                                  void *stream);
 
-/* Number of launch configurations the autotuner tries (20) and the i-th. */
-int32_t fk_autotune_space(fk_launch_config *configs, int32_t max_configs);
+/* Number of launch configurations the autotuner tries (20); fills space[i]
+ * with the i-th for i < max_configs (space may be NULL). */
+int32_t fk_autotune_space(fk_launch_config *space, int32_t max_configs);
 
 /* Time every launch configuration on these items (one warm-up launch, then
  * the median of 3 samples of `reps` back-to-back launches timed by HIP

@@ -895,13 +895,13 @@ extern "C" fk_status fk_run_timed(fk_plan *plan, const fk_item *items, int32_t n
 
 // ------------------------------------------------------------- autotune --
 
-extern "C" int32_t fk_autotune_space(fk_launch_config *configs, int32_t max_configs)
+extern "C" int32_t fk_autotune_space(fk_launch_config *space, int32_t max_configs)
 {
     int32_t n = 0;
     for (int t : {64, 128, 256, 512, 1024})
         for (int k : {1, 2, 4, 8}) {
-            if (configs && n < max_configs)
-                configs[n] = fk_launch_config{t, k};
+            if (space && n < max_configs)
+                space[n] = fk_launch_config{t, k};
             ++n;
         }
     return n;
