@@ -1,16 +1,17 @@
-"""Every launch configuration of run-time op-list chains against the oracle.
-Coarsened threads take their units through registers in groups (fewer
-units than K where the whole tile would spill): 4 of 3 channels, 2 of 4,
-half that into planar fp32, 1 for fp32 plain reads into planar fp32.  Each
-chain here runs at all 20 configurations (K = 1, 2, 4, 8 at every block
-size), on frames whose rows end in a partial unit and whose items span
-several tiles, and must give the oracle's bits in the strict mode."""
+"""Every launch configuration against the oracle.  Coarsened threads take
+their units through registers in groups (fewer units than K where the
+whole tile would spill): 4 of 3 channels, 2 of 4, half that for the
+run-time op list into planar fp32, 1 for fp32 plain reads into planar
+fp32.  Run-time op lists, the depth sweep's compile-time chains and the
+normalise chain run at all 20 configurations (K = 1, 2, 4, 8 at every
+block size), on frames whose rows end in a partial unit and whose items
+span several tiles, and give the oracle's bits in the strict mode."""
 import pytest
 
 import datagen
 import oracle
 import paper_2508_07071_amd as fk
-from fkhelpers import Plan, assert_bitexact, host, to_dev
+from fkhelpers import Plan, assert_bitexact, assert_close, host, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -61,5 +62,43 @@ def test_random_op_list_at_every_config_matches_oracle(read, din, C, dout, layou
         for c in fk.fk_autotune_space():
             p.set_config(c.block_threads, c.coarsen)
             outs = host(p.run(dframes, items))
+            for b, (o, r) in enumerate(zip(outs, refs)):
+                assert_bitexact(o, r["out"], f"{c} item {b}")
+
+
+@pytest.mark.parametrize("n_ops", [16, 64, 256])
+def test_compile_time_depth_chains_at_every_config_match_oracle(n_ops):
+    """The depth sweep's compile-time chains (groups of 4 units at K = 8)
+    at all 20 configurations, both modes: strict bits against the oracle,
+    contracted results within tolerance."""
+    say("compile-time chain, every config", n_ops)
+    cfg = datagen.config1(n_ops, seed=3, frame_hw=(37, 301))
+    chain, frames, items = cfg["chain"], cfg["frames"], cfg["items"]
+    refs = oracle.run_chain(chain, frames, items)
+    dframes = to_dev(frames)
+    for strict in (True, False):
+        with Plan(chain, 1, strict=strict) as p:
+            assert fk.fk_plan_get_tier(p.h) == 1
+            for c in fk.fk_autotune_space():
+                p.set_config(c.block_threads, c.coarsen)
+                out = host(p.run(dframes, items))[0]
+                if strict:
+                    assert_bitexact(out, refs[0]["out"], f"{c}")
+                else:
+                    assert_close(out, refs[0], what=f"{c}")
+
+
+def test_normalize_chain_at_every_config_matches_oracle():
+    """The hot chain (crop+resize, swap, cvt, mul, sub, div, planar fp32) at
+    all 20 configurations in the strict mode, items of 4-pixel units (below
+    2^20 output pixels)."""
+    say("normalise chain, every config")
+    cfg = datagen.config2(9, seed=5)
+    refs = oracle.run_chain(cfg["chain"], cfg["frames"], cfg["items"])
+    dframes = to_dev(cfg["frames"])
+    with Plan(cfg["chain"], 9, strict=True) as p:
+        for c in fk.fk_autotune_space():
+            p.set_config(c.block_threads, c.coarsen)
+            outs = host(p.run(dframes, cfg["items"]))
             for b, (o, r) in enumerate(zip(outs, refs)):
                 assert_bitexact(o, r["out"], f"{c} item {b}")
