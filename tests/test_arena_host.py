@@ -54,7 +54,8 @@ def test_arena_matches_first_fit_model():
         src = os.path.join(d, "drv.cpp")
         exe = os.path.join(d, "drv")
         open(src, "w").write(DRIVER)
-        subprocess.check_call(["g++", "-O1", "-std=c++17", "-I", CSRC, "-o", exe, src])
+        subprocess.check_call(["g++", "-O1", "-std=c++17", "-fsanitize=undefined", "-fno-sanitize-recover=undefined",
+                               "-I", CSRC, "-o", exe, src])
         model = Model(1 << 20)
         live, script, expect = [], [], []
         for _ in range(3000):

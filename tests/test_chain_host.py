@@ -60,7 +60,8 @@ def driver():
     with tempfile.TemporaryDirectory() as d:
         src, exe = os.path.join(d, "drv.cpp"), os.path.join(d, "drv")
         open(src, "w").write(DRIVER)
-        subprocess.check_call(["g++", "-O1", "-std=c++17", "-ffp-contract=off", "-I", CSRC, "-o", exe,
+        subprocess.check_call(["g++", "-O1", "-std=c++17", "-ffp-contract=off", "-fsanitize=undefined",
+                               "-fno-sanitize-recover=undefined", "-I", CSRC, "-o", exe,
                                src, os.path.join(CSRC, "fk_chain.cpp")])
 
         def run(chains):

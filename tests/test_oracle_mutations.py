@@ -79,12 +79,12 @@ PINS = [
 ]
 
 
-def build_variant(src_text, path):
+def build_variant(src_text, path, extra=()):
     c = path + ".c"
     with open(c, "w") as f:
         f.write(src_text)
     subprocess.check_call(["gcc", "-O1", "-std=c11", "-fno-fast-math", "-ffp-contract=off", "-fPIC",
-                           "-shared", "-w", "-o", path, c, "-lm"])
+                           *extra, "-shared", "-w", "-o", path, c, "-lm"])
 
 
 def load_as_oracle(path, monkeypatch):
@@ -111,6 +111,17 @@ def test_unmodified_oracle_passes_the_pin_subset(monkeypatch):
     with tempfile.TemporaryDirectory() as d:
         path = os.path.join(d, "orig.so")
         build_variant(SRC, path)
+        load_as_oracle(path, monkeypatch)
+        assert caught_by_pins() is None
+
+
+def test_oracle_has_no_undefined_behaviour_on_the_pins(monkeypatch):
+    """The oracle built with the undefined-behaviour sanitizer (integer
+    overflow, shifts, out-of-bounds indexing of fixed arrays, misaligned
+    access; any report aborts) runs the pin subset and passes it."""
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "ubsan.so")
+        build_variant(SRC, path, ("-fsanitize=undefined", "-fno-sanitize-recover=undefined"))
         load_as_oracle(path, monkeypatch)
         assert caught_by_pins() is None
 
