@@ -19,8 +19,10 @@
 // Work decomposition: an item's output is cut into units of kUnitPx = 4
 // consecutive pixels of one row.  A tile is blockDim.x * K units of one
 // item; thread t handles units tile_base + j * blockDim.x + t (j < K), so
-// every load/store instruction of a wave touches consecutive units.  The
-// grid strides over the tiles of all items (persistent horizontal fusion).
+// every load/store instruction of a wave touches consecutive units, and
+// takes them through its registers in groups small enough that the tile is
+// never spilled (unit_group).  The grid strides over the tiles of all items
+// (persistent horizontal fusion).
 //
 // Also here: k_resize_px, the same pattern with pixel-strided lanes for the
 // bilinear gathers of large launches; k_loop_px, one pixel per lane for long
@@ -780,8 +782,8 @@ struct LoopMulAddCompute {
 
 // ------------------------------------------------------ run-time ops --
 // The op list is uniform across the grid: each op is one scalar branch and
-// its constants come through the scalar cache, then applied to all
-// K * 4 * C values of the thread's tile.  A LOOP record over one record
+// its constants come through the scalar cache, then applied to all values
+// the thread holds (a register group of its units).  A LOOP record over one record
 // makes that record run `count` times in a register loop; a longer LOOP
 // jumps back over its body until the body has run `count` times (bodies
 // hold no loops, so one counter serves every loop of the list).

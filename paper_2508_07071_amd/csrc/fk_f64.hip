@@ -5,7 +5,7 @@
 // later op rounds to double).  Pixel-strided lanes over the tiles of
 // k_transform (T * K units of 4 pixels): lane t holds pixels
 // pbase + q T + t, q < 4K, so each load and store instruction of a wave
-// touches consecutive pixels; the op list runs over up to 16 of the lane's
+// touches consecutive pixels; the op list runs over up to 12 of the lane's
 // values at a time.
 #include "fk_device.hpp"
 
