@@ -371,28 +371,52 @@ struct ReadCropNearest {
         const int sy = nearest_index(oy, it.h, it.oh);
         return (gsrc_t)it.src + (int64_t)(it.y + sy) * it.pitch + (int64_t)it.x * (C * ES);
     }
-    __device__ __forceinline__ static void pixel(const ItemRec &it, gsrc_t row, int ox, float (&r)[C])
+    // u8 pixels of 3 or 4 channels come out of one dword-aligned 8-byte
+    // window (two dword loads, the bytes picked with v_alignbyte) in place
+    // of C byte loads, where the crop+resize read's rule keeps its (wider)
+    // windows inside the frame's allocation
+    __device__ __forceinline__ static bool window_ok(const ItemRec &it)
+    {
+        if constexpr (DT == DT_U8 && C >= 3)
+            return ReadCropResize<DT_U8, C>::window_ok(it);
+        else
+            return false;
+    }
+    __device__ __forceinline__ static void pixel(const ItemRec &it, gsrc_t row, int ox, bool win,
+                                                 float (&r)[C])
     {
         constexpr int ES = DSize<DT>::v;
         const int sx = nearest_index(ox, it.w, it.ow);
+        if constexpr (DT == DT_U8 && C >= 3) {
+            if (win) {
+                const uint64_t a = (uint64_t)(uintptr_t)(row + sx * C);
+                const FK_GLOBAL uint32_t *p = (const FK_GLOBAL uint32_t *)(a & ~(uint64_t)3);
+                const uint32_t d = __builtin_amdgcn_alignbyte(p[1], p[0], (uint32_t)(a & 3));
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    r[c] = (float)((d >> (8 * c)) & 0xffu);
+                return;
+            }
+        }
 #pragma unroll
         for (int c = 0; c < C; ++c)
             r[c] = load_elem<DT>(row + (sx * C + c) * ES);
     }
-    __device__ __forceinline__ static bool px_prep(const ItemRec &) { return false; }
-    __device__ __forceinline__ static void load_px(const ItemRec &it, bool, int oy, int ox, float (&r)[C])
+    __device__ __forceinline__ static bool px_prep(const ItemRec &it) { return window_ok(it); }
+    __device__ __forceinline__ static void load_px(const ItemRec &it, bool win, int oy, int ox, float (&r)[C])
     {
-        pixel(it, row_of(it, oy), ox, r);
+        pixel(it, row_of(it, oy), ox, win, r);
     }
 
     __device__ __forceinline__ static void load(const ItemRec &it, int oy, int ox0, int n,
                                                 float (&r)[kUnitPx][C])
     {
         gsrc_t row = row_of(it, oy);
+        const bool win = window_ok(it);
 #pragma unroll
         for (int i = 0; i < kUnitPx; ++i) {
             if (i < n) {
-                pixel(it, row, ox0 + i, r[i]);
+                pixel(it, row, ox0 + i, win, r[i]);
             } else {
 #pragma unroll
                 for (int c = 0; c < C; ++c)
