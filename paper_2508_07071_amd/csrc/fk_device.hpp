@@ -504,18 +504,60 @@ struct ReadNV12Resize {
     static constexpr int kind = RD_NV12_RESIZE;
     static constexpr int elem_size = 1;
 
+    // Windows: in a frame whose base is a multiple of 4 and whose rows hold
+    // at least 8 bytes, a tap row's two luma bytes come from one
+    // dword-aligned 8-byte window and the chroma pairs serving them from
+    // another (two dword loads each, bytes picked with v_alignbyte) in place
+    // of six byte loads.  A window reads up to 3 bytes before and 7 after
+    // its first byte: a luma window past its row runs into the next luma
+    // row or the chroma plane, so only a chroma window on the last chroma
+    // row must be kept inside the row's pixels.
+    __device__ __forceinline__ static bool window_ok(const ItemRec &it)
+    {
+        if ((it.src & 3u) || (int)it.fw < 8)
+            return false;
+        const int last_y = it.y + it.h - 1;
+        const bool last_chroma_row = (last_y >> 1) == ((int)it.fh >> 1) - 1;
+        return !last_chroma_row || ((it.x + it.w - 1) & ~1) + 8 <= (int)it.fw;
+    }
+
+    // the taps at absolute columns X0 and X1 = X0 or X0 + 1 of absolute
+    // source row Y, from a luma and a chroma window
+    __device__ __forceinline__ static void row_taps(const ItemRec &it, int Y, int X0, int X1, float (&a)[3],
+                                                    float (&b)[3])
+    {
+        gsrc_t base = (gsrc_t)it.src;
+        const uint64_t la = (uint64_t)(uintptr_t)(base + (int64_t)Y * it.pitch + X0);
+        const FK_GLOBAL uint32_t *lp = (const FK_GLOBAL uint32_t *)(la & ~(uint64_t)3);
+        const uint32_t lw = __builtin_amdgcn_alignbyte(lp[1], lp[0], (uint32_t)(la & 3));
+        const int c0 = X0 & ~1;
+        const uint64_t ca = (uint64_t)(uintptr_t)(base + ((int64_t)it.fh + (Y >> 1)) * it.pitch + c0);
+        const FK_GLOBAL uint32_t *cp = (const FK_GLOBAL uint32_t *)(ca & ~(uint64_t)3);
+        const uint32_t cw = __builtin_amdgcn_alignbyte(cp[1], cp[0], (uint32_t)(ca & 3));
+        const int dl = X1 - X0;          // 0 or 1
+        const int dc = (X1 & ~1) - c0;   // 0 or 2
+        nv12_to_bgr((float)(lw & 0xffu), (float)(cw & 0xffu), (float)((cw >> 8) & 0xffu), a);
+        nv12_to_bgr((float)((lw >> (8 * dl)) & 0xffu), (float)((cw >> (8 * dc)) & 0xffu),
+                    (float)((cw >> (8 * dc + 8)) & 0xffu), b);
+    }
+
     // output column ox of the output row whose source rows are y0, y1
-    __device__ __forceinline__ static void pixel(const ItemRec &it, int y0, int y1, float ay, int ox,
+    __device__ __forceinline__ static void pixel(const ItemRec &it, int y0, int y1, float ay, int ox, bool win,
                                                  float (&r)[C])
     {
         int x0, x1;
         float ax;
         bilinear_coord(ox, it.sx, it.w, x0, x1, ax);
         float p00[3], p01[3], p10[3], p11[3];
-        nv12_pixel(it, it.x + x0, it.y + y0, p00);
-        nv12_pixel(it, it.x + x1, it.y + y0, p01);
-        nv12_pixel(it, it.x + x0, it.y + y1, p10);
-        nv12_pixel(it, it.x + x1, it.y + y1, p11);
+        if (win) {
+            row_taps(it, it.y + y0, it.x + x0, it.x + x1, p00, p01);
+            row_taps(it, it.y + y1, it.x + x0, it.x + x1, p10, p11);
+        } else {
+            nv12_pixel(it, it.x + x0, it.y + y0, p00);
+            nv12_pixel(it, it.x + x1, it.y + y0, p01);
+            nv12_pixel(it, it.x + x0, it.y + y1, p10);
+            nv12_pixel(it, it.x + x1, it.y + y1, p11);
+        }
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const float top = fmaf(ax, p01[c] - p00[c], p00[c]);
@@ -523,13 +565,13 @@ struct ReadNV12Resize {
             r[c] = fmaf(ay, bot - top, top);
         }
     }
-    __device__ __forceinline__ static bool px_prep(const ItemRec &) { return false; }
-    __device__ __forceinline__ static void load_px(const ItemRec &it, bool, int oy, int ox, float (&r)[C])
+    __device__ __forceinline__ static bool px_prep(const ItemRec &it) { return window_ok(it); }
+    __device__ __forceinline__ static void load_px(const ItemRec &it, bool win, int oy, int ox, float (&r)[C])
     {
         int y0, y1;
         float ay;
         bilinear_coord(oy, it.sy, it.h, y0, y1, ay);
-        pixel(it, y0, y1, ay, ox, r);
+        pixel(it, y0, y1, ay, ox, win, r);
     }
 
     __device__ __forceinline__ static void load(const ItemRec &it, int oy, int ox0, int n,
@@ -538,10 +580,11 @@ struct ReadNV12Resize {
         int y0, y1;
         float ay;
         bilinear_coord(oy, it.sy, it.h, y0, y1, ay);
+        const bool win = window_ok(it);
 #pragma unroll
         for (int i = 0; i < kUnitPx; ++i) {
             if (i < n) {
-                pixel(it, y0, y1, ay, ox0 + i, r[i]);
+                pixel(it, y0, y1, ay, ox0 + i, win, r[i]);
             } else {
 #pragma unroll
                 for (int c = 0; c < C; ++c)
@@ -1141,7 +1184,7 @@ __device__ __forceinline__ void tile_item(const KArgs &a, const FK_CONST KArgs *
 // (from the kernels' scratch sizes): 4 units of 3 channels, 2 of 4, and
 // half that for the run-time op list into planar fp32, whose per-channel
 // 16-byte stores gather each value anew (once more halved for fp32 plain
-// reads).
+// reads); 2 for the NV12 resize read.
 template <class Read, class Compute, class Write, int C, int K>
 constexpr int unit_group()
 {
@@ -1152,6 +1195,8 @@ constexpr int unit_group()
         g = 2;
     if (rt && planar32 && Read::kind == RD_PLAIN && Read::elem_size == 4)
         g /= 2;
+    if (Read::kind == RD_NV12_RESIZE && g > 2)
+        g = 2;  // four converted taps per pixel
     return K < g ? K : g;
 }
 
