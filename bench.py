@@ -143,12 +143,19 @@ def vf_sweep(args):
         h = fk.fk_plan_create(desc, R, opts)
         plans[n] = (h, desc)
         items_by_set[n] = [fk.make_items(ch, [frames[r]], [item], [outs[r]]) for r in range(R)]
-        # autotune over all R sets in one batched launch (HBM-resident working set)
-        allsets = fk.make_items(ch, frames, [dict(item, frame=r) for r in range(R)], outs)
         if args.autotune:
-            best, times = fk.fk_autotune(h, allsets, R, 7)
-            log(f"N={n} autotune (4 sets/launch) ms:",
-                {f"{c.block_threads}x{c.coarsen}": round(t / R, 4) for c, t in zip(fk.fk_autotune_space(), times)})
+            # tuned as the step runs it: one frame per launch, frames read
+            # from HBM (rotating sets).  fk_autotune would time all sets in
+            # one batched launch, whose best configuration differs: 256 x 8
+            # at N = 256 there, 111.7 us as a single launch against 97-100.
+            times = []
+            for c in fk.fk_autotune_space():
+                fk.fk_plan_set_config(h, c)
+                times.append(rotating_ms(lambda it: fk.fk_run(h, it, 1, stream), items_by_set[n], 40, 0.002))
+            best = fk.fk_autotune_space()[min(range(len(times)), key=times.__getitem__)]
+            fk.fk_plan_set_config(h, best)
+            log(f"N={n} autotune (single launches, rotating sets) ms:",
+                {f"{c.block_threads}x{c.coarsen}": round(t, 4) for c, t in zip(fk.fk_autotune_space(), times)})
         else:
             best = fk.fk_plan_get_config(h)
         tuned[n] = (best.block_threads, best.coarsen, fk.fk_plan_get_tier(h))
@@ -1352,7 +1359,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--strict", action="store_true")
     ap.add_argument("--autotune", action="store_true",
-                    help="autotune each depth's launch config first (default: the library default)")
+                    help="tune each depth's launch config first on single launches over rotating frames "
+                         "(default: the library default)")
     ap.add_argument("--no-unfused", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=432)
