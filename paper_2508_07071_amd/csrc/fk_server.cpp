@@ -225,8 +225,15 @@ bool launch_one(fk_server *s)
     for (Req *r : s->admitted) {
         if (r->launched == (int)r->crops.size())
             continue;
-        if (r->ready && hipEventQuery(r->ready) != hipSuccess)
-            break;  // first in, first out: later requests wait for this frame
+        if (r->ready) {
+            const hipError_t q = hipEventQuery(r->ready);
+            if (q == hipErrorNotReady)
+                break;  // first in, first out: later requests wait for this frame
+            if (q != hipSuccess) {
+                fail(s, "frame copy", q);  // the scheduler completes everything with the error
+                return false;
+            }
+        }
         if (s->opts.mode != FK_SERVER_BATCHED && !items.empty())
             break;  // one request per launch
         const int take = std::min((int)r->crops.size() - r->launched, cap - (int)items.size());
@@ -439,8 +446,11 @@ extern "C" fk_status fk_server_submit(fk_server *s, const fk_request *req, uint6
     try {
         if (!s || !req || !ticket)
             return set_error(FK_ERR_INVALID_ARG, "null argument");
-        if (s->failed.load())
+        if (s->failed.load()) {
+            // fail() writes the message under the mutex after raising the flag
+            std::lock_guard<std::mutex> g(s->mu);
             return set_error(FK_ERR_BAD_STATE, "server failed: %s", s->fail_msg.c_str());
+        }
         if (!req->frame || req->width < 1 || req->height < 1 ||
             req->pitch_bytes < (int64_t)req->width * s->C * s->es_in)
             return set_error(FK_ERR_INVALID_ARG, "bad frame");
