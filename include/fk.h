@@ -343,7 +343,13 @@ int32_t fk_autotune_space(fk_launch_config *space, int32_t max_configs);
  * events on an internal stream, divided by `reps`), write the 20
  * median times in milliseconds to `times_ms` (may be NULL), select the
  * fastest (ties: fewer threads, then less coarsening) into the plan and
- * `best` (may be NULL).  Synchronous; outputs are overwritten. */
+ * `best` (may be NULL).  Synchronous; outputs are overwritten.  The
+ * internal stream does not wait for the caller's streams: the frames must
+ * be ready (e.g. the stream that wrote them synchronized) before the call.
+ * Every launch reads the same items, so frames that fit the 256 MB
+ * Infinity Cache are timed from it; the times are those of an n_items
+ * launch, and a batched launch ranks configurations differently from a
+ * single-item one. */
 fk_status fk_autotune(fk_plan *plan, const fk_item *items, int32_t n_items, int32_t reps,
                       float *times_ms, fk_launch_config *best);
 
