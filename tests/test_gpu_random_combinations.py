@@ -5,7 +5,12 @@ launch configuration from the 20, the tier (automatic or run-time op
 list), eager or graph launches, the gather option, and where the frame
 sits in memory (dense, rows padded by 1, 4 or 64 elements, or u8 frames
 1-3 bytes past a dword boundary).  Strict plans give the oracle's bits,
-fused and unfused; contracted plans stay within the tolerance."""
+fused and unfused; contracted plans stay within the tolerance.  The same
+draws cover stats writes (order-free min/max exact, sums within the fp64
+reordering bound) and fp64 chains.  FK_RANDOM_BLOCKS=n runs n blocks of
+8 cases per test instead of the default."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -18,6 +23,10 @@ from fkhelpers import Plan, assert_bitexact, assert_close, host
 pytestmark = pytest.mark.gpu
 
 KINDS = ["plain", "crop_resize", "crop_nearest", "nv12", "nv12_resize"]
+
+
+def blocks(default):
+    return range(int(os.environ.get("FK_RANDOM_BLOCKS", default)))
 
 
 def say(*a):
@@ -73,7 +82,7 @@ def draw(g):
     return ch, frames, items, (fh, fw)
 
 
-@pytest.mark.parametrize("block", range(8))
+@pytest.mark.parametrize("block", blocks(16))
 def test_random_combinations_match_oracle(block):
     space = fk.fk_autotune_space()
     for i in range(block * 8, block * 8 + 8):
@@ -102,3 +111,71 @@ def test_random_combinations_match_oracle(block):
                     assert_bitexact(uouts[b], r["out"], f"{what}: unfused item {b}")
                 else:
                     assert_close(o, r, what=f"{what}: contracted item {b}")
+
+
+@pytest.mark.parametrize("block", blocks(4))
+def test_random_stats_combinations_match_oracle(block):
+    from test_gpu_stats import check, image_of, stats_of
+    space = fk.fk_autotune_space()
+    for i in range(block * 8, block * 8 + 8):
+        g = datagen.rng(77000 + i)
+        ch, frames, items, (fh, fw) = draw(g)
+        st = [r["out"] for r in oracle.run_chain(stats_of(ch), frames, items)]
+        ims = oracle.run_chain(image_of(ch), frames, items)
+        placed = [place(f, g) for f in frames]
+        dframes = [p[0] for p in placed]
+        cfg = space[int(g.integers(0, len(space)))]
+        tier = [fk.FK_TIER_AUTO, fk.FK_TIER_RUNTIME][int(g.integers(0, 2))]
+        graph = bool(g.integers(0, 4) == 0)
+        what = (f"stats case {i}: {ch['read']['kind']} {ch['read']['dtype']}x{ch['read']['channels']} "
+                f"{len(ch['ops'])} ops, B={len(items)}, {fh}x{fw} {[p[1] for p in placed]}, "
+                f"{cfg.block_threads}x{cfg.coarsen}, tier {tier}, graph {graph}")
+        say(what)
+        for strict in (True, False):
+            with Plan(stats_of(ch), len(items), strict=strict, tier=tier, use_graph=graph) as p:
+                p.set_config(cfg.block_threads, cfg.coarsen)
+                first = host(p.run(dframes, items))
+                again = host(p.run(dframes, items))  # partials and counters start clean
+            for b in range(len(items)):
+                check(first[b], st[b], ims[b], strict, f"{what} item {b} strict={strict}")
+                check(again[b], st[b], ims[b], strict, f"{what} rerun item {b} strict={strict}")
+
+
+@pytest.mark.parametrize("block", blocks(4))
+def test_random_f64_combinations_match_oracle(block):
+    from test_gpu_f64 import REL64
+    space = fk.fk_autotune_space()
+    for i in range(block * 8, block * 8 + 8):
+        g = datagen.rng(66000 + i)
+        spec = datagen.random_chain_spec(g, max_ops=48, side=(16, 300), max_batch=5)
+        ch = spec["chain"]
+        ch["read"].update(kind="plain", dtype=["u8", "f16", "f32", "f64"][int(g.integers(0, 4))], out_w=0, out_h=0)
+        ch["write"]["dtype"] = "f64"
+        fh, fw = spec["frame_hw"]
+        nf = 1 + int(g.integers(0, 3))
+        frames = [datagen.frame(g, fh, fw, ch["read"]["channels"], dtype=ch["read"]["dtype"]) for _ in range(nf)]
+        items = []
+        for b in range(1 + int(g.integers(0, 5))):
+            w, h = int(g.integers(1, fw + 1)), int(g.integers(1, fh + 1))
+            items.append({"frame": b % nf, "x": int(g.integers(0, fw - w + 1)),
+                          "y": int(g.integers(0, fh - h + 1)), "w": w, "h": h})
+        refs = oracle.run_chain(ch, frames, items)
+        placed = [place(f, g) for f in frames]
+        dframes = [p[0] for p in placed]
+        cfg = space[int(g.integers(0, len(space)))]
+        graph = bool(g.integers(0, 4) == 0)
+        what = (f"fp64 case {i}: {ch['read']['dtype']}x{ch['read']['channels']} {len(ch['ops'])} ops -> f64 "
+                f"{ch['write']['layout']}, B={len(items)}, {fh}x{fw} {[p[1] for p in placed]}, "
+                f"{cfg.block_threads}x{cfg.coarsen}, graph {graph}")
+        say(what)
+        for strict in (True, False):
+            with Plan(ch, len(items), strict=strict, use_graph=graph) as p:
+                p.set_config(cfg.block_threads, cfg.coarsen)
+                outs = host(p.run(dframes, items))
+                uouts = host(p.run_unfused(dframes, items)) if strict else None
+            for b, (o, r) in enumerate(zip(outs, refs)):
+                if strict:
+                    assert_bitexact(o, r["out"], f"{what}: item {b}")
+                    assert_bitexact(uouts[b], r["out"], f"{what}: unfused item {b}")
+                else:
+                    assert_close(o, r, rel=REL64, what=f"{what}: item {b}")
