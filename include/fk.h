@@ -197,9 +197,11 @@ typedef struct {
     int32_t coarsen;
 } fk_launch_config;
 
-#define FK_CONFIG_DEFAULT 0  /* 256 threads; coarsening 1, or 4 for chains of
-                                more than 32 normalised ops or the 256-op
-                                compile-time chain, 8 for a stats write */
+#define FK_CONFIG_DEFAULT 0  /* 256 threads; coarsening 1, except: 4 for the
+                                256-op compile-time chain and other compile-time
+                                chains of more than 32 normalised ops; 2 for a
+                                run-time op list of more than 32 records after
+                                a plain read; 8 for a stats write */
 #define FK_CONFIG_MANUAL 1   /* opts.manual */
 #define FK_CONFIG_AUTOTUNE 2 /* set by fk_autotune (default until then) */
 #define FK_CONFIG_MODEL 3    /* predicted by a cost model (fk_plan_use_model) */
