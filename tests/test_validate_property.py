@@ -1,0 +1,118 @@
+"""Item validation (CPU only, no device touched): fk_items_validate against
+a restatement of the documented item rules, over random chains and items
+drawn by hypothesis (frame sides and pitch, element alignment of both
+pointers, ROI placement, output sizes at and past their limits, NV12
+parity).  The first rule an item breaks decides the status: FK_OK,
+FK_ERR_INVALID_ARG or FK_ERR_UNSUPPORTED."""
+import pytest
+from hypothesis import given, settings, strategies as st
+
+import paper_2508_07071_amd as fk
+
+KINDS = ["plain", "crop_resize", "crop_nearest", "nv12", "nv12_resize"]
+ES = {"u8": 1, "f16": 2, "f32": 4, "f64": 8}
+RESIZES = {"crop_resize", "crop_nearest", "nv12_resize"}
+
+
+def expected(kind, dtype, C, out_es, it):
+    OK, INV, UNS = fk.FK_OK, fk.FK_ERR_INVALID_ARG, fk.FK_ERR_UNSUPPORTED
+    es = ES[dtype]
+    if not it["ptr"] or not it["dst"]:
+        return INV
+    if it["width"] < 1 or it["height"] < 1:
+        return INV
+    if it["width"] > 65535 or it["height"] > 65535:
+        return UNS
+    if kind.startswith("nv12"):
+        if it["width"] % 2 or it["height"] % 2 or it["pitch"] < it["width"]:
+            return INV
+    elif it["pitch"] < it["width"] * C * es or it["pitch"] % es:
+        return INV
+    if it["ptr"] % es or it["dst"] % out_es:
+        return INV
+    x, y, w, h = it["x"], it["y"], it["w"], it["h"]
+    if w < 1 or h < 1 or x < 0 or y < 0 or x + w > it["width"] or y + h > it["height"]:
+        return INV
+    ow, oh = it["out_w"], it["out_h"]
+    if kind in RESIZES:
+        if ow < 1 or oh < 1:
+            return INV
+        if ow > 65535 or oh > 65535 or ow * oh > (1 << 28):
+            return UNS
+    else:
+        if not ((ow == 0 and oh == 0) or (ow == w and oh == h)):
+            return INV
+        if w * h > (1 << 28):
+            return UNS
+    return OK
+
+
+MUTATIONS = ["null_src", "null_dst", "src_align", "dst_align", "width0", "height_neg", "wide", "tall",
+             "pitch_small", "pitch_odd", "x_neg", "y_neg", "roi_right", "roi_below", "w0", "h0",
+             "out0", "out_wide", "out_area", "out_mismatch", "nv12_odd"]
+
+
+@st.composite
+def case(draw):
+    """A valid item for a random chain, then with probability 1/2 one
+    mutation that breaks (or, for some chains, does not break) a rule."""
+    kind = draw(st.sampled_from(KINDS))
+    nv12 = kind.startswith("nv12")
+    if nv12:
+        dtype, C = "u8", 3
+    else:
+        dtype, C = draw(st.sampled_from(["u8", "f16", "f32"])), draw(st.sampled_from([1, 3, 4]))
+    wd, layout = draw(st.sampled_from([("f32", "planar"), ("f16", "packed"), ("f64", "stats")]))
+    es, oes = ES[dtype], ES[wd]
+    W = draw(st.one_of(st.integers(1, 300), st.integers(60000, 65535)))
+    H = draw(st.one_of(st.integers(1, 300), st.integers(60000, 65535)))
+    if nv12:
+        W, H = max(2, W & ~1), max(2, H & ~1)
+    row = W if nv12 else W * C * es
+    pitch = row + es * draw(st.integers(0, 8))
+    w, h = draw(st.integers(1, W)), draw(st.integers(1, H))
+    x, y = draw(st.integers(0, W - w)), draw(st.integers(0, H - h))
+    if kind in RESIZES:
+        ow, oh = draw(st.integers(1, 4096)), draw(st.integers(1, 4096))
+    else:
+        ow, oh = draw(st.sampled_from([(0, 0), (w, h)]))
+    it = dict(ptr=0x10000, dst=0x20000, width=W, height=H, pitch=pitch, x=x, y=y, w=w, h=h, out_w=ow, out_h=oh)
+    if draw(st.booleans()):
+        m = draw(st.sampled_from(MUTATIONS))
+        upd = {"null_src": dict(ptr=0), "null_dst": dict(dst=0), "src_align": dict(ptr=0x10001),
+               "dst_align": dict(dst=0x20000 + draw(st.sampled_from([1, 2, 4]))),
+               "width0": dict(width=0), "height_neg": dict(height=-3), "wide": dict(width=65536),
+               "tall": dict(height=65537), "pitch_small": dict(pitch=row - 1),
+               "pitch_odd": dict(pitch=pitch + 1), "x_neg": dict(x=-1), "y_neg": dict(y=-2),
+               "roi_right": dict(x=W - w + 1), "roi_below": dict(y=H - h + 1), "w0": dict(w=0),
+               "h0": dict(h=-1), "out0": dict(out_w=0, out_h=draw(st.integers(0, 5))),
+               "out_wide": dict(out_w=65536), "out_area": dict(out_w=1 << 15, out_h=1 << 14),
+               "out_mismatch": dict(out_w=w + 1, out_h=h), "nv12_odd": dict(width=W + 1)}[m]
+        it.update(upd)
+    return kind, dtype, C, (wd, layout), it
+
+
+@settings(max_examples=3000, deadline=None)
+@given(case())
+def test_items_validate_follows_the_documented_rules(c):
+    kind, dtype, C, (wd, layout), it = c
+    chain = {"read": {"kind": kind, "dtype": dtype, "channels": C, "out_w": 0, "out_h": 0},
+             "ops": [{"kind": "cvt", "k": []}], "write": {"dtype": wd, "layout": layout}}
+    desc = fk.chain_desc(chain)
+    assert fk.fk_chain_validate(desc) == fk.FK_OK
+    arr = (fk.fk_item * 1)()
+    a = arr[0]
+    a.src.ptr, a.src.width, a.src.height, a.src.pitch_bytes = it["ptr"] or None, it["width"], it["height"], it["pitch"]
+    a.x, a.y, a.w, a.h = it["x"], it["y"], it["w"], it["h"]
+    a.dst = it["dst"] or None
+    a.out_w, a.out_h = it["out_w"], it["out_h"]
+    want = expected(kind, dtype, C, ES[wd], it)
+    assert fk.fk_items_validate(desc, arr, 1) == want, (kind, dtype, C, wd, it)
+
+
+def test_empty_and_negative_counts():
+    desc = fk.chain_desc({"read": {"kind": "plain", "dtype": "u8", "channels": 3, "out_w": 0, "out_h": 0},
+                          "ops": [], "write": {"dtype": "f32", "layout": "packed"}})
+    assert fk.fk_items_validate(desc, None, 0) == fk.FK_OK
+    assert fk.fk_items_validate(desc, None, 1) == fk.FK_ERR_INVALID_ARG
+    assert fk.fk_items_validate(desc, None, -1) == fk.FK_ERR_INVALID_ARG
