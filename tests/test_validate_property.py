@@ -1,9 +1,11 @@
-"""Item validation (CPU only, no device touched): fk_items_validate against
-a restatement of the documented item rules, over random chains and items
-drawn by hypothesis (frame sides and pitch, element alignment of both
-pointers, ROI placement, output sizes at and past their limits, NV12
-parity).  The first rule an item breaks decides the status: FK_OK,
-FK_ERR_INVALID_ARG or FK_ERR_UNSUPPORTED."""
+"""Chain and item validation (CPU only, no device touched):
+fk_chain_validate and fk_items_validate against a restatement of the
+documented rules, over chains and items drawn by hypothesis (valid ones and
+ones with fields replaced: read kinds, dtypes, channel counts, write forms,
+op kinds, constant counts, loop spans and bodies; frame sides and pitch,
+element alignment of both pointers, ROI placement, output sizes at and past
+their limits, NV12 parity).  The first rule broken decides the status:
+FK_OK, FK_ERR_INVALID_ARG or FK_ERR_UNSUPPORTED."""
 import pytest
 from hypothesis import given, settings, strategies as st
 
@@ -116,3 +118,91 @@ def test_empty_and_negative_counts():
     assert fk.fk_items_validate(desc, None, 0) == fk.FK_OK
     assert fk.fk_items_validate(desc, None, 1) == fk.FK_ERR_INVALID_ARG
     assert fk.fk_items_validate(desc, None, -1) == fk.FK_ERR_INVALID_ARG
+
+
+# ------------------------------------------------------------------ chains --
+
+def chain_expected(rk, dt, C, od, lay, ops):
+    """The documented chain rules, first broken rule first."""
+    OK, INV, UNS = fk.FK_OK, fk.FK_ERR_INVALID_ARG, fk.FK_ERR_UNSUPPORTED
+    if not 0 <= rk <= 4:
+        return INV
+    if rk in (3, 4) and (dt != 0 or C != 3):
+        return INV
+    if dt not in (0, 1, 2, 3):
+        return INV
+    if C not in (1, 3, 4):
+        return UNS
+    if lay == 2:
+        if od != 3:
+            return UNS
+    else:
+        if od not in (1, 2, 3):
+            return UNS
+        if lay not in (0, 1):
+            return INV
+        if od == 3 and rk != 0:
+            return UNS
+    if dt == 3 and (lay == 2 or od != 3):
+        return UNS
+    for i, (kind, n, span, count) in enumerate(ops):
+        if not 0 <= kind <= 6:
+            return INV
+        if kind == 6:
+            if n != 0 or not 1 <= span <= i or count < 1:
+                return INV
+            if any(not 2 <= ops[j][0] <= 5 for j in range(i - span, i)):
+                return INV
+        elif kind in (0, 1):
+            if n != 0:
+                return INV
+        elif n not in (1, C):
+            return INV
+    return OK
+
+
+@st.composite
+def raw_chain(draw):
+    """A valid chain whose fields are each replaced, with probability 1/10,
+    by an arbitrary (often invalid) value."""
+    def odd():
+        return draw(st.integers(0, 9)) == 0
+    rk = draw(st.integers(-1, 6)) if odd() else draw(st.integers(0, 4))
+    nv12 = rk in (3, 4)
+    dt = draw(st.integers(-1, 4)) if odd() else (0 if nv12 else draw(st.integers(0, 2)))
+    C = draw(st.integers(0, 5)) if odd() else (3 if nv12 else draw(st.sampled_from([1, 3, 4])))
+    if odd():
+        od, lay = draw(st.integers(-1, 4)), draw(st.integers(-1, 3))
+    else:
+        od, lay = draw(st.sampled_from([(2, 1), (1, 0), (2, 0), (3, 2)] + ([(3, 0), (3, 1)] if rk == 0 else [])))
+        if dt == 3:
+            od, lay = 3, draw(st.sampled_from([0, 1]))
+    ops = []
+    for i in range(draw(st.integers(0, 8))):
+        kind = draw(st.integers(-1, 7)) if odd() else draw(st.integers(0, 6 if i >= 1 else 5))
+        if kind in (0, 1):
+            n = draw(st.integers(0, 4)) if odd() else 0
+        elif kind == 6:
+            n = draw(st.integers(0, 2)) if odd() else 0
+        else:
+            n = draw(st.integers(0, 5)) if odd() else draw(st.sampled_from([1, max(C, 1)]))
+        span = (draw(st.integers(-1, i + 1)) if odd() else draw(st.integers(1, max(i, 1)))) if kind == 6 else 0
+        count = (draw(st.integers(-1, 5)) if odd() else draw(st.integers(1, 5))) if kind == 6 else 0
+        ops.append((kind, n, span, count))
+    return rk, dt, C, od, lay, ops
+
+
+@settings(max_examples=3000, deadline=None)
+@given(raw_chain())
+def test_chain_validate_follows_the_documented_rules(c):
+    rk, dt, C, od, lay, ops = c
+    arr = (fk.fk_op_desc * max(1, len(ops)))()
+    for a, (kind, n, span, count) in zip(arr, ops):
+        a.kind, a.n_consts, a.loop_span, a.loop_count = kind, n, span, count
+        for j in range(4):
+            a.consts[j] = 1.0
+    d = fk.fk_chain_desc()
+    d.read.kind, d.read.in_dtype, d.read.channels = rk, dt, C
+    d.ops, d.n_ops = arr, len(ops)
+    d.write.out_dtype, d.write.layout = od, lay
+    assert fk.fk_chain_validate(d) == chain_expected(rk, dt, C, od, lay, ops), c
