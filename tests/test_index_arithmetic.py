@@ -15,7 +15,11 @@ Nearest-neighbour source index: floor((2o + 1) in / (2 out)) from an fp32
 estimate of the quotient corrected once by exact 64-bit products
 (nearest_index in the device header), restated in numpy float32 (round to
 nearest even; the library is built with correctly rounded fp32 division)
-and checked exact for every input and output side up to 65535."""
+and checked exact for every input and output side up to 65535.
+
+Tile to item: the owning batch slot of a tile, by binary search over the
+tile offsets with a first probe where equal items would put it
+(find_item_guess), against bisection on random batches."""
 import os
 import re
 
@@ -130,3 +134,72 @@ def test_nearest_restatement_matches_the_device_source():
                  "int q = (int)((float)num * (1.0f / (float)den));",
                  "if ((uint64_t)q * den > num) --q;", "else if ((uint64_t)(q + 1) * den <= num) ++q;"):
         assert line in body, line
+
+
+# ---------------------------------------------------- tile -> item lookup --
+
+def find_item(tb, n, tile):
+    lo, hi = 0, n - 1
+    while lo < hi:
+        mid = (lo + hi + 1) >> 1
+        if tb[mid] <= tile:
+            lo = mid
+        else:
+            hi = mid - 1
+    return lo
+
+
+def find_item_guess(tb, n, tile, total):
+    if n <= 4:
+        return find_item(tb, n, tile)
+    lo, hi = 0, n - 1
+    g = (tile * n) // total
+    if tb[g] <= tile:
+        if tb[g + 1] > tile:
+            return g
+        lo = g + 1
+    else:
+        hi = g - 1
+    while lo < hi:
+        mid = (lo + hi + 1) >> 1
+        if tb[mid] <= tile:
+            lo = mid
+        else:
+            hi = mid - 1
+    return lo
+
+
+def test_tile_lookup_finds_the_owning_item():
+    """Every tile of random batches (equal, uneven and skewed tile counts,
+    1 to 1,191 items) maps to the item whose tile range holds it, by the
+    plain search and by the search with a first probe."""
+    import bisect
+    g = np.random.default_rng(12)
+    for trial in range(400):
+        n = int(g.choice([1, 2, 3, 4, 5, 7, 50, 256, 1191]))
+        kind = trial % 3
+        if kind == 0:
+            counts = np.full(n, int(g.integers(1, 9)))
+        elif kind == 1:
+            counts = g.integers(1, 40, size=n)
+        else:
+            counts = np.where(g.random(n) < 0.1, g.integers(100, 1000, size=n), 1)
+        tb = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64).tolist()
+        total = tb[-1]
+        tiles = range(total) if total <= 4000 else g.integers(0, total, size=4000).tolist()
+        for t in tiles:
+            want = bisect.bisect_right(tb, t) - 1
+            assert find_item(tb, n, t) == want
+            assert find_item_guess(tb, n, t, total) == want, (n, t, total)
+
+
+def test_tile_lookup_restatement_matches_the_device_source():
+    src = open(os.path.join(os.path.dirname(__file__), "..", "paper_2508_07071_amd", "csrc",
+                            "fk_device.hpp")).read()
+    start = src.index("int find_item_guess(")
+    flat = re.sub(r"\s+", " ", src[start:src.index("return lo;", start)])
+    for line in ("if (n_items <= 4) return find_item(tb, n_items, tile);",
+                 "const int g = (int)(((uint64_t)tile * (uint64_t)n_items) / total);",
+                 "if (tb[g] <= tile) { if (tb[g + 1] > tile) return g; lo = g + 1; } else { hi = g - 1; }",
+                 "const int mid = (lo + hi + 1) >> 1; if (tb[mid] <= tile) lo = mid; else hi = mid - 1;"):
+        assert line in flat, line
